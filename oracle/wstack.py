@@ -1,0 +1,379 @@
+"""FP64 CPU oracle for the w-stacking imaging path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call
+this module; only the tests, the smoke check and the benchmark's CPU baseline
+do.  It shares no code with the HIP library: it is a plain, slow, obviously
+correct NumPy restatement of the method, written from the paper's Sec. 2
+(Eqs. 1-3) in float64 throughout, with NumPy's FFT and ``bincount`` as the only
+library primitives.
+
+The paper leaves several conventions open (kernel width and normalisation,
+the grid-to-wavelength map, the plane placement, the FFT centring, what
+happens to taps that fall off the grid).  The readings taken here are:
+
+* grid cell size du = 1/fov (fov = full image width in radians), so that
+  du * dl = 1/N with dl = fov/N; the zero spacing sits at cell N/2;
+* visibility m lands at x = u fov + N_u/2, y = v fov_m + N_v/2, its kernel is
+  centred on the nearest cell i0 = floor(x + 1/2), j0 = floor(y + 1/2);
+* nearest w-plane (Sec. 2): k = clamp(floor((w - w_min)/dw), 0, N_w - 1) with
+  dw = (w_max - w_min)/N_w and plane centres w_k = w_min + (k + 1/2) dw
+  (N_w = 1: a single plane at (w_min + w_max)/2);
+* Gaussian kernel of support K cells (Sec. 2): sigma = K/7 cells unless given,
+  G = c g(i - x) g(j - y), g(d) = exp(-d^2 / (2 sigma^2)), c = 1/(2 pi sigma^2);
+  the visibility is multiplied by its weight (natural weighting);
+* taps that fall outside the grid are dropped and counted;
+* each plane is transformed with the unnormalised, centred, backward
+  (e^{+2 pi i}) 2-D DFT of Eq. (2);
+* the phase screen is exp(+2 pi i w_k (n - 1)) with n - 1 = sqrt(1 - l^2 - m^2)
+  - 1 evaluated as -r^2 / (1 + sqrt(1 - r^2)) (no cancellation near r = 0);
+* the dirty image is the plain sum over planes (the right-hand side of
+  Eq. (2), no 1/n or (w_max - w_min) factor).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Params:
+    nu: int
+    nv: int
+    nw: int
+    fov_l: float
+    fov_m: float
+    w_min: float
+    w_max: float
+    support: int
+    sigma: float = 0.0
+
+    @classmethod
+    def of(cls, wl) -> "Params":
+        """Take the geometry fields from any object that carries them."""
+        return cls(wl.nu, wl.nv, wl.nw, wl.fov_l, wl.fov_m, wl.w_min,
+                   wl.w_max, wl.support, getattr(wl, "sigma", 0.0))
+
+
+# ---------------------------------------------------------------------------
+# Kernel (Sec. 2, Eq. (3): Gaussian convolution function of support K cells)
+# ---------------------------------------------------------------------------
+
+def kernel_sigma(p: Params) -> float:
+    """Gaussian width in cells; the paper gives only the support (7 cells)."""
+    return float(p.sigma) if p.sigma > 0 else p.support / 7.0
+
+
+def kernel_norm(p: Params) -> float:
+    """c = 1/(2 pi sigma^2): the continuous 2-D Gaussian integrates to one."""
+    s = kernel_sigma(p)
+    return 1.0 / (2.0 * math.pi * s * s)
+
+
+def gauss(d, sigma):
+    """One-dimensional Gaussian factor g(d) = exp(-d^2 / (2 sigma^2))."""
+    d = np.asarray(d, dtype=np.float64)
+    return np.exp(-(d * d) / (2.0 * sigma * sigma))
+
+
+# ---------------------------------------------------------------------------
+# w-planes (Sec. 2: visibilities go to the closest w-plane)
+# ---------------------------------------------------------------------------
+
+def plane_spacing(p: Params) -> float:
+    if p.nw == 1:
+        return 1.0
+    return (p.w_max - p.w_min) / p.nw
+
+
+def plane_centres(p: Params) -> np.ndarray:
+    """w_k, the w value each plane stands for."""
+    if p.nw == 1:
+        return np.array([0.5 * (p.w_min + p.w_max)])
+    dw = plane_spacing(p)
+    return p.w_min + (np.arange(p.nw) + 0.5) * dw
+
+
+def plane_index(p: Params, w) -> np.ndarray:
+    """Index of the closest plane centre, clamped to the end planes."""
+    w = np.asarray(w, dtype=np.float64)
+    if p.nw == 1:
+        return np.zeros(w.shape, dtype=np.int64)
+    k = np.floor((w - p.w_min) / plane_spacing(p))
+    return np.clip(k, 0, p.nw - 1).astype(np.int64)
+
+
+# ---------------------------------------------------------------------------
+# Step 1 - coordinates of each visibility on the mesh (Sec. 2)
+# ---------------------------------------------------------------------------
+
+_FAR = 1.0e9  # a cell position far off any grid
+
+
+def coordinates(p: Params, uvw):
+    """Continuous cell position (x, y), nearest cell (i0, j0) and plane k.
+
+    A visibility with a non-finite coordinate, or one so far off the grid
+    that none of its taps can land on it, is parked at a position far off
+    the grid, so that all of its taps are dropped.
+    """
+    uvw = np.asarray(uvw, dtype=np.float64)
+    x = uvw[:, 0] * p.fov_l + p.nu / 2
+    y = uvw[:, 1] * p.fov_m + p.nv / 2
+    ok = np.isfinite(uvw).all(axis=1) & (np.abs(x) < _FAR) & (np.abs(y) < _FAR)
+    x = np.where(ok, x, -_FAR)
+    y = np.where(ok, y, -_FAR)
+    i0 = np.floor(x + 0.5).astype(np.int64)
+    j0 = np.floor(y + 0.5).astype(np.int64)
+    k = plane_index(p, np.where(ok, uvw[:, 2], p.w_min))
+    return x, y, i0, j0, k
+
+
+def _weights(weight, m):
+    if weight is None:
+        return np.ones(m, dtype=np.float64)
+    return np.asarray(weight, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Step 2 - convolutional gridding onto the plane stack (Eq. (3))
+# ---------------------------------------------------------------------------
+
+def grid(p: Params, uvw, vis, weight=None):
+    """Grid visibilities onto P[k][j][i] (complex128) with the Gaussian kernel.
+
+    For every tap (a, b) in [-h, h]^2 around the nearest cell, the cell
+    (i0 + a, j0 + b) of plane k receives w V c g(i - x) g(j - y) when it lies
+    on the grid; taps off the grid are dropped and counted.
+    Returns (planes, n_dropped_taps).
+    """
+    vis = np.asarray(vis).astype(np.complex128)
+    m = vis.shape[0]
+    x, y, i0, j0, k = coordinates(p, uvw)
+    wv = _weights(weight, m) * vis
+    h = (p.support - 1) // 2
+    s = kernel_sigma(p)
+    c = kernel_norm(p)
+    ncell = p.nw * p.nv * p.nu
+    re = np.zeros(ncell)
+    im = np.zeros(ncell)
+    dropped = 0
+    for b in range(-h, h + 1):
+        j = j0 + b
+        gy = gauss(j - y, s)
+        for a in range(-h, h + 1):
+            i = i0 + a
+            on = (i >= 0) & (i < p.nu) & (j >= 0) & (j < p.nv)
+            dropped += int(m - np.count_nonzero(on))
+            val = wv[on] * (c * gauss(i[on] - x[on], s) * gy[on])
+            flat = (k[on] * p.nv + j[on]) * p.nu + i[on]
+            re += np.bincount(flat, weights=val.real, minlength=ncell)
+            im += np.bincount(flat, weights=val.imag, minlength=ncell)
+    planes = (re + 1j * im).reshape(p.nw, p.nv, p.nu)
+    return planes, dropped
+
+
+# ---------------------------------------------------------------------------
+# Step 3 - per-plane 2-D FFT (Sec. 2, Eq. (2) inner integral)
+# ---------------------------------------------------------------------------
+
+def fft_planes(p: Params, planes, direction: int = +1):
+    """Centred, unnormalised 2-D DFT of every plane.
+
+    direction +1 (imaging, Eq. (2)):
+      F[q][p] = sum_{j,i} P[j][i] exp(+2 pi i [(i - Nu/2)(p - Nu/2)/Nu
+                                               + (j - Nv/2)(q - Nv/2)/Nv])
+    direction -1 uses exp(-2 pi i ...), the adjoint transform.
+    """
+    planes = np.asarray(planes, dtype=np.complex128)
+    shifted = np.fft.ifftshift(planes, axes=(-2, -1))
+    if direction > 0:
+        out = np.fft.ifft2(shifted, axes=(-2, -1)) * (p.nu * p.nv)
+    else:
+        out = np.fft.fft2(shifted, axes=(-2, -1))
+    return np.fft.fftshift(out, axes=(-2, -1))
+
+
+# ---------------------------------------------------------------------------
+# Step 4 - w-screen and plane sum (Eq. (2) outer integral)
+# ---------------------------------------------------------------------------
+
+def sky_coords(p: Params):
+    """Direction cosines (l, m) of pixel centres, l_p = (p - Nu/2) fov_l/Nu."""
+    l = (np.arange(p.nu) - p.nu / 2) * (p.fov_l / p.nu)
+    mm = (np.arange(p.nv) - p.nv / 2) * (p.fov_m / p.nv)
+    return l, mm
+
+
+def n_minus_one(l, m):
+    """sqrt(1 - l^2 - m^2) - 1 without cancellation: -r^2/(1 + sqrt(1 - r^2))."""
+    r2 = np.asarray(l, np.float64) ** 2 + np.asarray(m, np.float64) ** 2
+    return -r2 / (1.0 + np.sqrt(1.0 - r2))
+
+
+def screen_nm1(p: Params):
+    """n - 1 on the image grid, indexed [q][p]."""
+    l, mm = sky_coords(p)
+    return n_minus_one(l[None, :], mm[:, None])
+
+
+def wcorrect(p: Params, fplanes):
+    """I[q][p] = sum_k F_k[q][p] exp(+2 pi i w_k (n_pq - 1))."""
+    nm1 = screen_nm1(p)
+    img = np.zeros((p.nv, p.nu), dtype=np.complex128)
+    for k, wk in enumerate(plane_centres(p)):
+        img += fplanes[k] * np.exp(2j * math.pi * wk * nm1)
+    return img
+
+
+def image(p: Params, uvw, vis, weight=None):
+    """Dirty image: gridding -> per-plane FFT -> w-screen and sum."""
+    planes, _ = grid(p, uvw, vis, weight)
+    return wcorrect(p, fft_planes(p, planes, +1))
+
+
+# ---------------------------------------------------------------------------
+# Adjoint: degridding (the paper's future work, Sec. 5)
+# ---------------------------------------------------------------------------
+
+def degrid(p: Params, img, uvw, weight=None):
+    """Exact adjoint of ``image``: image -> visibilities.
+
+    Q_k = FFT^-(conj(screen_k) X); V_m = w_m sum_taps c g g Q_{k(m)}[j][i],
+    taps off the grid contributing nothing.
+    """
+    img = np.asarray(img).astype(np.complex128)
+    nm1 = screen_nm1(p)
+    wks = plane_centres(p)
+    q = np.stack([img * np.exp(-2j * math.pi * wk * nm1) for wk in wks])
+    q = fft_planes(p, q, -1)
+    m = np.asarray(uvw).shape[0]
+    x, y, i0, j0, k = coordinates(p, uvw)
+    h = (p.support - 1) // 2
+    s = kernel_sigma(p)
+    c = kernel_norm(p)
+    out = np.zeros(m, dtype=np.complex128)
+    qflat = q.reshape(-1)
+    for b in range(-h, h + 1):
+        j = j0 + b
+        gy = gauss(j - y, s)
+        for a in range(-h, h + 1):
+            i = i0 + a
+            on = (i >= 0) & (i < p.nu) & (j >= 0) & (j < p.nv)
+            flat = (k[on] * p.nv + j[on]) * p.nu + i[on]
+            out[on] += c * gauss(i[on] - x[on], s) * gy[on] * qflat[flat]
+    return _weights(weight, m) * out
+
+
+# ---------------------------------------------------------------------------
+# Direct forms for sampled outputs at full size (no FFT, no plane stack)
+# ---------------------------------------------------------------------------
+
+def grid_cells_direct(p: Params, uvw, vis, weight, cells):
+    """P[k][j][i] at the given (k, j, i) cells, summed visibility by visibility."""
+    vis = np.asarray(vis).astype(np.complex128)
+    x, y, i0, j0, kk = coordinates(p, uvw)
+    wv = _weights(weight, vis.shape[0]) * vis
+    h = (p.support - 1) // 2
+    s = kernel_sigma(p)
+    c = kernel_norm(p)
+    out = []
+    for (k, j, i) in cells:
+        sel = (kk == k) & (np.abs(i0 - i) <= h) & (np.abs(j0 - j) <= h)
+        out.append(np.sum(wv[sel] * c * gauss(i - x[sel], s)
+                          * gauss(j - y[sel], s)))
+    return np.array(out, dtype=np.complex128)
+
+
+def image_pixels_direct(p: Params, uvw, vis, weight, pixels, block=1 << 20):
+    """Dirty-image pixels I[q][p] from the definition, without an FFT.
+
+    Each visibility contributes w V exp(2 pi i w_k (n - 1)) times the DFT of
+    its own on-grid taps; the tap sum separates into a u factor and a v
+    factor.  ``pixels`` is a list of (q, p) pairs.
+    """
+    uvw = np.asarray(uvw, np.float64)
+    vis = np.asarray(vis).astype(np.complex128)
+    m = vis.shape[0]
+    wts = _weights(weight, m)
+    h = (p.support - 1) // 2
+    s = kernel_sigma(p)
+    c = kernel_norm(p)
+    wks = plane_centres(p)
+    l_all, m_all = sky_coords(p)
+    res = np.zeros(len(pixels), dtype=np.complex128)
+    for start in range(0, m, block):
+        sl = slice(start, min(m, start + block))
+        x, y, i0, j0, k = coordinates(p, uvw[sl])
+        wv = wts[sl] * vis[sl]
+        for t, (qq, pp) in enumerate(pixels):
+            fu = (pp - p.nu / 2) / p.nu
+            fv = (qq - p.nv / 2) / p.nv
+            su = np.zeros(x.shape, np.complex128)
+            sv = np.zeros(x.shape, np.complex128)
+            for a in range(-h, h + 1):
+                i = i0 + a
+                onu = (i >= 0) & (i < p.nu)
+                su += np.where(onu, gauss(i - x, s), 0.0) * np.exp(
+                    2j * math.pi * (i - p.nu / 2) * fu)
+                j = j0 + a
+                onv = (j >= 0) & (j < p.nv)
+                sv += np.where(onv, gauss(j - y, s), 0.0) * np.exp(
+                    2j * math.pi * (j - p.nv / 2) * fv)
+            nm1 = n_minus_one(l_all[pp], m_all[qq])
+            ph = np.exp(2j * math.pi * wks[k] * nm1)
+            res[t] += np.sum(wv * c * su * sv * ph)
+    return res
+
+
+def dft_image(p: Params, uvw, vis, weight, pixels=None):
+    """Ideal dirty image from Eqs. (1)-(2) with no gridding at all.
+
+    I(l, m) = sum_m w V exp(+2 pi i (u l + v m + w (n - 1))).  The w-stacked
+    image equals this times the kernel's Fourier taper when every w sits on a
+    plane centre, up to the kernel's aliasing and truncation.
+    """
+    uvw = np.asarray(uvw, np.float64)
+    wv = _weights(weight, uvw.shape[0]) * np.asarray(vis).astype(np.complex128)
+    l_all, m_all = sky_coords(p)
+    if pixels is None:
+        pixels = [(q, pp) for q in range(p.nv) for pp in range(p.nu)]
+    out = np.empty(len(pixels), dtype=np.complex128)
+    for t, (q, pp) in enumerate(pixels):
+        l, mm = l_all[pp], m_all[q]
+        ph = uvw[:, 0] * l + uvw[:, 1] * mm + uvw[:, 2] * n_minus_one(l, mm)
+        out[t] = np.sum(wv * np.exp(2j * math.pi * ph))
+    return out
+
+
+def kernel_taper(p: Params):
+    """Continuous Fourier transform of c g(x) g(y) at pixel (q, p), [q][p].
+
+    exp(-2 pi^2 sigma^2 (f_p^2 + f_q^2)) with f_p = (p - Nu/2)/Nu.
+    """
+    s = kernel_sigma(p)
+    fp = (np.arange(p.nu) - p.nu / 2) / p.nu
+    fq = (np.arange(p.nv) - p.nv / 2) / p.nv
+    return np.exp(-2 * math.pi ** 2 * s * s * (fp[None, :] ** 2
+                                                + fq[:, None] ** 2))
+
+
+# ---------------------------------------------------------------------------
+# Cost bookkeeping (Sec. 4.2)
+# ---------------------------------------------------------------------------
+
+def grid_point_additions(p: Params, uvw) -> int:
+    """Number of on-grid kernel taps: the paper's grid-point additions."""
+    x, y, i0, j0, k = coordinates(p, uvw)
+    h = (p.support - 1) // 2
+    cols = np.clip(np.minimum(i0 + h, p.nu - 1) - np.maximum(i0 - h, 0) + 1,
+                   0, None)
+    rows = np.clip(np.minimum(j0 + h, p.nv - 1) - np.maximum(j0 - h, 0) + 1,
+                   0, None)
+    return int(np.sum(cols * rows))
+
+
+def mesh_bytes(nu: int, nv: int, nw: int, complex_bytes: int = 16) -> int:
+    """Bytes of one N_u x N_v x N_w complex mesh (real + imaginary parts)."""
+    return nu * nv * nw * complex_bytes
