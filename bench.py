@@ -1,0 +1,259 @@
+"""Benchmark of the w-stacking imaging path on one MI355X.
+
+One step = the whole hot path on one batch of synthetic visibilities held in
+HBM: binning + gridding onto N_w w-planes (ws_grid_visibilities), then the
+per-plane 2-D FFT, w-screen and plane sum into the dirty image
+(ws_image_accumulate).  Default workload: 1e7 visibilities with a dense core
+(r = R U^2, w = wmax r/R + N(0, 0.1 wmax)), 4096^2 grid, 32 w-planes, 7x7
+Gaussian kernel, 5 deg field, FP32 path; the FP64 path is timed on the same
+inputs for comparison.
+
+Prints one JSON line (the last line on stdout).  value = visibilities imaged
+per second (Mvis/s) over the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(name, wl, elem, m):
+    """Bytes a kernel must move per launch (reads + writes), by definition.
+
+    grid_tiles: write every stack cell once + read each binned record once
+      (cell index 4 B, two fractional offsets and a complex value);
+    fft_cols: read + write the stack once;
+    row_screen_sum: read the stack once + read/write the image once;
+    bin_count: read uvw (24 B) + write key/rank (8 B) per visibility;
+    bin_scatter: read uvw, vis, weight, key/rank + write a record.
+    """
+    cells = wl.nu * wl.nv * wl.nw
+    img = wl.nu * wl.nv
+    rec = 4 + 2 * elem
+    return {
+        "grid_tiles": cells * elem + m * rec,
+        "fft_cols": 2 * cells * elem,
+        "row_screen_sum": cells * elem + 2 * img * elem,
+        "bin_count": m * (24 + 8),
+        "bin_scatter": m * (24 + elem + 4 + 8 + rec),
+    }.get(name)
+
+
+def time_path(plan, uvw, vis, wt, img, steps, warmup, torch):
+    for _ in range(warmup):
+        plan.reset()
+        img.zero_()
+        plan.grid(uvw, vis, wt)
+        plan.image_accumulate(img)
+    torch.cuda.synchronize()
+    plan.kernel_times(reset=True)
+    plan.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.reset()
+        img.zero_()
+        plan.grid(uvw, vis, wt)
+        plan.image_accumulate(img)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = plan.kernel_times(reset=True)
+    plan.set_profiling(False)
+    # A second timed pass without per-kernel events for the headline time.
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        plan.reset()
+        img.zero_()
+        plan.grid(uvw, vis, wt)
+        plan.image_accumulate(img)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    return (t3 - t2) / steps, (t1 - t0) / steps, kt
+
+
+def cpu_baseline(wl, budget_s=12.0):
+    """The FP64 oracle on a bounded sample of the same workload.
+
+    Sample: w-planes taken one at a time from the middle outwards, each with
+    the visibilities that fall on it, gridded and then transformed and
+    screened, until about ``budget_s`` seconds of oracle time are spent; the
+    time is scaled to the whole job (gridding by visibility count, FFT and
+    screen by plane count).  NumPy runs these steps on one core.
+    """
+    from oracle import wstack as o
+    p = o.Params.of(wl)
+    kall = o.plane_index(p, wl.uvw[:, 2])
+    dw = o.plane_spacing(p)
+    order = sorted(range(wl.nw), key=lambda k: abs(k - (wl.nw - 1) / 2))
+    t_grid = t_fft = 0.0
+    nvis = nplanes = 0
+    for k in order:
+        sel = kall == k
+        ps = o.Params(p.nu, p.nv, 1, p.fov_l, p.fov_m, p.w_min + k * dw,
+                      p.w_min + (k + 1) * dw, p.support, p.sigma)
+        t0 = time.perf_counter()
+        planes, _ = o.grid(ps, wl.uvw[sel], wl.vis[sel].astype(np.complex128),
+                           wl.weight[sel])
+        t1 = time.perf_counter()
+        o.wcorrect(ps, o.fft_planes(ps, planes, +1))
+        t2 = time.perf_counter()
+        t_grid += t1 - t0
+        t_fft += t2 - t1
+        nvis += int(sel.sum())
+        nplanes += 1
+        if t_grid + t_fft >= budget_s:
+            break
+    est = t_grid * wl.m / max(nvis, 1) + t_fft * wl.nw / nplanes
+    return {
+        "value": wl.m / est / 1e6, "unit": "Mvis/s", "cores": 1,
+        "kind": "oracle",
+        "sample": (f"FP64 NumPy oracle on {nplanes} of {wl.nw} w-planes: "
+                   f"{nvis} visibilities gridded in {t_grid:.1f} s, FFT + "
+                   f"screen of those planes in {t_fft:.1f} s; scaled to "
+                   f"{wl.m} visibilities and {wl.nw} planes = {est:.0f} s "
+                   f"per image"),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--m", type=int, default=10_000_000)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; "
+                          "--gpus must be 1"}))
+        return 2
+
+    import torch
+    import paper_2301_06061_amd as ws
+    import synth
+
+    dev = torch.device("cuda", 0)
+    t = time.perf_counter()
+    wl = synth.config2(m=args.m, precision=0)
+    log(f"workload: {wl.m} vis, {wl.nu}^2 x {wl.nw} planes, K={wl.support} "
+        f"({time.perf_counter() - t:.1f} s to draw)")
+    uvw = torch.from_numpy(wl.uvw).to(dev)
+    vis32 = torch.from_numpy(wl.vis).to(dev)
+    wt = torch.from_numpy(wl.weight).to(dev)
+
+    plan32 = ws.WStackPlan.from_workload(wl, precision="fp32")
+    img32 = plan32.new_image()
+    sec32, sec32_prof, kt32 = time_path(plan32, uvw, vis32, wt, img32,
+                                        args.steps, args.warmup, torch)
+    log(f"fp32: {sec32 * 1e3:.3f} ms/step")
+    for n_, (ms_, c_) in sorted(kt32.items(), key=lambda x: -x[1][0]):
+        log(f"  {n_:18s} {ms_ / max(c_, 1):8.3f} ms x {c_}")
+
+    res = {}
+    if not args.no_fp64:
+        plan64 = ws.WStackPlan.from_workload(wl, precision="fp64")
+        vis64 = vis32.to(torch.complex128)
+        img64 = plan64.new_image()
+        sec64, _, kt64 = time_path(plan64, uvw, vis64, wt, img64, args.steps,
+                                   args.warmup, torch)
+        log(f"fp64: {sec64 * 1e3:.3f} ms/step")
+        for n_, (ms_, c_) in sorted(kt64.items(), key=lambda x: -x[1][0]):
+            log(f"  {n_:18s} {ms_ / max(c_, 1):8.3f} ms x {c_}")
+        a = img32.to(torch.complex128)
+        rel = float(torch.linalg.vector_norm(a - img64) /
+                    torch.linalg.vector_norm(img64))
+        grid64 = sum(kt64[k][0] for k in kt64 if k not in (
+            "fft_cols", "row_screen_sum")) / args.steps
+        res["fp64"] = {
+            "ms_per_step": sec64 * 1e3,
+            "mvis_per_s": wl.m / sec64 / 1e6,
+            "grid_mvis_per_s": wl.m / (grid64 / 1e3) / 1e6,
+            "fp32_speedup": sec64 / sec32,
+            "fp32_grid_speedup": None,
+        }
+        res["rel_l2_fp32_vs_fp64"] = rel
+        del plan64, img64, vis64
+    grid32 = sum(kt32[k][0] for k in kt32 if k not in (
+        "fft_cols", "row_screen_sum")) / args.steps
+    if "fp64" in res:
+        res["fp64"]["fp32_grid_speedup"] = (res["fp64"]["grid_mvis_per_s"] and
+                                            (wl.m / (grid32 / 1e3) / 1e6) /
+                                            res["fp64"]["grid_mvis_per_s"])
+
+    # Roofline of the dominant kernel (largest share of the step).
+    name, (tot, cnt) = max(kt32.items(), key=lambda x: x[1][0])
+    avg_ms = tot / max(cnt, 1)
+    ab = algorithmic_bytes(name, wl, 8, wl.m)
+    roof = None
+    if ab is not None:
+        ach = ab / (avg_ms / 1e3) / 1e9
+        roof = {"kernel": name, "bound": "hbm", "achieved": ach,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "avg_ms": avg_ms, "algorithmic_bytes": ab}
+    kernels = {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]}
+               for k, v in kt32.items()}
+    gb = None
+    if "grid_tiles" in kt32:
+        g_ms = kt32["grid_tiles"][0] / kt32["grid_tiles"][1]
+        gab = algorithmic_bytes("grid_tiles", wl, 8, wl.m)
+        gb = {"avg_ms": g_ms, "achieved_gbs": gab / (g_ms / 1e3) / 1e9,
+              "frac": gab / (g_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        cpu = cpu_baseline(wl)
+        log(f"cpu baseline: {cpu['value']:.3f} Mvis/s "
+            f"({time.perf_counter() - t:.1f} s)")
+
+    out = {
+        "metric": "Mvis/s gridded + image s, 1 GPU; FP32 vs FP64 path at "
+                  "stated rel-L2 err",
+        "value": wl.m / sec32 / 1e6,
+        "unit": "Mvis/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "dense-core 1e7 vis, 4096^2 x 32 w-planes, "
+                               "K=7 Gaussian, 5 deg, FP32 path",
+                   "m": wl.m, "n": wl.nu, "nw": wl.nw, "support": wl.support,
+                   "precision": "fp32"},
+        "image_s": sec32,
+        "grid_mvis_per_s": wl.m / (grid32 / 1e3) / 1e6,
+        "ggpas": wl.m * wl.support ** 2 / (grid32 / 1e3) / 1e9,
+        "roofline": roof,
+        "grid_tiles_roofline": gb,
+        "kernels_fp32": kernels,
+        "cpu_baseline": cpu,
+    }
+    out.update(res)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,187 @@
+/*
+ * wstack.h - C ABI of the MI355X w-stacking imaging library (libwstack.so).
+ *
+ * The calls follow the paper's statement of the problem (Gheller, Taffoni &
+ * Goz, "High Performance W-stacking for Imaging Radio Astronomy Data",
+ * Sec. 2): visibilities with baseline coordinates (u, v, w) and weights are
+ * convolved with a Gaussian kernel onto a Cartesian mesh of N_u x N_v x N_w
+ * cells (Eq. 3, the nearest w-plane taking each visibility), every w-plane
+ * is Fourier transformed (Eq. 2, inner integral), and a w-dependent phase
+ * screen is applied to each transformed plane before the planes are summed
+ * into the dirty image (Eq. 2, outer integral).  Degridding, the adjoint
+ * map from an image back to visibilities, is the paper's future work
+ * (Sec. 5) and is provided as the exact conjugate transpose.
+ *
+ * Conventions (the paper leaves them open; these are the library's):
+ *   - u, v, w in wavelengths; fov_l, fov_m are the full image widths in
+ *     radians.  Cell size du = 1/fov_l, dv = 1/fov_m; pixel size
+ *     dl = fov_l/nu, dm = fov_m/nv.  Zero spacing at cell (nu/2, nv/2).
+ *   - Visibility position x = u fov_l + nu/2, y = v fov_m + nv/2 (FP64);
+ *     the K x K kernel is centred on the nearest cell floor(x + 1/2),
+ *     floor(y + 1/2); tap weight c g(i - x) g(j - y) with
+ *     g(d) = exp(-d^2/(2 sigma^2)), c = 1/(2 pi sigma^2).
+ *   - Plane k = clamp(floor((w - w_min)/dw), 0, nw - 1), dw = (w_max -
+ *     w_min)/nw, plane centre w_k = w_min + (k + 1/2) dw (nw = 1: one plane
+ *     at (w_min + w_max)/2).
+ *   - Transform: F[q][p] = sum_{j,i} P[j][i] exp(+2 pi i [(i - nu/2)(p -
+ *     nu/2)/nu + (j - nv/2)(q - nv/2)/nv]) (direction +1), unnormalised.
+ *   - Screen: exp(+2 pi i w_k (n - 1)), n - 1 = -r^2/(1 + sqrt(1 - r^2)),
+ *     r^2 = l^2 + m^2, l_p = (p - nu/2) dl, m_q = (q - nv/2) dm.
+ *
+ * Layouts: complex values are interleaved (re, im) - complex64 on the FP32
+ * path, complex128 on the FP64 path.  The plane stack is row-major
+ * [k][j][i] (i along u, fastest), the image [q][p] (p along l, fastest).
+ * uvw is float64 [m][3]; weights float32 [m] (NULL means unit weights).
+ *
+ * Memory: every device array is owned by the caller (for example torch
+ * tensors); the library never allocates device memory.  A plan owns only a
+ * small host structure.  All work is enqueued asynchronously on the plan's
+ * HIP stream; pointers must stay valid until that work completes.
+ *
+ * Errors: every call returns a ws_status; WS_OK is 0 and errors are
+ * negative.  Nothing is enqueued when a call fails its argument checks.
+ * ws_last_error() returns a thread-local description of the last failure.
+ * Kernel faults are asynchronous and surface at a later call or ws_sync().
+ * Threading: one plan must not be used from two threads at once; distinct
+ * plans are independent.
+ */
+#ifndef WSTACK_H
+#define WSTACK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ws_status;
+#define WS_OK 0
+#define WS_INVALID_ARG (-1)          /* null pointer, bad enum, bad range */
+#define WS_UNSUPPORTED_SIZE (-2)     /* grid or support outside the limits */
+#define WS_WORKSPACE_TOO_SMALL (-3)  /* a caller buffer is too small */
+#define WS_HIP_ERROR (-4)            /* a HIP runtime call failed */
+#define WS_BAD_STATE (-5)            /* call not allowed in the plan's state */
+
+#define WS_FP32 0 /* complex64 data, FP32 gridding, FFT and accumulation;
+                     FP64 positions, plane index and phase argument */
+#define WS_FP64 1 /* complex128 data, everything in FP64 (the paper's
+                     precision, Sec. 4.2 memory model) */
+
+/* Imaging geometry and kernel.
+ *   nu, nv   grid size, each a power of two in [16, 16384]
+ *   nw       number of w-planes, >= 1
+ *   fov_l, fov_m  full field of view in radians, > 0, with
+ *            (fov_l/2)^2 + (fov_m/2)^2 < 1
+ *   w_min, w_max  w range in wavelengths covered by the planes;
+ *            w_max > w_min when nw > 1
+ *   support  kernel support K in cells, odd, 1..15 (the paper uses 7)
+ *   sigma    Gaussian width in cells; <= 0 selects K/7
+ *   precision  WS_FP32 or WS_FP64
+ *   tile     gridding tile edge in cells (power of two, 16..64, > K - 1);
+ *            0 = automatic
+ *   chunk    most visibilities one gridding work item accumulates before a
+ *            split tile is merged; 0 = automatic */
+typedef struct ws_params {
+  int32_t nu, nv, nw;
+  double fov_l, fov_m;
+  double w_min, w_max;
+  int32_t support;
+  double sigma;
+  int32_t precision;
+  int32_t tile;
+  int32_t chunk;
+} ws_params;
+
+typedef struct ws_plan ws_plan;
+
+/* Check a parameter set without touching the GPU (host only). */
+ws_status ws_validate_params(const ws_params* params);
+
+/* Sizes in bytes of the two caller-owned device buffers a plan needs:
+ * the plane stack (nw * nv * nu complex cells) and the workspace for
+ * batches of up to max_vis visibilities (1 <= max_vis < 2^31).  Host only;
+ * needs no GPU.  Either output pointer may be NULL. */
+ws_status ws_workspace_bytes(const ws_params* params, int64_t max_vis,
+                             size_t* planes_bytes, size_t* work_bytes);
+
+/* Build a plan over caller-owned device buffers (Sec. 2: the Cartesian
+ * mesh of N_u x N_v x N_w cells).  planes and work must be device
+ * pointers of at least the sizes ws_workspace_bytes() returns, 256-byte
+ * aligned.  hip_stream is a hipStream_t (NULL = the null stream).  The
+ * stack starts empty: it is cleared lazily by the first call that needs
+ * it, so no work is enqueued here except the small twiddle tables.
+ * *out receives a host handle to release with ws_plan_destroy(). */
+ws_status ws_grid_init(const ws_params* params, int64_t max_vis, void* planes,
+                       size_t planes_bytes, void* work, size_t work_bytes,
+                       void* hip_stream, ws_plan** out);
+
+/* Convolutional gridding (Eq. 3) of m visibilities onto the plane stack,
+ * each to its nearest w-plane.  Additive: the first call after init or
+ * reset writes every cell of the stack exactly once (zeros included);
+ * later calls add to it, like the paper's slab-by-slab accumulation
+ * (Sec. 3.2).  uvw: device float64 [m][3]; vis: device complex64 (FP32
+ * path) or complex128 (FP64 path) [m]; weight: device float32 [m] or NULL.
+ * n_dropped_taps: device int64 that the number of kernel taps falling off
+ * the grid is ADDED to, or NULL.  A visibility with a non-finite
+ * coordinate drops all of its taps; non-finite values propagate.
+ * 0 <= m <= max_vis.  Fails with WS_BAD_STATE after ws_fft_planes(). */
+ws_status ws_grid_visibilities(ws_plan* plan, int64_t m, const double* uvw,
+                               const void* vis, const float* weight,
+                               int64_t* n_dropped_taps);
+
+/* In-place, unnormalised, centred 2-D FFT of every plane (Eq. 2, inner
+ * integral); direction +1 = exp(+2 pi i ...) (imaging), -1 = exp(-2 pi i
+ * ...) (its adjoint).  The stack then holds transforms. */
+ws_status ws_fft_planes(ws_plan* plan, int32_t direction);
+
+/* w-correction and plane reduction (Eq. 2, outer integral):
+ * image[q][p] += sum_k F_k[q][p] exp(+2 pi i w_k (n_pq - 1)), reading the
+ * transformed stack.  image: device [nv][nu] complex, same precision as the
+ * plan.  The caller zeroes the image before the first accumulation. */
+ws_status ws_wcorrect_accumulate(ws_plan* plan, void* image);
+
+/* Fused form of ws_fft_planes(+1) followed by ws_wcorrect_accumulate():
+ * the last FFT stage, the screen and the plane sum run in one pass that
+ * never writes the transformed planes back.  Same result to rounding.  It
+ * consumes the stack: afterwards the plan is reset (empty). */
+ws_status ws_image_accumulate(ws_plan* plan, void* image);
+
+/* Degridding (Sec. 5 future work): the exact adjoint of gridding, FFT(+1)
+ * and w-correction.  vis_out[m] = w_m sum_taps c g g Q_k(m)[j][i] with
+ * Q_k = FFT(-1)(conj(screen_k) * X).  image: device [nv][nu], complex in the
+ * plan's precision, or real (float32 on the FP32 path, float64 on the FP64
+ * path) when image_is_real != 0.  vis_out: device [m] complex, overwritten.
+ * Uses the plane stack as scratch and leaves the plan reset (empty). */
+ws_status ws_degrid(ws_plan* plan, const void* image, int32_t image_is_real,
+                    int64_t m, const double* uvw, const float* weight,
+                    void* vis_out);
+
+/* Start a new image: the stack counts as empty again (cleared lazily). */
+ws_status ws_plan_reset(ws_plan* plan);
+
+/* Replace the stream later calls enqueue on (a hipStream_t, NULL = null). */
+ws_status ws_set_stream(ws_plan* plan, void* hip_stream);
+
+/* Wait for all work the plan enqueued; reports asynchronous HIP errors. */
+ws_status ws_sync(ws_plan* plan);
+
+/* Per-kernel timing: when enabled, every kernel launch of the plan is
+ * bracketed by HIP events on the plan's stream and its duration is added
+ * to a per-kernel total.  ws_kernel_times() waits for the plan's stream,
+ * then fills up to cap entries of names (static strings), total ms and
+ * launch counts, and returns the number of kernels in *n; it also resets
+ * the totals when reset != 0. */
+ws_status ws_set_profiling(ws_plan* plan, int32_t enable);
+ws_status ws_kernel_times(ws_plan* plan, int32_t cap, const char** names,
+                          double* total_ms, int64_t* launches, int32_t* n,
+                          int32_t reset);
+
+void ws_plan_destroy(ws_plan* plan);
+const char* ws_status_string(ws_status status);
+const char* ws_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WSTACK_H */

@@ -1,0 +1,670 @@
+// C ABI of libwstack.so: argument checks, workspace layout, plan state and
+// the launch sequences of the four imaging steps (Sec. 2: gridding, FFT,
+// phase correction and plane reduction) and of degridding.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wstack.h"
+#include "ws_kernels.h"
+
+using namespace ws;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ws_status fail(ws_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr int kMaxN = 4096;
+constexpr int kMinN = 16;
+constexpr int kMaxSupport = 15;
+constexpr int64_t kMaxVis = (int64_t(1) << 31) - 1;
+
+enum PlaneState { kEmpty = 0, kGridded = 1, kTransformed = 2 };
+
+// Derived sizes of a parameter set.
+struct Layout {
+  int T;
+  uint32_t chunk;
+  uint32_t chunk_degrid;
+  int elem;
+  int64_t ntiles;
+  int64_t nkeys;
+  uint32_t max_slots;
+  uint32_t max_extra;
+  size_t planes_bytes;
+  // workspace offsets
+  size_t o_tw_u, o_tw_v, o_counts, o_sums, o_keyrank, o_cell, o_dxy, o_val,
+      o_idx, o_chunks, o_slot, o_counters, o_split, o_extra, o_partials,
+      total;
+};
+
+ws_status check_params(const ws_params* p) {
+  if (p == nullptr) return fail(WS_INVALID_ARG, "params is NULL");
+  if (!pow2(p->nu) || !pow2(p->nv))
+    return fail(WS_UNSUPPORTED_SIZE, "nu=%d, nv=%d: must be powers of two",
+                p->nu, p->nv);
+  if (p->nu < kMinN || p->nv < kMinN || p->nu > kMaxN || p->nv > kMaxN)
+    return fail(WS_UNSUPPORTED_SIZE, "nu=%d, nv=%d: supported range [%d, %d]",
+                p->nu, p->nv, kMinN, kMaxN);
+  if (p->nw < 1) return fail(WS_INVALID_ARG, "nw=%d: need >= 1", p->nw);
+  if (p->support < 1 || p->support > kMaxSupport || (p->support % 2) == 0)
+    return fail(WS_UNSUPPORTED_SIZE, "support=%d: must be odd in [1, %d]",
+                p->support, kMaxSupport);
+  if (!(p->fov_l > 0) || !(p->fov_m > 0) || !std::isfinite(p->fov_l) ||
+      !std::isfinite(p->fov_m))
+    return fail(WS_INVALID_ARG, "fov must be finite and > 0");
+  const double c2 = 0.25 * (p->fov_l * p->fov_l + p->fov_m * p->fov_m);
+  if (!(c2 < 1.0))
+    return fail(WS_INVALID_ARG, "field of view reaches past the horizon");
+  if (!std::isfinite(p->w_min) || !std::isfinite(p->w_max))
+    return fail(WS_INVALID_ARG, "w range must be finite");
+  if (p->nw > 1 && !(p->w_max > p->w_min))
+    return fail(WS_INVALID_ARG, "w_max must exceed w_min when nw > 1");
+  if (p->nw == 1 && p->w_max < p->w_min)
+    return fail(WS_INVALID_ARG, "w_max < w_min");
+  if (!std::isfinite(p->sigma))
+    return fail(WS_INVALID_ARG, "sigma must be finite");
+  if (p->precision != WS_FP32 && p->precision != WS_FP64)
+    return fail(WS_INVALID_ARG, "precision=%d: use WS_FP32 or WS_FP64",
+                p->precision);
+  if (p->tile != 0) {
+    if (!pow2(p->tile) || p->tile < 16 || p->tile > 64)
+      return fail(WS_UNSUPPORTED_SIZE, "tile=%d: power of two in [16, 64]",
+                  p->tile);
+    if (p->tile > p->nu || p->tile > p->nv)
+      return fail(WS_UNSUPPORTED_SIZE, "tile=%d larger than the grid",
+                  p->tile);
+    if (p->tile <= p->support - 1)
+      return fail(WS_UNSUPPORTED_SIZE, "tile=%d must exceed support-1",
+                  p->tile);
+  }
+  if (p->chunk < 0 || p->chunk > (1 << 24))
+    return fail(WS_INVALID_ARG, "chunk=%d out of range", p->chunk);
+  const int64_t cells = (int64_t)p->nu * p->nv;
+  if (p->nw > (int64_t(1) << 40) / cells)
+    return fail(WS_UNSUPPORTED_SIZE, "plane stack too large");
+  return WS_OK;
+}
+
+ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
+  ws_status st = check_params(p);
+  if (st != WS_OK) return st;
+  if (max_vis < 1 || max_vis > kMaxVis)
+    return fail(WS_INVALID_ARG, "max_vis=%lld: need 1 <= max_vis < 2^31",
+                (long long)max_vis);
+  const int nmin = p->nu < p->nv ? p->nu : p->nv;
+  L->T = p->tile != 0 ? p->tile : (nmin < 64 ? nmin : 64);
+  if (L->T <= p->support - 1)
+    return fail(WS_UNSUPPORTED_SIZE, "grid %d too small for support %d", nmin,
+                p->support);
+  L->chunk = p->chunk != 0 ? (uint32_t)p->chunk : 2048u;
+  L->chunk_degrid = p->chunk != 0 ? (uint32_t)p->chunk : 4096u;
+  L->elem = p->precision == WS_FP64 ? 16 : 8;
+  const int64_t tu = p->nu / L->T, tv = p->nv / L->T;
+  L->ntiles = tu * tv * p->nw;
+  L->nkeys = L->ntiles * kRegions;
+  if (L->nkeys >= (int64_t)0xFFFFFFF0ll)
+    return fail(WS_UNSUPPORTED_SIZE, "too many bins (%lld)",
+                (long long)L->nkeys);
+  int64_t slots = 2 * max_vis / L->chunk + 64;
+  if (slots > 4096) slots = 4096;
+  L->max_slots = (uint32_t)slots;
+  // Further work items beyond one per tile: at most max_slots when
+  // gridding (split tiles hold scratch slots), at most max_vis / chunk when
+  // degridding (each record is read by one tile).
+  const int64_t ex = max_vis / L->chunk_degrid + 2;
+  L->max_extra = (uint32_t)(ex > slots ? ex : slots);
+  L->planes_bytes = (size_t)p->nw * p->nv * p->nu * L->elem;
+  const size_t A = 256;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes, A);
+    return at;
+  };
+  const int64_t nscan = L->nkeys > L->ntiles ? L->nkeys : L->ntiles;
+  L->o_tw_u = take((size_t)p->nu * L->elem);
+  L->o_tw_v = take((size_t)p->nv * L->elem);
+  L->o_counts = take((size_t)(L->nkeys + 1) * 4);
+  L->o_sums = take((size_t)(scan_sums_len(nscan) + 1) * 4);
+  L->o_keyrank = take((size_t)max_vis * 8);
+  L->o_cell = take((size_t)max_vis * 4);
+  L->o_dxy = take((size_t)max_vis * L->elem);
+  L->o_val = take((size_t)max_vis * L->elem);
+  L->o_idx = take((size_t)max_vis * 4);
+  L->o_chunks = take((size_t)(L->ntiles + 1) * 4);
+  L->o_slot = take((size_t)L->ntiles * 4);
+  L->o_counters = take(64);
+  L->o_split = take((size_t)(L->max_slots / 2 + 1) * 4);
+  L->o_extra = take((size_t)L->max_extra * 8);
+  L->o_partials = take((size_t)L->max_slots * L->T * L->T * L->elem);
+  L->total = o;
+  return WS_OK;
+}
+
+}  // namespace
+
+struct ws_plan {
+  ws_params p;
+  int64_t max_vis;
+  Layout L;
+  Geo g;
+  void* planes;
+  unsigned char* work;
+  hipStream_t stream;
+  int state;
+  int device;
+  int cus;  // compute units of the device (sizes persistent launches)
+  // profiling
+  bool profile;
+  struct Pending {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<const char*> names;
+  std::vector<double> ms;
+  std::vector<int64_t> launches;
+
+  template <typename T>
+  T* w(size_t off) {
+    return reinterpret_cast<T*>(work + off);
+  }
+};
+
+namespace {
+
+int kernel_id(ws_plan* pl, const char* name) {
+  for (size_t i = 0; i < pl->names.size(); ++i)
+    if (std::strcmp(pl->names[i], name) == 0) return (int)i;
+  pl->names.push_back(name);
+  pl->ms.push_back(0.0);
+  pl->launches.push_back(0);
+  return (int)pl->names.size() - 1;
+}
+
+// Runs one launcher; when profiling, brackets it with events on the stream.
+template <class F>
+ws_status launch(ws_plan* pl, const char* name, F&& f) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (pl->profile) {
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+      return fail(WS_HIP_ERROR, "hipEventCreate failed");
+    hipEventRecord(a, pl->stream);
+  }
+  f();
+  hipError_t e = hipGetLastError();
+  if (pl->profile) {
+    hipEventRecord(b, pl->stream);
+    pl->pending.push_back({kernel_id(pl, name), a, b});
+  }
+  if (e != hipSuccess)
+    return fail(WS_HIP_ERROR, "%s: launch failed: %s", name,
+                hipGetErrorString(e));
+  return WS_OK;
+}
+
+#define WS_TRY(expr)                 \
+  do {                               \
+    ws_status _s = (expr);           \
+    if (_s != WS_OK) return _s;      \
+  } while (0)
+
+Geo make_geo(const ws_params* p, const Layout& L) {
+  Geo g{};
+  g.nu = p->nu;
+  g.nv = p->nv;
+  g.nw = p->nw;
+  g.K = p->support;
+  g.h = (p->support - 1) / 2;
+  g.T = L.T;
+  g.tiles_u = p->nu / L.T;
+  g.tiles_v = p->nv / L.T;
+  g.ntiles = (int)L.ntiles;
+  g.fov_l = p->fov_l;
+  g.fov_m = p->fov_m;
+  g.w_min = p->w_min;
+  if (p->nw == 1) {
+    g.dw = 1.0;
+    g.w0 = 0.5 * (p->w_min + p->w_max);
+  } else {
+    g.dw = (p->w_max - p->w_min) / p->nw;
+    g.w0 = p->w_min + 0.5 * g.dw;
+  }
+  g.dl = p->fov_l / p->nu;
+  g.dm = p->fov_m / p->nv;
+  const double sigma = p->sigma > 0 ? p->sigma : p->support / 7.0;
+  g.inv2s2 = 1.0 / (2.0 * sigma * sigma);
+  g.kappa = (float)(1.4426950408889634074 / (2.0 * sigma * sigma));
+  g.cnorm = 1.0 / (2.0 * M_PI * sigma * sigma);
+  return g;
+}
+
+template <typename R>
+ws_status zero_planes(ws_plan* pl) {
+  const int64_t n = (int64_t)pl->p.nw * pl->p.nv * pl->p.nu;
+  return launch(pl, "fill_zero",
+                [&] { launch_fill_zero<R>(pl->planes, n, pl->stream); });
+}
+
+// Binning shared by gridding and degridding: counts, offsets, records and
+// the per-tile work items.  Returns the grid size bound for the item kernel.
+template <typename R>
+ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
+                      const void* vis, const float* weight, int degrid,
+                      int64_t* n_dropped, uint32_t* max_items) {
+  const Layout& L = pl->L;
+  const Geo& g = pl->g;
+  hipStream_t st = pl->stream;
+  uint32_t* counts = pl->w<uint32_t>(L.o_counts);
+  uint32_t* sums = pl->w<uint32_t>(L.o_sums);
+  uint2* keyrank = pl->w<uint2>(L.o_keyrank);
+  uint32_t* chunks = pl->w<uint32_t>(L.o_chunks);
+  uint32_t* slot = pl->w<uint32_t>(L.o_slot);
+  uint32_t* counters = pl->w<uint32_t>(L.o_counters);
+  uint32_t* split = pl->w<uint32_t>(L.o_split);
+  const uint32_t chunk = degrid ? L.chunk_degrid : L.chunk;
+  WS_TRY(launch(pl, "zero_counts", [&] {
+    launch_zero_u32(counts, L.nkeys + 1, st);
+    launch_zero_u32(counters, 16, st);
+  }));
+  WS_TRY(launch(pl, "bin_count", [&] {
+    launch_bin_count(g, uvw, m, counts, keyrank,
+                     reinterpret_cast<unsigned long long*>(n_dropped), st);
+  }));
+  WS_TRY(launch(pl, "scan_keys", [&] {
+    launch_exclusive_scan(counts, counts, L.nkeys, sums, st);
+  }));
+  WS_TRY(launch(pl, "bin_scatter", [&] {
+    launch_bin_scatter<R>(g, uvw, vis, weight, m, keyrank, counts,
+                          pl->w<uint32_t>(L.o_cell), pl->work + L.o_dxy,
+                          pl->work + L.o_val,
+                          degrid ? pl->w<uint32_t>(L.o_idx) : nullptr, st);
+  }));
+  WS_TRY(launch(pl, "tile_work", [&] {
+    launch_tile_work(g, counts, degrid, chunk, chunks, slot, counters, split,
+                     L.max_slots, pl->w<uint2>(L.o_extra), L.max_extra, st);
+  }));
+  // Items: one per tile plus the further chunks of split tiles.
+  const int64_t reads = degrid ? m : 4 * m;
+  int64_t extra = (reads + chunk - 1) / chunk + 1;
+  if (extra > L.max_extra) extra = L.max_extra;
+  *max_items = (uint32_t)(L.ntiles + extra);
+  return WS_OK;
+}
+
+template <typename R>
+ws_status grid_impl(ws_plan* pl, int64_t m, const double* uvw, const void* vis,
+                    const float* weight, int64_t* n_dropped) {
+  const Layout& L = pl->L;
+  uint32_t max_items = 0;
+  WS_TRY(bin_records<R>(pl, m, uvw, vis, weight, 0, n_dropped, &max_items));
+  const int acc = pl->state == kGridded ? 1 : 0;
+  WS_TRY(launch(pl, "grid_tiles", [&] {
+    launch_grid_tiles<R>(pl->g, pl->w<uint32_t>(L.o_counts),
+                         pl->w<uint32_t>(L.o_counters), pl->w<uint2>(L.o_extra),
+                         pl->w<uint32_t>(L.o_chunks),
+                         pl->w<uint32_t>(L.o_slot), pl->w<uint32_t>(L.o_cell),
+                         pl->work + L.o_dxy, pl->work + L.o_val, L.chunk,
+                         pl->planes, pl->work + L.o_partials, acc, max_items,
+                         pl->cus, pl->stream);
+  }));
+  WS_TRY(launch(pl, "grid_merge", [&] {
+    launch_grid_merge<R>(pl->g, pl->w<uint32_t>(L.o_counters),
+                         pl->w<uint32_t>(L.o_split),
+                         pl->w<uint32_t>(L.o_chunks),
+                         pl->w<uint32_t>(L.o_slot), pl->work + L.o_partials,
+                         pl->planes, acc, L.max_slots / 2 + 1, pl->stream);
+  }));
+  pl->state = kGridded;
+  return WS_OK;
+}
+
+template <typename R>
+ws_status fft_impl(ws_plan* pl, int sign) {
+  const ws_params& p = pl->p;
+  bool ok = true;
+  WS_TRY(launch(pl, "fft_rows", [&] {
+    ok = launch_fft_rows<R>(pl->planes, p.nu, (int64_t)p.nw * p.nv,
+                            pl->work + pl->L.o_tw_u, sign, pl->stream);
+  }));
+  if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no row FFT for nu=%d", p.nu);
+  WS_TRY(launch(pl, "fft_cols", [&] {
+    ok = launch_fft_cols<R>(pl->planes, p.nv, p.nu, p.nw,
+                            pl->work + pl->L.o_tw_v, sign, pl->stream);
+  }));
+  if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no column FFT for nv=%d", p.nv);
+  return WS_OK;
+}
+
+template <typename R>
+ws_status image_impl(ws_plan* pl, void* image) {
+  const ws_params& p = pl->p;
+  bool ok = true;
+  WS_TRY(launch(pl, "fft_cols", [&] {
+    ok = launch_fft_cols<R>(pl->planes, p.nv, p.nu, p.nw,
+                            pl->work + pl->L.o_tw_v, +1, pl->stream);
+  }));
+  if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no column FFT for nv=%d", p.nv);
+  WS_TRY(launch(pl, "row_screen_sum", [&] {
+    ok = launch_row_screen_sum<R>(pl->planes, image, pl->g,
+                                  pl->work + pl->L.o_tw_u, pl->stream);
+  }));
+  if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no fused row FFT for nu=%d", p.nu);
+  return WS_OK;
+}
+
+template <typename R>
+ws_status degrid_impl(ws_plan* pl, const void* image, int image_is_real,
+                      int64_t m, const double* uvw, const float* weight,
+                      void* vis_out) {
+  const ws_params& p = pl->p;
+  const Layout& L = pl->L;
+  bool ok = true;
+  WS_TRY(launch(pl, "screen_row_bcast", [&] {
+    ok = launch_screen_row_bcast<R>(image, image_is_real, pl->planes, pl->g,
+                                    pl->work + L.o_tw_u, pl->stream);
+  }));
+  if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no fused row FFT for nu=%d", p.nu);
+  WS_TRY(launch(pl, "fft_cols", [&] {
+    ok = launch_fft_cols<R>(pl->planes, p.nv, p.nu, p.nw,
+                            pl->work + L.o_tw_v, -1, pl->stream);
+  }));
+  if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no column FFT for nv=%d", p.nv);
+  if (m == 0) return WS_OK;
+  uint32_t max_items = 0;
+  WS_TRY(bin_records<R>(pl, m, uvw, nullptr, weight, 1, nullptr, &max_items));
+  WS_TRY(launch(pl, "degrid_tiles", [&] {
+    launch_degrid_tiles<R>(pl->g, pl->w<uint32_t>(L.o_counts),
+                           pl->w<uint32_t>(L.o_counters),
+                           pl->w<uint2>(L.o_extra), pl->planes,
+                           pl->w<uint32_t>(L.o_cell), pl->work + L.o_dxy,
+                           pl->work + L.o_val, pl->w<uint32_t>(L.o_idx),
+                           L.chunk_degrid, vis_out, max_items, pl->cus,
+                           pl->stream);
+  }));
+  return WS_OK;
+}
+
+bool aligned(const void* p, size_t a) {
+  return (reinterpret_cast<uintptr_t>(p) % a) == 0;
+}
+
+ws_status check_plan(ws_plan* pl) {
+  if (pl == nullptr) return fail(WS_INVALID_ARG, "plan is NULL");
+  if (hipSetDevice(pl->device) != hipSuccess)
+    return fail(WS_HIP_ERROR, "hipSetDevice(%d) failed", pl->device);
+  return WS_OK;
+}
+
+ws_status check_vis_args(ws_plan* pl, int64_t m, const double* uvw,
+                         const float* weight) {
+  if (m < 0 || m > pl->max_vis)
+    return fail(WS_WORKSPACE_TOO_SMALL,
+                "m=%lld outside [0, max_vis=%lld]", (long long)m,
+                (long long)pl->max_vis);
+  if (m > 0 && uvw == nullptr) return fail(WS_INVALID_ARG, "uvw is NULL");
+  if (!aligned(uvw, 8) || !aligned(weight, 4))
+    return fail(WS_INVALID_ARG, "misaligned uvw or weight");
+  return WS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ws_status ws_validate_params(const ws_params* params) {
+  return check_params(params);
+}
+
+ws_status ws_workspace_bytes(const ws_params* params, int64_t max_vis,
+                             size_t* planes_bytes, size_t* work_bytes) {
+  Layout L;
+  WS_TRY(make_layout(params, max_vis, &L));
+  if (planes_bytes) *planes_bytes = L.planes_bytes;
+  if (work_bytes) *work_bytes = L.total;
+  return WS_OK;
+}
+
+ws_status ws_grid_init(const ws_params* params, int64_t max_vis, void* planes,
+                       size_t planes_bytes, void* work, size_t work_bytes,
+                       void* hip_stream, ws_plan** out) {
+  if (out == nullptr) return fail(WS_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  Layout L;
+  WS_TRY(make_layout(params, max_vis, &L));
+  if (planes == nullptr || work == nullptr)
+    return fail(WS_INVALID_ARG, "planes or work is NULL");
+  if (!aligned(planes, 256) || !aligned(work, 256))
+    return fail(WS_INVALID_ARG, "planes and work must be 256-byte aligned");
+  if (planes_bytes < L.planes_bytes)
+    return fail(WS_WORKSPACE_TOO_SMALL, "planes: %zu bytes < %zu needed",
+                planes_bytes, L.planes_bytes);
+  if (work_bytes < L.total)
+    return fail(WS_WORKSPACE_TOO_SMALL, "work: %zu bytes < %zu needed",
+                work_bytes, L.total);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess)
+    return fail(WS_HIP_ERROR, "hipGetDevice failed (no GPU?)");
+  ws_plan* pl = new (std::nothrow) ws_plan();
+  if (pl == nullptr) return fail(WS_INVALID_ARG, "out of host memory");
+  pl->p = *params;
+  pl->max_vis = max_vis;
+  pl->L = L;
+  pl->g = make_geo(params, L);
+  pl->planes = planes;
+  pl->work = static_cast<unsigned char*>(work);
+  pl->stream = static_cast<hipStream_t>(hip_stream);
+  pl->state = kEmpty;
+  pl->device = dev;
+  pl->cus = 256;
+  {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount,
+                              dev) == hipSuccess && n > 0)
+      pl->cus = n;
+  }
+  pl->profile = false;
+  ws_status st;
+  if (params->precision == WS_FP64) {
+    st = launch(pl, "twiddles", [&] {
+      launch_twiddles<double>(pl->work + L.o_tw_u, params->nu, pl->stream);
+      launch_twiddles<double>(pl->work + L.o_tw_v, params->nv, pl->stream);
+    });
+  } else {
+    st = launch(pl, "twiddles", [&] {
+      launch_twiddles<float>(pl->work + L.o_tw_u, params->nu, pl->stream);
+      launch_twiddles<float>(pl->work + L.o_tw_v, params->nv, pl->stream);
+    });
+  }
+  if (st != WS_OK) {
+    delete pl;
+    return st;
+  }
+  *out = pl;
+  return WS_OK;
+}
+
+ws_status ws_grid_visibilities(ws_plan* plan, int64_t m, const double* uvw,
+                               const void* vis, const float* weight,
+                               int64_t* n_dropped_taps) {
+  WS_TRY(check_plan(plan));
+  WS_TRY(check_vis_args(plan, m, uvw, weight));
+  if (m > 0 && vis == nullptr) return fail(WS_INVALID_ARG, "vis is NULL");
+  if (!aligned(vis, plan->L.elem) || !aligned(n_dropped_taps, 8))
+    return fail(WS_INVALID_ARG, "misaligned vis or n_dropped_taps");
+  if (plan->state == kTransformed)
+    return fail(WS_BAD_STATE,
+                "the stack holds transforms; call ws_plan_reset first");
+  if (plan->p.precision == WS_FP64)
+    return grid_impl<double>(plan, m, uvw, vis, weight, n_dropped_taps);
+  return grid_impl<float>(plan, m, uvw, vis, weight, n_dropped_taps);
+}
+
+ws_status ws_fft_planes(ws_plan* plan, int32_t direction) {
+  WS_TRY(check_plan(plan));
+  if (direction != 1 && direction != -1)
+    return fail(WS_INVALID_ARG, "direction=%d: use +1 or -1", direction);
+  const bool f64 = plan->p.precision == WS_FP64;
+  if (plan->state == kEmpty) {
+    WS_TRY(f64 ? zero_planes<double>(plan) : zero_planes<float>(plan));
+    plan->state = kTransformed;
+    return WS_OK;
+  }
+  WS_TRY(f64 ? fft_impl<double>(plan, direction)
+             : fft_impl<float>(plan, direction));
+  plan->state = kTransformed;
+  return WS_OK;
+}
+
+ws_status ws_wcorrect_accumulate(ws_plan* plan, void* image) {
+  WS_TRY(check_plan(plan));
+  if (image == nullptr) return fail(WS_INVALID_ARG, "image is NULL");
+  if (!aligned(image, plan->L.elem))
+    return fail(WS_INVALID_ARG, "misaligned image");
+  if (plan->state == kEmpty) return WS_OK;  // all planes are zero
+  return launch(plan, "wcorrect", [&] {
+    if (plan->p.precision == WS_FP64)
+      launch_wcorrect<double>(plan->planes, image, plan->g, plan->stream);
+    else
+      launch_wcorrect<float>(plan->planes, image, plan->g, plan->stream);
+  });
+}
+
+ws_status ws_image_accumulate(ws_plan* plan, void* image) {
+  WS_TRY(check_plan(plan));
+  if (image == nullptr) return fail(WS_INVALID_ARG, "image is NULL");
+  if (!aligned(image, plan->L.elem))
+    return fail(WS_INVALID_ARG, "misaligned image");
+  if (plan->state == kTransformed)
+    return fail(WS_BAD_STATE,
+                "the stack already holds transforms; use "
+                "ws_wcorrect_accumulate");
+  if (plan->state == kEmpty) return WS_OK;
+  ws_status st = plan->p.precision == WS_FP64
+                     ? image_impl<double>(plan, image)
+                     : image_impl<float>(plan, image);
+  plan->state = kEmpty;
+  return st;
+}
+
+ws_status ws_degrid(ws_plan* plan, const void* image, int32_t image_is_real,
+                    int64_t m, const double* uvw, const float* weight,
+                    void* vis_out) {
+  WS_TRY(check_plan(plan));
+  WS_TRY(check_vis_args(plan, m, uvw, weight));
+  if (image == nullptr) return fail(WS_INVALID_ARG, "image is NULL");
+  if (m > 0 && vis_out == nullptr)
+    return fail(WS_INVALID_ARG, "vis_out is NULL");
+  const size_t ea = image_is_real ? plan->L.elem / 2 : plan->L.elem;
+  if (!aligned(image, ea) || !aligned(vis_out, plan->L.elem))
+    return fail(WS_INVALID_ARG, "misaligned image or vis_out");
+  ws_status st = plan->p.precision == WS_FP64
+                     ? degrid_impl<double>(plan, image, image_is_real != 0, m,
+                                           uvw, weight, vis_out)
+                     : degrid_impl<float>(plan, image, image_is_real != 0, m,
+                                          uvw, weight, vis_out);
+  plan->state = kEmpty;
+  return st;
+}
+
+ws_status ws_plan_reset(ws_plan* plan) {
+  if (plan == nullptr) return fail(WS_INVALID_ARG, "plan is NULL");
+  plan->state = kEmpty;
+  return WS_OK;
+}
+
+ws_status ws_set_stream(ws_plan* plan, void* hip_stream) {
+  if (plan == nullptr) return fail(WS_INVALID_ARG, "plan is NULL");
+  plan->stream = static_cast<hipStream_t>(hip_stream);
+  return WS_OK;
+}
+
+ws_status ws_sync(ws_plan* plan) {
+  WS_TRY(check_plan(plan));
+  const hipError_t e = hipStreamSynchronize(plan->stream);
+  if (e != hipSuccess)
+    return fail(WS_HIP_ERROR, "stream error: %s", hipGetErrorString(e));
+  return WS_OK;
+}
+
+ws_status ws_set_profiling(ws_plan* plan, int32_t enable) {
+  if (plan == nullptr) return fail(WS_INVALID_ARG, "plan is NULL");
+  plan->profile = enable != 0;
+  return WS_OK;
+}
+
+ws_status ws_kernel_times(ws_plan* plan, int32_t cap, const char** names,
+                          double* total_ms, int64_t* launches, int32_t* n,
+                          int32_t reset) {
+  WS_TRY(check_plan(plan));
+  if (hipStreamSynchronize(plan->stream) != hipSuccess)
+    return fail(WS_HIP_ERROR, "stream error while collecting times");
+  for (auto& pe : plan->pending) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, pe.a, pe.b) == hipSuccess) {
+      plan->ms[pe.id] += t;
+      plan->launches[pe.id] += 1;
+    }
+    hipEventDestroy(pe.a);
+    hipEventDestroy(pe.b);
+  }
+  plan->pending.clear();
+  const int32_t cnt = (int32_t)plan->names.size();
+  for (int32_t i = 0; i < cnt && i < cap; ++i) {
+    if (names) names[i] = plan->names[i];
+    if (total_ms) total_ms[i] = plan->ms[i];
+    if (launches) launches[i] = plan->launches[i];
+  }
+  if (n) *n = cnt;
+  if (reset) {
+    for (auto& v : plan->ms) v = 0.0;
+    for (auto& v : plan->launches) v = 0;
+  }
+  return WS_OK;
+}
+
+void ws_plan_destroy(ws_plan* plan) {
+  if (plan == nullptr) return;
+  for (auto& pe : plan->pending) {
+    hipEventDestroy(pe.a);
+    hipEventDestroy(pe.b);
+  }
+  delete plan;
+}
+
+const char* ws_status_string(ws_status status) {
+  switch (status) {
+    case WS_OK: return "WS_OK";
+    case WS_INVALID_ARG: return "WS_INVALID_ARG";
+    case WS_UNSUPPORTED_SIZE: return "WS_UNSUPPORTED_SIZE";
+    case WS_WORKSPACE_TOO_SMALL: return "WS_WORKSPACE_TOO_SMALL";
+    case WS_HIP_ERROR: return "WS_HIP_ERROR";
+    case WS_BAD_STATE: return "WS_BAD_STATE";
+    default: return "WS_UNKNOWN_STATUS";
+  }
+}
+
+const char* ws_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

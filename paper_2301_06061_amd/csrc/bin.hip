@@ -1,0 +1,314 @@
+// Binning of visibilities by (w-plane, uv tile, edge region): the MI355X
+// counterpart of the paper's per-slab linked lists (Sec. 3.2), which gather
+// the visibilities of one slab, halo included, into contiguous arrays so
+// that the gridding kernel reads them in order.  Here a counting sort builds
+// one contiguous record range per key:
+//   bin_count   FP64 placement, key and rank of every visibility; ranks
+//               come from an LDS hash table per workgroup, so a hot key
+//               costs one global atomic per workgroup, not per visibility
+//   scan_*      exclusive scan of the key counts into record offsets
+//   bin_scatter writes the packed record of every visibility at
+//               offset[key] + rank
+//   tile_work   per tile: records to process (own + neighbours' facing
+//               strips), number of work items, split-tile scratch slots
+#include "ws_kernels.h"
+
+namespace ws {
+
+namespace {
+
+constexpr int kCountThreads = 256;
+constexpr int kCountPerBlock = 2048;    // visibilities per workgroup
+constexpr int kHashSize = 4096;         // >= 2 x kCountPerBlock
+constexpr int kCountPerThread = kCountPerBlock / kCountThreads;
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t key) {
+  return (key * 2654435761u) >> (32 - 12);  // 12 = log2(kHashSize)
+}
+
+__global__ __launch_bounds__(kCountThreads) void k_bin_count(
+    Geo g, const double* __restrict__ uvw, int64_t m,
+    uint32_t* __restrict__ counts, uint2* __restrict__ keyrank,
+    unsigned long long* __restrict__ dropped) {
+  __shared__ uint32_t s_key[kHashSize];
+  __shared__ uint32_t s_cnt[kHashSize];
+  __shared__ unsigned long long s_drop;
+  const int tid = threadIdx.x;
+  for (int s = tid; s < kHashSize; s += kCountThreads) {
+    s_key[s] = kNoKey;
+    s_cnt[s] = 0;
+  }
+  if (tid == 0) s_drop = 0;
+  __syncthreads();
+
+  uint32_t my_key[kCountPerThread];
+  uint32_t my_slot[kCountPerThread];
+  uint32_t my_rank[kCountPerThread];
+  unsigned long long my_drop = 0;
+  const int64_t base = (int64_t)blockIdx.x * kCountPerBlock;
+#pragma unroll
+  for (int e = 0; e < kCountPerThread; ++e) {
+    const int64_t gi = base + e * kCountThreads + tid;
+    my_key[e] = kNoKey;
+    if (gi < m) {
+      double x, y;
+      int i0, j0, k;
+      const double u = uvw[3 * gi], v = uvw[3 * gi + 1], w = uvw[3 * gi + 2];
+      if (place(g, u, v, w, x, y, i0, j0, k)) {
+        my_drop += (unsigned long long)(g.K * g.K - taps_on_grid(g, i0, j0));
+        const uint32_t key = bin_key(g, i0, j0, k);
+        uint32_t s = hash_slot(key);
+        while (true) {
+          const uint32_t prev = atomicCAS(&s_key[s], kNoKey, key);
+          if (prev == kNoKey || prev == key) break;
+          s = (s + 1) & (kHashSize - 1);
+        }
+        my_key[e] = key;
+        my_slot[e] = s;
+        my_rank[e] = atomicAdd(&s_cnt[s], 1u);
+      } else {
+        my_drop += (unsigned long long)(g.K * g.K);
+      }
+    }
+  }
+  if (dropped != nullptr && my_drop != 0) atomicAdd(&s_drop, my_drop);
+  __syncthreads();
+  // One global atomic per distinct key of the workgroup; the returned old
+  // count becomes the workgroup's base rank for that key (kept in s_cnt).
+  for (int s = tid; s < kHashSize; s += kCountThreads) {
+    const uint32_t key = s_key[s];
+    if (key != kNoKey) s_cnt[s] = atomicAdd(&counts[key], s_cnt[s]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kCountPerThread; ++e) {
+    const int64_t gi = base + e * kCountThreads + tid;
+    if (gi < m) {
+      uint2 kr;
+      kr.x = my_key[e];
+      kr.y = my_key[e] == kNoKey ? 0u : s_cnt[my_slot[e]] + my_rank[e];
+      keyrank[gi] = kr;
+    }
+  }
+  if (tid == 0 && dropped != nullptr && s_drop != 0)
+    atomicAdd(dropped, s_drop);
+}
+
+// ---- exclusive scan of uint32 counts (reduce, scan of block sums, apply) --
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPerThread = 16;
+constexpr int kScanBlock = kScanThreads * kScanPerThread;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v,
+                                                         uint32_t* s_tmp,
+                                                         uint32_t* total) {
+  // Inclusive wave scan, then a scan of the wave totals.
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_tmp[wave] = x;
+  __syncthreads();
+  uint32_t wbase = 0;
+  uint32_t all = 0;
+  for (int w2 = 0; w2 < (int)(blockDim.x >> 6); ++w2) {
+    const uint32_t t = s_tmp[w2];
+    if (w2 < wave) wbase += t;
+    all += t;
+  }
+  __syncthreads();
+  *total = all;
+  return wbase + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(
+    const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ sums) {
+  __shared__ uint32_t s_tmp[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  uint32_t acc = 0;
+#pragma unroll
+  for (int e = 0; e < kScanPerThread; ++e) {
+    const int64_t i = base + (int64_t)e * kScanThreads + threadIdx.x;
+    if (i < n) acc += in[i];
+  }
+  uint32_t total;
+  block_exclusive_scan(acc, s_tmp, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t* __restrict__ sums,
+                                                    int64_t nb) {
+  // One workgroup: exclusive scan of nb block sums in place; sums[nb] = total.
+  __shared__ uint32_t s_tmp[16];
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
+    const int64_t i = b0 + threadIdx.x;
+    const uint32_t v = i < nb ? sums[i] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(v, s_tmp, &total);
+    if (i < nb) sums[i] = carry + ex;
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(
+    const uint32_t* in, uint32_t* out, int64_t n,
+    const uint32_t* __restrict__ sums, int64_t nb) {
+  // Each thread owns kScanPerThread consecutive elements.
+  __shared__ uint32_t s_tmp[kScanThreads / 64];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock +
+                       (int64_t)threadIdx.x * kScanPerThread;
+  uint32_t v[kScanPerThread];
+  uint32_t acc = 0;
+#pragma unroll
+  for (int e = 0; e < kScanPerThread; ++e) {
+    const int64_t i = base + e;
+    v[e] = i < n ? in[i] : 0u;
+    acc += v[e];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(acc, s_tmp, &total) + sums[blockIdx.x];
+#pragma unroll
+  for (int e = 0; e < kScanPerThread; ++e) {
+    const int64_t i = base + e;
+    if (i < n) out[i] = run;
+    run += v[e];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nb];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_bin_scatter(
+    Geo g, const double* __restrict__ uvw, const cplx<R>* __restrict__ vis,
+    const float* __restrict__ weight, int64_t m,
+    const uint2* __restrict__ keyrank, const uint32_t* __restrict__ offsets,
+    uint32_t* __restrict__ rec_cell, cplx<R>* __restrict__ rec_dxy,
+    cplx<R>* __restrict__ rec_val, uint32_t* __restrict__ rec_idx) {
+  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= m) return;
+  const uint2 kr = keyrank[gi];
+  if (kr.x == kNoKey) return;
+  double x, y;
+  int i0, j0, k;
+  place(g, uvw[3 * gi], uvw[3 * gi + 1], uvw[3 * gi + 2], x, y, i0, j0, k);
+  const uint32_t pos = offsets[kr.x] + kr.y;
+  rec_cell[pos] = pack_cell(i0, j0);
+  // Fractional offsets from the nearest cell, subtracted in FP64 first.
+  rec_dxy[pos] = cplx<R>{(R)(x - (double)i0), (R)(y - (double)j0)};
+  const R wt = weight != nullptr ? (R)weight[gi] : (R)1;
+  if (rec_idx == nullptr) {
+    const cplx<R> vv = vis[gi];
+    rec_val[pos] = cplx<R>{wt * vv.re, wt * vv.im};
+  } else {
+    rec_val[pos] = cplx<R>{wt, (R)0};
+    rec_idx[pos] = (uint32_t)gi;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tile_work(
+    Geo g, const uint32_t* __restrict__ offsets, int mode_degrid,
+    uint32_t chunk, uint32_t* __restrict__ tile_chunks,
+    uint32_t* __restrict__ tile_slot, uint32_t* __restrict__ counters,
+    uint32_t* __restrict__ split_list, uint32_t max_slots,
+    uint2* __restrict__ extra, uint32_t max_extra) {
+  // counters[0]: scratch slots taken, [1]: split tiles, [2]: extra items.
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.ntiles) return;
+  uint32_t work = 0;
+  if (mode_degrid) {
+    work = offsets[(uint32_t)t * kRegions + kRegions] -
+           offsets[(uint32_t)t * kRegions];
+  } else {
+    uint32_t lo[10], hi[10];
+    const int ns = tile_segments(g, t, lo, hi);
+    for (int s = 0; s < ns; ++s) work += offsets[hi[s]] - offsets[lo[s]];
+  }
+  uint32_t nch = work == 0 ? 1u : (work + chunk - 1) / chunk;
+  tile_slot[t] = 0;
+  if (nch > 1 && !mode_degrid) {
+    const uint32_t s0 = atomicAdd(&counters[0], nch);
+    if (s0 + nch <= max_slots) {
+      tile_slot[t] = s0;
+      split_list[atomicAdd(&counters[1], 1u)] = (uint32_t)t;
+    } else {
+      nch = 1;  // scratch exhausted: one item grids the whole tile
+    }
+  }
+  if (nch > 1) {
+    const uint32_t e0 = atomicAdd(&counters[2], nch - 1);
+    if (e0 + (nch - 1) <= max_extra) {
+      for (uint32_t c = 1; c < nch; ++c)
+        extra[e0 + c - 1] = make_uint2((uint32_t)t, c);
+    } else {
+      nch = 1;  // cannot happen with the sizes the plan reserves
+    }
+  }
+  tile_chunks[t] = nch;
+}
+
+}  // namespace
+
+void launch_bin_count(const Geo& g, const double* uvw, int64_t m,
+                      uint32_t* counts, uint2* keyrank,
+                      unsigned long long* dropped, hipStream_t st) {
+  if (m == 0) return;
+  const int64_t nb = (m + kCountPerBlock - 1) / kCountPerBlock;
+  hipLaunchKernelGGL(k_bin_count, dim3((unsigned)nb), dim3(kCountThreads), 0,
+                     st, g, uvw, m, counts, keyrank, dropped);
+}
+
+int64_t scan_sums_len(int64_t n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
+
+void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
+                           uint32_t* sums, hipStream_t st) {
+  // out has n + 1 entries; out[n] = total.  in may alias out.
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0,
+                     st, in, n, sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, sums, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0,
+                     st, in, out, n, sums, nb);
+}
+
+template <typename R>
+void launch_bin_scatter(const Geo& g, const double* uvw, const void* vis,
+                        const float* weight, int64_t m, const uint2* keyrank,
+                        const uint32_t* offsets, uint32_t* rec_cell,
+                        void* rec_dxy, void* rec_val, uint32_t* rec_idx,
+                        hipStream_t st) {
+  if (m == 0) return;
+  const int64_t nb = (m + 255) / 256;
+  hipLaunchKernelGGL(k_bin_scatter<R>, dim3((unsigned)nb), dim3(256), 0, st, g,
+                     uvw, (const cplx<R>*)vis, weight, m, keyrank, offsets,
+                     rec_cell, (cplx<R>*)rec_dxy, (cplx<R>*)rec_val, rec_idx);
+}
+
+template void launch_bin_scatter<float>(const Geo&, const double*, const void*,
+                                        const float*, int64_t, const uint2*,
+                                        const uint32_t*, uint32_t*, void*,
+                                        void*, uint32_t*, hipStream_t);
+template void launch_bin_scatter<double>(const Geo&, const double*,
+                                         const void*, const float*, int64_t,
+                                         const uint2*, const uint32_t*,
+                                         uint32_t*, void*, void*, uint32_t*,
+                                         hipStream_t);
+
+void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
+                      uint32_t chunk, uint32_t* tile_chunks,
+                      uint32_t* tile_slot, uint32_t* counters,
+                      uint32_t* split_list, uint32_t max_slots, uint2* extra,
+                      uint32_t max_extra, hipStream_t st) {
+  const int nb = (g.ntiles + 255) / 256;
+  hipLaunchKernelGGL(k_tile_work, dim3(nb), dim3(256), 0, st, g, offsets,
+                     mode_degrid, chunk, tile_chunks, tile_slot, counters,
+                     split_list, max_slots, extra, max_extra);
+}
+
+}  // namespace ws

@@ -1,0 +1,567 @@
+// Batched 2-D FFT of the w-planes (Eq. 2, inner integral) and the fused
+// w-screen kernels (Eq. 2, outer integral).
+//
+// Each 1-D transform is a Stockham autosort FFT (radix 8, one radix-4 or
+// radix-2 stage last) held in LDS: the first stage reads HBM directly and
+// the last writes HBM directly, so a transform costs one read and one write
+// of its line.  Rows are transformed one per workgroup; columns in blocks of
+// BC adjacent columns per workgroup (BC * 8 or 16 bytes per row segment),
+// with the blocks of one XCD covering adjacent columns so that the partial
+// cache lines of a segment are shared in that XCD's L2.  The centring
+// (DC at N/2 in both domains) is a (-1)^index sign on input and output,
+// valid for every N divisible by 4.  Twiddles e^{2 pi i t/N} come from
+// tables computed in FP64 once per plan.
+//
+// Fused kernels: after the column stage, one workgroup per image row q
+// transforms row q of every plane in turn and accumulates
+// F_k[q][p] exp(2 pi i w_k (n_pq - 1)) in registers, so the transformed
+// planes are never written back; the degridding counterpart multiplies an
+// image row by each plane's conjugate screen before transforming it.  The
+// screen phasor is advanced plane to plane by an FP64 complex multiply
+// (the planes are equispaced in w), seeded with FP64 sincospi of the
+// phase reduced to [-1/2, 1/2] turn.
+#include "ws_kernels.h"
+
+namespace ws {
+
+namespace {
+
+template <typename R>
+__device__ __forceinline__ cplx<R> rot_i(cplx<R> a, R s) {
+  // a * (s i)
+  return {-s * a.im, s * a.re};
+}
+
+template <typename R>
+__device__ __forceinline__ void dft2(cplx<R>* v) {
+  const cplx<R> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <typename R>
+__device__ __forceinline__ void dft4(cplx<R>* v, R s) {
+  const cplx<R> a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+  const cplx<R> a2 = cadd(v[1], v[3]);
+  const cplx<R> a3 = rot_i(csub(v[1], v[3]), s);
+  v[0] = cadd(a0, a2);
+  v[2] = csub(a0, a2);
+  v[1] = cadd(a1, a3);
+  v[3] = csub(a1, a3);
+}
+
+template <typename R>
+__device__ __forceinline__ void dft8(cplx<R>* v, R s) {
+  // Two length-4 transforms of the even and odd samples, then one radix-2
+  // stage with the eighth roots of unity e^{s 2 pi i t/8}.
+  cplx<R> e[4] = {v[0], v[2], v[4], v[6]};
+  cplx<R> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4(e, s);
+  dft4(o, s);
+  const R h = (R)0.70710678118654752440084436210484903928;
+  const cplx<R> o1 = {h * (o[1].re - s * o[1].im), h * (o[1].im + s * o[1].re)};
+  const cplx<R> o2 = rot_i(o[2], s);
+  const cplx<R> o3 = {h * (-o[3].re - s * o[3].im), h * (s * o[3].re - o[3].im)};
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+
+template <typename R, int RAD>
+__device__ __forceinline__ void dft(cplx<R>* v, R s) {
+  if constexpr (RAD == 8) dft8(v, s);
+  else if constexpr (RAD == 4) dft4(v, s);
+  else dft2(v);
+}
+
+// Twiddles e^{s 2 pi i idx/N} from two small LDS tables, e^{2 pi i lo/N}
+// for lo < 64 and e^{2 pi i 64 hi/N}, both rounded from FP64 values.
+template <typename R>
+struct Twiddles {
+  const cplx<R>* t_lo;
+  const cplx<R>* t_hi;
+  __device__ __forceinline__ cplx<R> operator()(int idx, R s) const {
+    const cplx<R> a = t_lo[idx & 63], b = t_hi[idx >> 6];
+    const cplx<R> w = cmul(a, b);
+    return {w.re, s * w.im};
+  }
+};
+
+constexpr int kTwLo = 64;
+
+// Fill the LDS twiddle tables of a length-n transform from the global table.
+template <typename R>
+__device__ __forceinline__ Twiddles<R> load_twiddles(cplx<R>* s_lo,
+                                                     cplx<R>* s_hi,
+                                                     const cplx<R>* tw, int n) {
+  for (int i = threadIdx.x; i < kTwLo; i += blockDim.x) s_lo[i] = tw[i % n];
+  for (int i = threadIdx.x; i < (n + kTwLo - 1) / kTwLo; i += blockDim.x)
+    s_hi[i] = tw[i * kTwLo];
+  return Twiddles<R>{s_lo, s_hi};
+}
+
+// LDS slot of line element e: one padding slot after every 8 elements, so
+// that the strided stores of the first stages hit distinct banks.
+__device__ __forceinline__ constexpr int lslot(int e) { return e + (e >> 3); }
+
+template <int N>
+constexpr int lds_line(int bc) {
+  return (N + N / 8) * bc;
+}
+
+// Stage P of a length-2^LOGN Stockham FFT over BC interleaved columns
+// (element e of column c at lds[e * BC + c]).  Stage 0 reads through
+// ld(e, c); the last stage hands each output to st(e, c, it, r, value).
+template <typename R, int LOGN, int BC, int NT, int P>
+struct Stage {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int NP8 = LOGN / 3;
+  static constexpr int REM = LOGN % 3;
+  static constexpr int NPASS = NP8 + (REM ? 1 : 0);
+  static constexpr int RAD = P < NP8 ? 8 : (REM == 1 ? 2 : 4);
+  static constexpr int NS = 1 << (3 * P);
+  static constexpr int NB = N / RAD;
+  static constexpr int TPC = NT / BC;
+  static constexpr int IT = (NB + TPC - 1) / TPC;
+  static constexpr bool FIRST = P == 0;
+  static constexpr bool LAST = P == NPASS - 1;
+
+  template <class Load, class Store>
+  __device__ __forceinline__ static void run(cplx<R>* lds, const Load& ld,
+                                             const Store& st,
+                                             const Twiddles<R>& tw, R s) {
+    const int c = threadIdx.x % BC;
+    const int jt = threadIdx.x / BC;
+    cplx<R> v[IT][RAD];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int j = jt + it * TPC;
+      if (NB % TPC == 0 || j < NB) {
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) {
+          const int e = j + r * NB;
+          if constexpr (FIRST) v[it][r] = ld(e, c, it, r);
+          else v[it][r] = lds[lslot(e) * BC + c];
+        }
+      }
+    }
+    if constexpr (!FIRST) __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int j = jt + it * TPC;
+      if (NB % TPC == 0 || j < NB) {
+        const int k = j & (NS - 1);
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int r = 1; r < RAD; ++r)
+            v[it][r] = cmul(v[it][r], tw(r * k * (N / (NS * RAD)), s));
+        }
+        dft<R, RAD>(v[it], s);
+        if constexpr (LAST) {
+#pragma unroll
+          for (int r = 0; r < RAD; ++r) st(j + r * NB, c, it, r, v[it][r]);
+        } else {
+          const int ob = (j / NS) * NS * RAD + k;
+#pragma unroll
+          for (int r = 0; r < RAD; ++r)
+            lds[lslot(ob + r * NS) * BC + c] = v[it][r];
+        }
+      }
+    }
+    if constexpr (!LAST) {
+      __syncthreads();
+      Stage<R, LOGN, BC, NT, P + 1>::run(lds, ld, st, tw, s);
+    }
+  }
+};
+
+template <typename R, int LOGN, int BC, int NT, class Load, class Store>
+__device__ __forceinline__ void fft_line(cplx<R>* lds, const Load& ld,
+                                         const Store& st,
+                                         const Twiddles<R>& tw, R s) {
+  Stage<R, LOGN, BC, NT, 0>::run(lds, ld, st, tw, s);
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> checker(cplx<R> v, int e) {
+  return (e & 1) ? cplx<R>{-v.re, -v.im} : v;
+}
+
+// ---- plain row and column transforms (in place, any plane count) --------
+
+template <typename R, int LOGN, int NT>
+__global__ __launch_bounds__(NT) void k_fft_rows(cplx<R>* data, int64_t nrows,
+                                                 const cplx<R>* __restrict__ tw,
+                                                 R s) {
+  constexpr int N = 1 << LOGN;
+  __shared__ cplx<R> lds[lds_line<N>(1)];
+  __shared__ cplx<R> s_lo[kTwLo], s_hi[(N + kTwLo - 1) / kTwLo];
+  const int64_t row = blockIdx.x;
+  if (row >= nrows) return;
+  const Twiddles<R> twl = load_twiddles(s_lo, s_hi, tw, N);
+  __syncthreads();
+  cplx<R>* line = data + row * N;
+  auto ld = [&](int e, int, int, int) { return checker(line[e], e); };
+  auto st = [&](int e, int, int, int, cplx<R> v) { line[e] = checker(v, e); };
+  fft_line<R, LOGN, 1, NT>(lds, ld, st, twl, s);
+}
+
+template <typename R, int LOGN, int BC, int NT>
+__global__ __launch_bounds__(NT) void k_fft_cols(cplx<R>* data, int ncols,
+                                                 int nplanes,
+                                                 const cplx<R>* __restrict__ tw,
+                                                 R s) {
+  constexpr int N = 1 << LOGN;  // column length = number of rows
+  __shared__ cplx<R> lds[lds_line<N>(BC)];
+  __shared__ cplx<R> s_lo[kTwLo], s_hi[(N + kTwLo - 1) / kTwLo];
+  // XCD-aware order: the blocks one XCD runs (b, b+8, ...) take adjacent
+  // column blocks of the same plane.
+  const int nb_plane = ncols / BC;
+  const int nb = nb_plane * nplanes;
+  const int per_xcd = (nb + 7) / 8;
+  const int L = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (L >= nb) return;
+  const int plane = L / nb_plane;
+  const int col0 = (L - plane * nb_plane) * BC;
+  cplx<R>* base = data + (size_t)plane * N * ncols + col0;
+  auto ld = [&](int e, int c, int, int) {
+    return checker(base[(size_t)e * ncols + c], e);
+  };
+  auto st = [&](int e, int c, int, int, cplx<R> v) {
+    base[(size_t)e * ncols + c] = checker(v, e);
+  };
+  const Twiddles<R> twl = load_twiddles(s_lo, s_hi, tw, N);
+  __syncthreads();
+  fft_line<R, LOGN, BC, NT>(lds, ld, st, twl, s);
+}
+
+// ---- w-screen -------------------------------------------------------------
+
+// exp(2 pi i a) for a phase a in turns, reduced to [-1/2, 1/2] in FP64.
+__device__ __forceinline__ cplx<double> turns_phasor(double a) {
+  const double f = a - rint(a);
+  double sn, cs;
+  sincospi(2.0 * f, &sn, &cs);
+  return {cs, sn};
+}
+
+// n - 1 = sqrt(1 - l^2 - m^2) - 1 in the cancellation-free form.
+__device__ __forceinline__ double n_minus_one(const Geo& g, int p, int q) {
+  const double l = (double)(p - g.nu / 2) * g.dl;
+  const double m = (double)(q - g.nv / 2) * g.dm;
+  const double r2 = l * l + m * m;
+  return -r2 / (1.0 + sqrt(1.0 - r2));
+}
+
+// Screen phasor of plane 0 and the plane-to-plane step at pixel (p, q);
+// conj = true gives the conjugate screen.
+__device__ __forceinline__ void screen_seed(const Geo& g, int p, int q,
+                                            bool conj, cplx<double>& ph,
+                                            cplx<double>& step) {
+  const double nm1 = n_minus_one(g, p, q);
+  ph = turns_phasor(g.w0 * nm1);
+  step = turns_phasor(g.dw * nm1);
+  if (conj) {
+    ph.im = -ph.im;
+    step.im = -step.im;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_wcorrect(const cplx<R>* __restrict__ F,
+                                                  cplx<R>* __restrict__ img,
+                                                  Geo g) {
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t npix = (int64_t)g.nu * g.nv;
+  if (pix >= npix) return;
+  const int q = (int)(pix / g.nu), p = (int)(pix - (int64_t)q * g.nu);
+  cplx<double> ph, step;
+  screen_seed(g, p, q, false, ph, step);
+  cplx<R> acc = {(R)0, (R)0};
+  for (int k = 0; k < g.nw; ++k) {
+    const cplx<R> f = F[(size_t)k * npix + pix];
+    const cplx<R> w = {(R)ph.re, (R)ph.im};
+    acc = cadd(acc, cmul(f, w));
+    ph = cmul(ph, step);
+  }
+  img[pix] = cadd(img[pix], acc);
+}
+
+// Row transform of every plane + screen + plane sum into image row q.
+template <typename R, int LOGN, int NT>
+__global__ __launch_bounds__(NT) void k_row_screen_sum(
+    const cplx<R>* __restrict__ planes, cplx<R>* __restrict__ img, Geo g,
+    const cplx<R>* __restrict__ tw) {
+  constexpr int N = 1 << LOGN;
+  using L = Stage<R, LOGN, 1, NT, (LOGN / 3) + ((LOGN % 3) ? 1 : 0) - 1>;
+  constexpr int IT = L::IT, RAD = L::RAD, NB = L::NB;
+  __shared__ cplx<R> lds[lds_line<N>(1)];
+  __shared__ cplx<R> s_lo[kTwLo], s_hi[(N + kTwLo - 1) / kTwLo];
+  const int q = blockIdx.x;
+  const Twiddles<R> twl = load_twiddles(s_lo, s_hi, tw, N);
+  __syncthreads();
+  cplx<R> acc[IT][RAD];
+  cplx<double> ph[IT][RAD], step[IT][RAD];
+#pragma unroll
+  for (int it = 0; it < IT; ++it)
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) {
+      const int p = threadIdx.x + it * NT + r * NB;
+      acc[it][r] = {(R)0, (R)0};
+      if (NB % NT == 0 || threadIdx.x + it * NT < NB)
+        screen_seed(g, p, q, false, ph[it][r], step[it][r]);
+    }
+  for (int k = 0; k < g.nw; ++k) {
+    const cplx<R>* line = planes + ((size_t)k * g.nv + q) * N;
+    auto ld = [&](int e, int, int, int) { return checker(line[e], e); };
+    auto st = [&](int e, int, int it, int r, cplx<R> v) {
+      v = checker(v, e);
+      const cplx<R> w = {(R)ph[it][r].re, (R)ph[it][r].im};
+      acc[it][r] = cadd(acc[it][r], cmul(v, w));
+      ph[it][r] = cmul(ph[it][r], step[it][r]);
+    };
+    fft_line<R, LOGN, 1, NT>(lds, ld, st, twl, (R)1);
+  }
+  cplx<R>* out = img + (size_t)q * N;
+#pragma unroll
+  for (int it = 0; it < IT; ++it)
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) {
+      const int j = threadIdx.x + it * NT;
+      if (NB % NT == 0 || j < NB) {
+        const int p = j + r * NB;
+        out[p] = cadd(out[p], acc[it][r]);
+      }
+    }
+}
+
+// Degridding counterpart: image row q times each plane's conjugate screen,
+// then the row transform (sign -1), written to row q of every plane.
+template <typename R, int LOGN, int NT>
+__global__ __launch_bounds__(NT) void k_screen_row_bcast(
+    const void* __restrict__ img, int img_real, cplx<R>* __restrict__ planes,
+    Geo g, const cplx<R>* __restrict__ tw) {
+  constexpr int N = 1 << LOGN;
+  using F0 = Stage<R, LOGN, 1, NT, 0>;
+  constexpr int IT = F0::IT, RAD = F0::RAD, NB = F0::NB;
+  __shared__ cplx<R> lds[lds_line<N>(1)];
+  __shared__ cplx<R> s_lo[kTwLo], s_hi[(N + kTwLo - 1) / kTwLo];
+  const int q = blockIdx.x;
+  const Twiddles<R> twl = load_twiddles(s_lo, s_hi, tw, N);
+  __syncthreads();
+  cplx<R> x[IT][RAD];
+  cplx<double> ph[IT][RAD], step[IT][RAD];
+#pragma unroll
+  for (int it = 0; it < IT; ++it)
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) {
+      const int j = threadIdx.x + it * NT;
+      x[it][r] = {(R)0, (R)0};
+      if (NB % NT == 0 || j < NB) {
+        const int p = j + r * NB;
+        if (img_real) {
+          x[it][r].re = reinterpret_cast<const R*>(img)[(size_t)q * N + p];
+        } else {
+          x[it][r] = reinterpret_cast<const cplx<R>*>(img)[(size_t)q * N + p];
+        }
+        screen_seed(g, p, q, true, ph[it][r], step[it][r]);
+      }
+    }
+  for (int k = 0; k < g.nw; ++k) {
+    cplx<R>* line = planes + ((size_t)k * g.nv + q) * N;
+    auto ld = [&](int e, int, int it, int r) {
+      const cplx<R> w = {(R)ph[it][r].re, (R)ph[it][r].im};
+      const cplx<R> v = cmul(x[it][r], w);
+      ph[it][r] = cmul(ph[it][r], step[it][r]);
+      return checker(v, e);
+    };
+    auto st = [&](int e, int, int, int, cplx<R> v) { line[e] = checker(v, e); };
+    fft_line<R, LOGN, 1, NT>(lds, ld, st, twl, (R)-1);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_fill_zero(cplx<R>* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = i; t < n; t += stride) p[t] = cplx<R>{(R)0, (R)0};
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero_u32(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = i; t < n; t += stride) p[t] = 0u;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_twiddles(cplx<R>* tw, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double sn, cs;
+  sincospi(2.0 * (double)i / (double)n, &sn, &cs);
+  tw[i] = cplx<R>{(R)cs, (R)sn};
+}
+
+// Threads per row transform: enough to cover the N/8 first-stage
+// butterflies once, 64..512.
+constexpr int row_threads(int logn) {
+  return (1 << logn) / 8 < 64 ? 64 : ((1 << logn) / 8 > 512 ? 512 : (1 << logn) / 8);
+}
+
+template <typename R, int LOGN>
+void rows_t(cplx<R>* data, int64_t nrows, const cplx<R>* tw, R s,
+            hipStream_t st) {
+  constexpr int NT = row_threads(LOGN);
+  hipLaunchKernelGGL((k_fft_rows<R, LOGN, NT>), dim3((unsigned)nrows),
+                     dim3(NT), 0, st, data, nrows, tw, s);
+}
+
+template <typename R, int LOGN>
+void cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
+            hipStream_t st) {
+  constexpr int N = 1 << LOGN;
+  constexpr int ELEM = sizeof(cplx<R>);
+  // Widest column block (<= 16) whose padded N x BC tile fits 150 KiB of
+  // LDS (the twiddle tables take the rest).
+  constexpr int BCMAX = (150 * 1024) / (lds_line<N>(1) * ELEM);
+  constexpr int BC = BCMAX >= 16 ? 16 : (BCMAX >= 8 ? 8 : (BCMAX >= 4 ? 4 : (BCMAX >= 2 ? 2 : 1)));
+  constexpr int NT = (N * BC) / 16 < 64 ? 64 : ((N * BC) / 16 > 512 ? 512 : (N * BC) / 16);
+  const int nb = (ncols / BC) * nplanes;
+  const int grid = ((nb + 7) / 8) * 8;
+  hipLaunchKernelGGL((k_fft_cols<R, LOGN, BC, NT>), dim3(grid), dim3(NT), 0,
+                     st, data, ncols, nplanes, tw, s);
+}
+
+template <typename R, int LOGN>
+void row_screen_t(const cplx<R>* planes, cplx<R>* img, const Geo& g,
+                  const cplx<R>* tw, hipStream_t st) {
+  constexpr int NT = row_threads(LOGN);
+  hipLaunchKernelGGL((k_row_screen_sum<R, LOGN, NT>), dim3(g.nv), dim3(NT), 0,
+                     st, planes, img, g, tw);
+}
+
+template <typename R, int LOGN>
+void screen_bcast_t(const void* img, int img_real, cplx<R>* planes,
+                    const Geo& g, const cplx<R>* tw, hipStream_t st) {
+  constexpr int NT = row_threads(LOGN);
+  hipLaunchKernelGGL((k_screen_row_bcast<R, LOGN, NT>), dim3(g.nv), dim3(NT),
+                     0, st, img, img_real, planes, g, tw);
+}
+
+int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+#define WS_LOGN_SWITCH(LOGN_VAR, CALL)                                     \
+  switch (LOGN_VAR) {                                                      \
+    case 4: { constexpr int LG = 4; CALL; } break;                         \
+    case 5: { constexpr int LG = 5; CALL; } break;                         \
+    case 6: { constexpr int LG = 6; CALL; } break;                         \
+    case 7: { constexpr int LG = 7; CALL; } break;                         \
+    case 8: { constexpr int LG = 8; CALL; } break;                         \
+    case 9: { constexpr int LG = 9; CALL; } break;                         \
+    case 10: { constexpr int LG = 10; CALL; } break;                       \
+    case 11: { constexpr int LG = 11; CALL; } break;                       \
+    case 12: { constexpr int LG = 12; CALL; } break;                       \
+    default: return false;                                                 \
+  }
+
+}  // namespace
+
+bool fft_supported(int n, int elem_bytes) {
+  (void)elem_bytes;
+  return n >= 16 && n <= 4096 && (n & (n - 1)) == 0;
+}
+
+template <typename R>
+bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw, int sign,
+                     hipStream_t st) {
+  const int lg = ilog2(n);
+  WS_LOGN_SWITCH(lg, (rows_t<R, LG>((cplx<R>*)data, nrows, (const cplx<R>*)tw,
+                                    (R)sign, st)));
+  return true;
+}
+
+template <typename R>
+bool launch_fft_cols(void* data, int nrows, int ncols, int nplanes,
+                     const void* tw, int sign, hipStream_t st) {
+  const int lg = ilog2(nrows);
+  WS_LOGN_SWITCH(lg, (cols_t<R, LG>((cplx<R>*)data, ncols, nplanes,
+                                    (const cplx<R>*)tw, (R)sign, st)));
+  return true;
+}
+
+template <typename R>
+bool launch_row_screen_sum(const void* planes, void* img, const Geo& g,
+                           const void* tw_u, hipStream_t st) {
+  const int lg = ilog2(g.nu);
+  WS_LOGN_SWITCH(lg, (row_screen_t<R, LG>((const cplx<R>*)planes, (cplx<R>*)img,
+                                          g, (const cplx<R>*)tw_u, st)));
+  return true;
+}
+
+template <typename R>
+bool launch_screen_row_bcast(const void* img, int img_real, void* planes,
+                             const Geo& g, const void* tw_u, hipStream_t st) {
+  const int lg = ilog2(g.nu);
+  WS_LOGN_SWITCH(lg, (screen_bcast_t<R, LG>(img, img_real, (cplx<R>*)planes, g,
+                                            (const cplx<R>*)tw_u, st)));
+  return true;
+}
+
+template <typename R>
+void launch_wcorrect(const void* F, void* img, const Geo& g, hipStream_t st) {
+  const int64_t npix = (int64_t)g.nu * g.nv;
+  hipLaunchKernelGGL(k_wcorrect<R>, dim3((unsigned)((npix + 255) / 256)),
+                     dim3(256), 0, st, (const cplx<R>*)F, (cplx<R>*)img, g);
+}
+
+template <typename R>
+void launch_fill_zero(void* p, int64_t n, hipStream_t st) {
+  if (n == 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_zero<R>, dim3((unsigned)blocks), dim3(256), 0, st,
+                     (cplx<R>*)p, n);
+}
+
+void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st) {
+  if (n == 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_fill_zero_u32, dim3((unsigned)blocks), dim3(256), 0, st,
+                     p, n);
+}
+
+template <typename R>
+void launch_twiddles(void* tw, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_twiddles<R>, dim3((n + 255) / 256), dim3(256), 0, st,
+                     (cplx<R>*)tw, n);
+}
+
+#define WS_INST(R)                                                            \
+  template bool launch_fft_rows<R>(void*, int, int64_t, const void*, int,    \
+                                   hipStream_t);                             \
+  template bool launch_fft_cols<R>(void*, int, int, int, const void*, int,   \
+                                   hipStream_t);                             \
+  template bool launch_row_screen_sum<R>(const void*, void*, const Geo&,     \
+                                         const void*, hipStream_t);          \
+  template bool launch_screen_row_bcast<R>(const void*, int, void*,          \
+                                           const Geo&, const void*,          \
+                                           hipStream_t);                     \
+  template void launch_wcorrect<R>(const void*, void*, const Geo&,           \
+                                   hipStream_t);                             \
+  template void launch_fill_zero<R>(void*, int64_t, hipStream_t);           \
+  template void launch_twiddles<R>(void*, int, hipStream_t);
+WS_INST(float)
+WS_INST(double)
+#undef WS_INST
+
+}  // namespace ws

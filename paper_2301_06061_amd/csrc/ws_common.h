@@ -1,0 +1,182 @@
+// Shared device-side definitions of the w-stacking library: complex types,
+// the per-plan geometry block every kernel receives, the FP64 visibility
+// placement (Sec. 2: nearest cell and nearest w-plane) and the bin-key
+// layout used by the binning, gridding and degridding kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace ws {
+
+template <typename R>
+struct cplx {
+  R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> cadd(cplx<R> a, cplx<R> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> csub(cplx<R> a, cplx<R> b) {
+  return {a.re - b.re, a.im - b.im};
+}
+
+// Number of bin regions per tile: a tile's cells split into a 3 x 3 pattern
+// of edge strips (width h) and the interior, so that the records a
+// neighbouring tile needs form a few contiguous key ranges.
+constexpr int kRegions = 9;
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+// Integer cell indices are packed into 16 bits each with this offset.
+constexpr int kCellBias = 64;
+
+// Geometry block passed by value to every kernel.
+struct Geo {
+  int nu, nv, nw;      // grid size and plane count
+  int K, h;            // kernel support and half-width
+  int T;               // gridding tile edge (cells)
+  int tiles_u, tiles_v;
+  int ntiles;          // nw * tiles_u * tiles_v
+  double fov_l, fov_m; // full field of view (radians)
+  double w_min, dw;    // plane origin and spacing (dw unused when nw == 1)
+  double w0;           // centre of plane 0
+  double dl, dm;       // pixel size in direction cosines
+  double inv2s2;       // 1 / (2 sigma^2), FP64
+  float kappa;         // log2(e) / (2 sigma^2), FP32 (exp2 form)
+  double cnorm;        // 1 / (2 pi sigma^2)
+};
+
+// FP64 placement of one visibility.  Contraction is off so that the cell
+// position and the plane index round exactly as the separate IEEE multiply,
+// add and divide of the definition.  Returns false when every tap of the
+// visibility falls off the grid (including non-finite coordinates).
+__host__ __device__ inline bool place(const Geo& g, double u, double v,
+                                      double w, double& x, double& y, int& i0,
+                                      int& j0, int& k) {
+#pragma clang fp contract(off)
+  x = u * g.fov_l + 0.5 * (double)g.nu;
+  y = v * g.fov_m + 0.5 * (double)g.nv;
+  // x - x is 0 for every finite x and NaN for NaN and +-Inf.
+  if (!(u - u == 0.0 && v - v == 0.0 && w - w == 0.0)) return false;
+  if (!(fabs(x) < 1.0e9 && fabs(y) < 1.0e9)) return false;
+  const double fi = floor(x + 0.5);
+  const double fj = floor(y + 0.5);
+  if (fi < -g.h || fi > g.nu - 1 + g.h || fj < -g.h || fj > g.nv - 1 + g.h)
+    return false;
+  i0 = (int)fi;
+  j0 = (int)fj;
+  if (g.nw == 1) {
+    k = 0;
+  } else {
+    double t = floor((w - g.w_min) / g.dw);
+    t = t < 0.0 ? 0.0 : t;
+    t = t > (double)(g.nw - 1) ? (double)(g.nw - 1) : t;
+    k = (int)t;
+  }
+  return true;
+}
+
+// Number of the K*K taps of a visibility centred on (i0, j0) that lie on
+// the grid.
+__host__ __device__ inline int taps_on_grid(const Geo& g, int i0, int j0) {
+  int lo = i0 - g.h < 0 ? 0 : i0 - g.h;
+  int hi = i0 + g.h > g.nu - 1 ? g.nu - 1 : i0 + g.h;
+  const int cols = hi >= lo ? hi - lo + 1 : 0;
+  lo = j0 - g.h < 0 ? 0 : j0 - g.h;
+  hi = j0 + g.h > g.nv - 1 ? g.nv - 1 : j0 + g.h;
+  const int rows = hi >= lo ? hi - lo + 1 : 0;
+  return cols * rows;
+}
+
+// Region of a tile-local coordinate along one axis: 0 = the strip within h
+// of the low edge, 2 = within h of the high edge, 1 = interior.
+__host__ __device__ inline int strip(int local, int T, int h) {
+  return local < h ? 0 : (local >= T - h ? 2 : 1);
+}
+
+// Regions are numbered around the tile's rim, then the interior:
+//   (ry, rx): (0,0)=0 (0,1)=1 (0,2)=2 (1,2)=3 (2,2)=4 (2,1)=5 (2,0)=6 (1,0)=7
+//   (1,1)=8.
+// With this order, the records a neighbouring tile needs (one edge: three
+// regions; one corner: one region) are a single key range, except the
+// low-u edge, which is two.
+__host__ __device__ inline int region_code(int ry, int rx) {
+  const int tab[3][3] = {{0, 1, 2}, {7, 8, 3}, {6, 5, 4}};
+  return tab[ry][rx];
+}
+
+// Bin key of a placed visibility: (plane, tile row, tile column, region).
+// The home tile is the one holding the nearest cell, clamped to the grid.
+__host__ __device__ inline uint32_t bin_key(const Geo& g, int i0, int j0,
+                                            int k) {
+  const int ic = i0 < 0 ? 0 : (i0 > g.nu - 1 ? g.nu - 1 : i0);
+  const int jc = j0 < 0 ? 0 : (j0 > g.nv - 1 ? g.nv - 1 : j0);
+  const int tx = ic / g.T, ty = jc / g.T;
+  const int rx = strip(ic - tx * g.T, g.T, g.h);
+  const int ry = strip(jc - ty * g.T, g.T, g.h);
+  const uint32_t tile =
+      ((uint32_t)k * (uint32_t)g.tiles_v + (uint32_t)ty) * (uint32_t)g.tiles_u +
+      (uint32_t)tx;
+  return tile * kRegions + (uint32_t)region_code(ry, rx);
+}
+
+__host__ __device__ inline uint32_t pack_cell(int i0, int j0) {
+  return (uint32_t)(i0 + kCellBias) | ((uint32_t)(j0 + kCellBias) << 16);
+}
+
+__host__ __device__ inline int cell_i(uint32_t c) {
+  return (int)(c & 0xFFFFu) - kCellBias;
+}
+
+__host__ __device__ inline int cell_j(uint32_t c) {
+  return (int)(c >> 16) - kCellBias;
+}
+
+// The key ranges (in units of keys) of the records whose kernel footprint
+// reaches tile t: its own nine regions plus the facing strips and corners
+// of its up to eight neighbours.  Writes up to 10 [lo, hi) pairs; returns
+// the count.
+__host__ __device__ inline int tile_segments(const Geo& g, int t,
+                                             uint32_t lo[10],
+                                             uint32_t hi[10]) {
+  const int per_plane = g.tiles_u * g.tiles_v;
+  const int k = t / per_plane;
+  const int rem = t - k * per_plane;
+  const int ty = rem / g.tiles_u;
+  const int tx = rem - ty * g.tiles_u;
+  const uint32_t base = (uint32_t)k * per_plane;
+  auto key0 = [&](int yy, int xx) {
+    return (base + (uint32_t)(yy * g.tiles_u + xx)) * kRegions;
+  };
+  int n = 0;
+  auto add = [&](uint32_t a, uint32_t b) {
+    lo[n] = a;
+    hi[n] = b;
+    ++n;
+  };
+  add(key0(ty, tx), key0(ty, tx) + 9);
+  const bool L = tx > 0, Rt = tx + 1 < g.tiles_u;
+  const bool A = ty > 0, B = ty + 1 < g.tiles_v;
+  if (Rt) {  // right neighbour's low-u strip: regions 6, 7 and 0
+    add(key0(ty, tx + 1) + 6, key0(ty, tx + 1) + 8);
+    add(key0(ty, tx + 1) + 0, key0(ty, tx + 1) + 1);
+  }
+  if (L) add(key0(ty, tx - 1) + 2, key0(ty, tx - 1) + 5);  // high-u strip
+  if (B) add(key0(ty + 1, tx) + 0, key0(ty + 1, tx) + 3);  // low-v strip
+  if (A) add(key0(ty - 1, tx) + 4, key0(ty - 1, tx) + 7);  // high-v strip
+  if (Rt && B) add(key0(ty + 1, tx + 1) + 0, key0(ty + 1, tx + 1) + 1);
+  if (L && B) add(key0(ty + 1, tx - 1) + 2, key0(ty + 1, tx - 1) + 3);
+  if (Rt && A) add(key0(ty - 1, tx + 1) + 6, key0(ty - 1, tx + 1) + 7);
+  if (L && A) add(key0(ty - 1, tx - 1) + 4, key0(ty - 1, tx - 1) + 5);
+  return n;
+}
+
+}  // namespace ws

@@ -1,0 +1,81 @@
+// Host-side launchers of the w-stacking kernels (one translation unit per
+// group: binning, gridding/degridding, FFT and screen).  Every launcher only
+// enqueues work on the given stream; buffers are caller-owned device memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ws_common.h"
+
+namespace ws {
+
+// binning (bin.hip)
+void launch_bin_count(const Geo& g, const double* uvw, int64_t m,
+                      uint32_t* counts, uint2* keyrank,
+                      unsigned long long* dropped, hipStream_t st);
+int64_t scan_sums_len(int64_t n);
+void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
+                           uint32_t* sums, hipStream_t st);
+template <typename R>
+void launch_bin_scatter(const Geo& g, const double* uvw, const void* vis,
+                        const float* weight, int64_t m, const uint2* keyrank,
+                        const uint32_t* offsets, uint32_t* rec_cell,
+                        void* rec_dxy, void* rec_val, uint32_t* rec_idx,
+                        hipStream_t st);
+void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
+                      uint32_t chunk, uint32_t* tile_chunks,
+                      uint32_t* tile_slot, uint32_t* counters,
+                      uint32_t* split_list, uint32_t max_slots, uint2* extra,
+                      uint32_t max_extra, hipStream_t st);
+
+// gridding and degridding (grid.hip)
+int grid_lds_pitch(int T, int K);
+size_t degrid_lds_bytes(int T, int K, int elem_bytes);
+template <typename R>
+void launch_grid_tiles(const Geo& g, const uint32_t* offsets,
+                       uint32_t* counters, const uint2* extra,
+                       const uint32_t* tile_chunks, const uint32_t* tile_slot,
+                       const uint32_t* rec_cell, const void* rec_dxy,
+                       const void* rec_val, uint32_t chunk, void* planes,
+                       void* partials, int accumulate, uint32_t max_items,
+                       int cus, hipStream_t st);
+template <typename R>
+void launch_grid_merge(const Geo& g, const uint32_t* counters,
+                       const uint32_t* split_list, const uint32_t* tile_chunks,
+                       const uint32_t* tile_slot, const void* partials,
+                       void* planes, int accumulate, uint32_t max_split,
+                       hipStream_t st);
+template <typename R>
+void launch_degrid_tiles(const Geo& g, const uint32_t* offsets,
+                         uint32_t* counters, const uint2* extra,
+                         const void* planes, const uint32_t* rec_cell,
+                         const void* rec_dxy, const void* rec_val,
+                         const uint32_t* rec_idx, uint32_t chunk,
+                         void* vis_out, uint32_t max_items, int cus,
+                         hipStream_t st);
+
+// FFT and screen (fft.hip)
+bool fft_supported(int n, int elem_bytes);
+template <typename R>
+bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw,
+                     int sign, hipStream_t st);
+template <typename R>
+bool launch_fft_cols(void* data, int nrows, int ncols, int nplanes,
+                     const void* tw, int sign, hipStream_t st);
+template <typename R>
+bool launch_row_screen_sum(const void* planes, void* img, const Geo& g,
+                           const void* tw_u, hipStream_t st);
+template <typename R>
+bool launch_screen_row_bcast(const void* img, int img_real, void* planes,
+                             const Geo& g, const void* tw_u, hipStream_t st);
+template <typename R>
+void launch_wcorrect(const void* F, void* img, const Geo& g, hipStream_t st);
+template <typename R>
+void launch_fill_zero(void* p, int64_t n, hipStream_t st);
+void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
+template <typename R>
+void launch_twiddles(void* tw, int n, hipStream_t st);
+
+}  // namespace ws

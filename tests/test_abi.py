@@ -1,0 +1,112 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and its host-only calls (validation, buffer sizes) behave as the
+header states.  No call here needs a GPU."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+import paper_2301_06061_amd as ws
+from paper_2301_06061_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wstack.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ws_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ws.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in wstack.h but not exported"
+    # the binding declares exactly the header's entry points
+    assert sorted(_abi.exported_symbols()) == names
+
+
+def _p(**kw):
+    base = dict(nu=512, nv=512, nw=8, fov_l=math.radians(1), fov_m=math.radians(1),
+                w_min=-100.0, w_max=100.0, support=7, sigma=0.0,
+                precision="fp64")
+    base.update(kw)
+    return ws.make_params(**base)
+
+
+def test_plane_bytes_match_paper_table3():
+    """FP64 path: 16-byte cells, so the Medium mesh is Table 3's 4.0 GB."""
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN,
+                                                   "paper_table3_mesh.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    medium = [r for r in rows if r[0] == "medium"][0]
+    nu, nv, nw, gb = int(medium[1]), int(medium[2]), int(medium[3]), float(medium[4])
+    pb, wb = ws.workspace_bytes(_p(nu=nu, nv=nv, nw=nw), 1 << 20)
+    assert pb / 2 ** 30 == pytest.approx(gb, rel=1e-12)
+    pb32, _ = ws.workspace_bytes(_p(nu=nu, nv=nv, nw=nw, precision="fp32"),
+                                 1 << 20)
+    assert pb32 * 2 == pb
+
+
+def test_workspace_grows_with_max_vis():
+    _, w1 = ws.workspace_bytes(_p(), 1000)
+    _, w2 = ws.workspace_bytes(_p(), 100000)
+    assert w2 > w1
+    # records: at least key/rank (8) + cell (4) + 2 complex (32) + index (4)
+    assert w2 - w1 >= 99000 * 48
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(nu=500), _abi.WS_UNSUPPORTED_SIZE),
+    (dict(nv=8), _abi.WS_UNSUPPORTED_SIZE),
+    (dict(nu=8192), _abi.WS_UNSUPPORTED_SIZE),
+    (dict(nw=0), _abi.WS_INVALID_ARG),
+    (dict(support=6), _abi.WS_UNSUPPORTED_SIZE),
+    (dict(support=17), _abi.WS_UNSUPPORTED_SIZE),
+    (dict(fov_l=0.0), _abi.WS_INVALID_ARG),
+    (dict(fov_l=float("nan")), _abi.WS_INVALID_ARG),
+    (dict(fov_l=2.0, fov_m=2.0), _abi.WS_INVALID_ARG),
+    (dict(w_min=1.0, w_max=1.0), _abi.WS_INVALID_ARG),
+    (dict(w_max=float("inf")), _abi.WS_INVALID_ARG),
+    (dict(precision=1, tile=48), _abi.WS_UNSUPPORTED_SIZE),
+    (dict(tile=8), _abi.WS_UNSUPPORTED_SIZE),
+    (dict(nu=16, nv=16, tile=16, support=17), _abi.WS_UNSUPPORTED_SIZE),
+])
+def test_invalid_params_rejected(kw, status):
+    with pytest.raises(ws.WStackError) as ei:
+        ws.validate(_p(**kw))
+    assert ei.value.status == status
+    assert len(str(ei.value)) > 20
+
+
+def test_valid_edge_params_accepted():
+    ws.validate(_p(nw=1, w_min=5.0, w_max=5.0))
+    ws.validate(_p(nu=16, nv=16, support=15))
+    ws.validate(_p(nu=4096, nv=16, support=1, tile=16))
+
+
+def test_max_vis_bounds():
+    with pytest.raises(ws.WStackError) as ei:
+        ws.workspace_bytes(_p(), 0)
+    assert ei.value.status == _abi.WS_INVALID_ARG
+    with pytest.raises(ws.WStackError):
+        ws.workspace_bytes(_p(), 1 << 31)
+
+
+def test_null_and_status_strings():
+    lib = ws.lib()
+    assert lib.ws_validate_params(None) == _abi.WS_INVALID_ARG
+    assert lib.ws_status_string(0) == b"WS_OK"
+    assert lib.ws_status_string(_abi.WS_BAD_STATE) == b"WS_BAD_STATE"
+    out = C.c_void_p(123)
+    st = lib.ws_grid_init(C.byref(_p()), 10, None, 0, None, 0, None,
+                          C.byref(out))
+    assert st == _abi.WS_INVALID_ARG and out.value is None
+    assert lib.ws_plan_reset(None) == _abi.WS_INVALID_ARG
+    lib.ws_plan_destroy(None)

@@ -1,0 +1,271 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: the FP64 path must match the oracle to 1e-12 relative (max
+error over the output, divided by its largest magnitude); the FP32 path to a
+relative L2 error of 1e-5 over all complex outputs, the target the imaging
+path is built to (FP32 data, FFT and accumulation; FP64 positions, plane
+index and phase).  Integer outputs (dropped-tap counts) must match exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from oracle import wstack as o  # noqa: E402
+import paper_2301_06061_amd as ws  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def rel_l2(got, ref):
+    got = np.asarray(got, np.complex128)
+    ref = np.asarray(ref, np.complex128)
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def rel_max(got, ref):
+    got = np.asarray(got, np.complex128)
+    ref = np.asarray(ref, np.complex128)
+    return float(np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def assert_close(got, ref, fp64, what=""):
+    if fp64:
+        err = rel_max(got, ref)
+        assert err <= TOL64, f"{what}: FP64 rel-max error {err:.3e}"
+    else:
+        err = rel_l2(got, ref)
+        assert err <= TOL32, f"{what}: FP32 rel-L2 error {err:.3e}"
+
+
+def dev(wl):
+    d = torch.device("cuda", 0)
+    uvw = torch.from_numpy(np.ascontiguousarray(wl.uvw)).to(d)
+    vis = torch.from_numpy(np.ascontiguousarray(wl.vis)).to(d)
+    wt = None if wl.weight is None else torch.from_numpy(
+        np.ascontiguousarray(wl.weight)).to(d)
+    return uvw, vis, wt
+
+
+def plan_for(wl, **kw):
+    return ws.WStackPlan.from_workload(wl, **kw)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+CASES = [
+    dict(n=64, nw=3, support=7, m=3000, law="core"),
+    dict(n=32, nw=1, support=15, m=500, law="gauss"),
+    dict(n=128, nw=4, support=9, m=5000, law="core", tile=32),
+    dict(n=64, nv=32, nw=2, support=5, m=2000, law="gauss"),
+    dict(n=64, nw=2, support=1, m=1000, law="gauss"),
+    dict(n=16, nw=5, support=3, m=300, law="core"),
+    dict(n=256, nw=6, support=7, m=20000, law="core"),
+]
+
+
+def _case(c, precision, seed=3):
+    kw = {k: v for k, v in c.items() if k not in ("tile",)}
+    wl = synth.random_case(seed, precision=1 if precision == "fp64" else 0,
+                           **kw)
+    if c["nw"] == 1:
+        wl.w_max = wl.w_min
+    return wl
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_grid_matches_oracle(precision, ci):
+    c = CASES[ci]
+    wl = _case(c, precision)
+    p = o.Params.of(wl)
+    ref, ref_drop = o.grid(p, wl.uvw, wl.vis, wl.weight)
+    plan = plan_for(wl, tile=c.get("tile", 0))
+    uvw, vis, wt = dev(wl)
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    plan.grid(uvw, vis, wt, dropped)
+    got = host(plan.planes)
+    assert_close(got, ref, precision == "fp64", "planes")
+    assert int(dropped.item()) == ref_drop
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(16, 16, 1), (64, 32, 3), (512, 512, 2),
+                                   (32, 4096, 1), (4096, 16, 1)])
+@pytest.mark.parametrize("direction", [1, -1])
+def test_fft_planes_matches_oracle(precision, shape, direction):
+    nu, nv, nw = shape
+    rng = np.random.default_rng(nu + nv + nw)
+    cdt = np.complex128 if precision == "fp64" else np.complex64
+    data = (rng.standard_normal((nw, nv, nu)) +
+            1j * rng.standard_normal((nw, nv, nu))).astype(cdt)
+    p = o.Params(nu, nv, nw, 0.02, 0.02, -1.0, 1.0, 7)
+    plan = ws.WStackPlan(nu, nv, nw, p.fov_l, p.fov_m, -1.0, 1.0, 7,
+                         precision=precision, max_vis=16,
+                         tile=16 if min(nu, nv) < 64 else 0)
+    e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    plan.grid(e, torch.empty(0, dtype=plan.cdtype, device="cuda"))
+    plan.planes.copy_(torch.from_numpy(data))
+    plan.fft(direction)
+    got = host(plan.planes)
+    ref = o.fft_planes(p, data, direction)
+    assert_close(got, ref, precision == "fp64", "fft")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("fov_deg", [1.0, 8.0, 30.0])
+def test_wcorrect_matches_oracle(precision, fov_deg):
+    nu, nv, nw = 64, 32, 5
+    rng = np.random.default_rng(5)
+    cdt = np.complex128 if precision == "fp64" else np.complex64
+    fov = math.radians(fov_deg)
+    p = o.Params(nu, nv, nw, fov, fov * nv / nu, -3.0e4, 5.0e4, 7)
+    data = (rng.standard_normal((nw, nv, nu)) +
+            1j * rng.standard_normal((nw, nv, nu))).astype(cdt)
+    plan = ws.WStackPlan(nu, nv, nw, p.fov_l, p.fov_m, p.w_min, p.w_max, 7,
+                         precision=precision, max_vis=16, tile=16)
+    e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    plan.grid(e, torch.empty(0, dtype=plan.cdtype, device="cuda"))
+    plan.planes.copy_(torch.from_numpy(data))
+    img = plan.new_image()
+    img += 1.0  # accumulation adds to what is there
+    plan.wcorrect(img)
+    ref = o.wcorrect(p, data.astype(np.complex128)) + 1.0
+    assert_close(host(img), ref, precision == "fp64", "wcorrect")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("ci", [0, 2, 3, 5, 6])
+def test_dirty_image_matches_oracle(precision, fused, ci):
+    c = CASES[ci]
+    wl = _case(c, precision, seed=8)
+    p = o.Params.of(wl)
+    ref = o.image(p, wl.uvw, wl.vis, wl.weight)
+    plan = plan_for(wl, tile=c.get("tile", 0))
+    uvw, vis, wt = dev(wl)
+    img = plan.dirty_image(uvw, vis, wt, fused=fused)
+    assert_close(host(img), ref, precision == "fp64", "image")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("real", [True, False])
+@pytest.mark.parametrize("ci", [0, 1, 2, 3, 5])
+def test_degrid_matches_oracle(precision, real, ci):
+    c = CASES[ci]
+    wl = _case(c, precision, seed=9)
+    p = o.Params.of(wl)
+    rng = np.random.default_rng(ci)
+    x = rng.standard_normal((wl.nv, wl.nu))
+    if not real:
+        x = x + 1j * rng.standard_normal((wl.nv, wl.nu))
+    ref = o.degrid(p, x, wl.uvw, wl.weight)
+    plan = plan_for(wl, tile=c.get("tile", 0))
+    uvw, _, wt = dev(wl)
+    xt = torch.from_numpy(x).to("cuda").to(plan.rdtype if real else plan.cdtype)
+    got = host(plan.degrid(xt, uvw, wt))
+    assert_close(got, ref, precision == "fp64", "degrid")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_grid_is_additive_over_calls(precision):
+    wl = _case(CASES[0], precision, seed=4)
+    p = o.Params.of(wl)
+    ref, _ = o.grid(p, wl.uvw, wl.vis, wl.weight)
+    plan = plan_for(wl)
+    uvw, vis, wt = dev(wl)
+    plan.grid(uvw[:1000], vis[:1000], wt[:1000])
+    plan.grid(uvw[1000:], vis[1000:], wt[1000:])
+    assert_close(host(plan.planes), ref, precision == "fp64", "two calls")
+    # a reset starts a new image
+    plan.reset()
+    plan.grid(uvw[:10], vis[:10], wt[:10])
+    ref10, _ = o.grid(p, wl.uvw[:10], wl.vis[:10], wl.weight[:10])
+    assert_close(host(plan.planes), ref10, precision == "fp64", "after reset")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("chunk", [64, 333, 0])
+def test_hot_bin_split_and_merge(precision, chunk):
+    """Every visibility within a few cells of one point: tiles split into
+    many work items whose partial tiles are merged."""
+    rng = np.random.default_rng(12)
+    n, m = 64, 6000
+    fov = math.radians(2.0)
+    xs = 32 + rng.normal(0, 1.5, m)
+    ys = 32 + rng.normal(0, 1.5, m)
+    uvw = np.stack([(xs - 32) / fov, (ys - 32) / fov,
+                    rng.uniform(-10, 10, m)], 1)
+    cdt = np.complex128 if precision == "fp64" else np.complex64
+    vis = (rng.standard_normal(m) + 1j * rng.standard_normal(m)).astype(cdt)
+    wl = synth.Workload(n, n, 2, fov, fov, -10.0, 10.0, 7, 0.0,
+                        1 if precision == "fp64" else 0, uvw, vis, None)
+    p = o.Params.of(wl)
+    ref, _ = o.grid(p, uvw, vis, None)
+    plan = plan_for(wl, chunk=chunk, tile=16)
+    u, v, _ = dev(wl)
+    plan.grid(u, v, None)
+    assert_close(host(plan.planes), ref, precision == "fp64", "hot bin")
+    img = plan.dirty_image(u, v, None)
+    assert_close(host(img), o.image(p, uvw, vis, None),
+                 precision == "fp64", "hot image")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_empty_and_invalid_inputs(precision):
+    wl = _case(CASES[0], precision, seed=6)
+    plan = plan_for(wl)
+    d = torch.device("cuda")
+    e = torch.empty((0, 3), dtype=torch.float64, device=d)
+    ev = torch.empty(0, dtype=plan.cdtype, device=d)
+    img = plan.dirty_image(e, ev)
+    assert float(img.abs().max().item()) == 0.0
+    out = plan.degrid(torch.ones((wl.nv, wl.nu), dtype=plan.rdtype, device=d),
+                      e)
+    assert out.numel() == 0
+    # non-finite and far-off coordinates drop all their taps and touch nothing
+    bad = np.array([[np.nan, 0, 0], [0, np.inf, 0], [0, 0, np.nan],
+                    [1e30, 0, 0], [0.0, 0.0, 0.0]])
+    vals = np.ones(5, dtype=np.complex128 if precision == "fp64"
+                   else np.complex64)
+    p = o.Params.of(wl)
+    ref, ref_drop = o.grid(p, bad, vals, None)
+    dropped = torch.zeros(1, dtype=torch.int64, device=d)
+    plan.reset()
+    plan.grid(torch.from_numpy(bad).to(d), torch.from_numpy(vals).to(d), None,
+              dropped)
+    assert int(dropped.item()) == ref_drop == 4 * 49
+    assert_close(host(plan.planes), ref, precision == "fp64", "bad coords")
+    # too many visibilities for the workspace is an error, not a fault
+    with pytest.raises(ws.WStackError):
+        big = torch.zeros((plan.max_vis + 1, 3), dtype=torch.float64, device=d)
+        plan.grid(big, torch.zeros(plan.max_vis + 1, dtype=plan.cdtype,
+                                   device=d))
+    # gridding onto transformed planes is refused
+    plan.reset()
+    plan.grid(e, ev)
+    plan.fft(+1)
+    with pytest.raises(ws.WStackError):
+        plan.grid(e, ev)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_config1_full_image(precision):
+    wl = synth.config1(precision=1 if precision == "fp64" else 0)
+    p = o.Params.of(wl)
+    ref = o.image(p, wl.uvw, wl.vis, wl.weight)
+    plan = plan_for(wl)
+    uvw, vis, wt = dev(wl)
+    img = host(plan.dirty_image(uvw, vis, wt))
+    assert_close(img, ref, precision == "fp64", "config1")
+    if precision == "fp32":
+        print(f"config1 FP32 rel-L2 {rel_l2(img, ref):.3e}")
