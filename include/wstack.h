@@ -63,13 +63,15 @@ typedef int32_t ws_status;
 #define WS_HIP_ERROR (-4)            /* a HIP runtime call failed */
 #define WS_BAD_STATE (-5)            /* call not allowed in the plan's state */
 
-#define WS_FP32 0 /* complex64 data, FP32 gridding, FFT and accumulation;
-                     FP64 positions, plane index and phase argument */
+#define WS_FP32 0 /* complex64 data and plane stack; FP32 kernel taps, FFT
+                     and screen; FP64 positions, plane index, phase argument
+                     and in-tile sums (FP64 LDS adds, rounded to FP32 once) */
 #define WS_FP64 1 /* complex128 data, everything in FP64 (the paper's
                      precision, Sec. 4.2 memory model) */
 
 /* Imaging geometry and kernel.
- *   nu, nv   grid size, each a power of two in [16, 16384]
+ *   nu, nv   grid size, each a power of two in [16, 16384]; on the FP64
+ *            path nu <= 8192 (one grid row must fit a workgroup's LDS)
  *   nw       number of w-planes, >= 1
  *   fov_l, fov_m  full field of view in radians, > 0, with
  *            (fov_l/2)^2 + (fov_m/2)^2 < 1
@@ -176,6 +178,48 @@ ws_status ws_set_profiling(ws_plan* plan, int32_t enable);
 ws_status ws_kernel_times(ws_plan* plan, int32_t cap, const char** names,
                           double* total_ms, int64_t* launches, int32_t* n,
                           int32_t reset);
+
+/* ---- batches: many independent images in one launch sequence ----------
+ * Many frequency channels or observations, each with its own plan (grid
+ * size, planes, w range, visibility count), imaged together: every plan's
+ * binning kernels, then ONE persistent gridding kernel draining a single
+ * queue that holds the (tile, chunk) work items of all plans, then each
+ * plan's FFT, w-screen and plane sum.  The paper's GPU thread loops over
+ * the channels of one baseline (Sec. 3.4.2); here channels are separate
+ * records of separate plans sharing one gridding launch.  All plans of a
+ * batch share precision, kernel support and device; the batch runs on the
+ * stream of plans[0], which every plan then uses. */
+typedef struct ws_batch ws_batch;
+
+/* Device workspace of a batch of n plans (1 <= n <= 64).  Host only. */
+ws_status ws_batch_workspace_bytes(int32_t n, size_t* work_bytes);
+
+/* Build a batch over n existing plans and a caller-owned, 256-byte aligned
+ * device workspace (copies a small job table into it).  The plans and the
+ * workspace must outlive the batch. */
+ws_status ws_batch_create(int32_t n, ws_plan* const* plans, void* work,
+                          size_t work_bytes, ws_batch** out);
+
+/* One dirty image per plan: images[i] += image of the m[i] visibilities
+ * uvw[i], vis[i], weight[i] (weight may be NULL, or any weight[i] NULL).
+ * The arrays are host arrays of n entries holding device pointers.  The
+ * plans are reset before and after. */
+ws_status ws_batch_image(ws_batch* batch, const int64_t* m,
+                         const double* const* uvw, const void* const* vis,
+                         const float* const* weight, void* const* images);
+
+/* Record ws_batch_image with exactly these arguments into a HIP graph by
+ * stream capture (the batch stream must not be the null stream); nothing
+ * runs until ws_batch_replay.  The buffers must stay allocated; their
+ * contents may change between replays (m[i] and the pointers may not). */
+ws_status ws_batch_capture(ws_batch* batch, const int64_t* m,
+                           const double* const* uvw, const void* const* vis,
+                           const float* const* weight, void* const* images);
+
+/* Launch the captured graph once on the batch stream. */
+ws_status ws_batch_replay(ws_batch* batch);
+
+void ws_batch_destroy(ws_batch* batch);
 
 void ws_plan_destroy(ws_plan* plan);
 const char* ws_status_string(ws_status status);

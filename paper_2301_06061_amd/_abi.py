@@ -60,6 +60,18 @@ _SIGS = {
                                     C.POINTER(C.c_double),
                                     C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int32), C.c_int32]),
+    "ws_batch_workspace_bytes": (C.c_int32, [C.c_int32,
+                                             C.POINTER(C.c_size_t)]),
+    "ws_batch_create": (C.c_int32, [C.c_int32, C.POINTER(_P), _P,
+                                    C.c_size_t, C.POINTER(_P)]),
+    "ws_batch_image": (C.c_int32, [_P, C.POINTER(C.c_int64), C.POINTER(_P),
+                                   C.POINTER(_P), C.POINTER(_P),
+                                   C.POINTER(_P)]),
+    "ws_batch_capture": (C.c_int32, [_P, C.POINTER(C.c_int64),
+                                     C.POINTER(_P), C.POINTER(_P),
+                                     C.POINTER(_P), C.POINTER(_P)]),
+    "ws_batch_replay": (C.c_int32, [_P]),
+    "ws_batch_destroy": (None, [_P]),
     "ws_plan_destroy": (None, [_P]),
     "ws_status_string": (C.c_char_p, [C.c_int32]),
     "ws_last_error": (C.c_char_p, []),

@@ -1,0 +1,126 @@
+"""Autotuner for the gridder's launch parameters.
+
+For a shape class - grid size, plane count, kernel support, precision and
+the visibility count rounded to a half decade - it times the gridding step
+(binning + tile accumulation + merge) on the caller's own data for every
+candidate (tile edge T, records per work item C) and keeps the fastest.
+Results are cached in a JSON file keyed by GPU architecture and shape
+class ($WSTACK_AUTOTUNE_CACHE, default ~/.cache/wstack/autotune.json).
+The kernel support itself is not tuned: it changes the result, so each K
+has its own compiled kernel and its own cache entries.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from .api import WStackPlan
+
+TILES = (32, 64)
+CHUNKS = (1024, 2048, 4096, 8192)
+
+
+def cache_path() -> str:
+    return os.environ.get(
+        "WSTACK_AUTOTUNE_CACHE",
+        os.path.join(os.path.expanduser("~"), ".cache", "wstack",
+                     "autotune.json"))
+
+
+def _arch() -> str:
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def shape_key(nu, nv, nw, support, precision, m) -> str:
+    bucket = 0 if m <= 0 else round(2 * math.log10(m)) / 2
+    return f"{_arch()}|{nu}x{nv}x{nw}|K{support}|{precision}|m1e{bucket:g}"
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(db: dict) -> None:
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def lookup(key: str) -> Optional[Tuple[int, int]]:
+    e = _load().get(key)
+    return None if e is None else (int(e["tile"]), int(e["chunk"]))
+
+
+def _valid_tile(t, wl) -> bool:
+    return t <= min(wl.nu, wl.nv) and t > wl.support - 1
+
+
+def time_grid(plan: WStackPlan, uvw, vis, weight, reps: int = 3) -> float:
+    """Median milliseconds of one gridding call (after one warm-up)."""
+    plan.reset()
+    plan.grid(uvw, vis, weight)
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        plan.reset()
+        a.record()
+        plan.grid(uvw, vis, weight)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    plan.reset()
+    return sorted(times)[len(times) // 2]
+
+
+def tune(wl, uvw, vis, weight=None, precision: str = "fp32",
+         tiles: Sequence[int] = TILES, chunks: Sequence[int] = CHUNKS,
+         reps: int = 3, use_cache: bool = True) -> Tuple[int, int]:
+    """Best (tile, chunk) for this workload's shape class.
+
+    ``wl`` carries the geometry (nu, nv, nw, fov, w range, support, sigma);
+    uvw, vis, weight are the device tensors that will be gridded.
+    """
+    m = int(uvw.shape[0])
+    key = shape_key(wl.nu, wl.nv, wl.nw, wl.support, precision, m)
+    if use_cache:
+        hit = lookup(key)
+        if hit is not None:
+            return hit
+    best = None
+    trials = {}
+    for t in tiles:
+        if not _valid_tile(t, wl):
+            continue
+        for c in chunks:
+            plan = WStackPlan(wl.nu, wl.nv, wl.nw, wl.fov_l, wl.fov_m,
+                              wl.w_min, wl.w_max, wl.support, wl.sigma,
+                              precision, max_vis=max(1, m), tile=t, chunk=c)
+            ms = time_grid(plan, uvw, vis, weight, reps)
+            plan.close()
+            del plan
+            trials[f"T{t}_C{c}"] = ms
+            if best is None or ms < best[2]:
+                best = (t, c, ms)
+    if best is None:
+        return (0, 0)
+    if use_cache:
+        db = _load()
+        db[key] = {"tile": best[0], "chunk": best[1], "ms": best[2],
+                   "trials": trials}
+        _store(db)
+    return best[0], best[1]

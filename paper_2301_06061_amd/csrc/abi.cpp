@@ -34,7 +34,12 @@ bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-constexpr int kMaxN = 4096;
+constexpr int kMaxN = 16384;
+// Largest column length transformed in one pass (whole column blocks in
+// LDS); longer columns use the four-step transform.
+constexpr int kOnePassCols = 4096;
+// Largest row length of the fused row-transform + screen kernels.
+constexpr int kFusedRows = 4096;
 constexpr int kMinN = 16;
 constexpr int kMaxSupport = 15;
 constexpr int64_t kMaxVis = (int64_t(1) << 31) - 1;
@@ -55,7 +60,7 @@ struct Layout {
   // workspace offsets
   size_t o_tw_u, o_tw_v, o_counts, o_sums, o_keyrank, o_cell, o_dxy, o_val,
       o_idx, o_chunks, o_slot, o_counters, o_split, o_extra, o_partials,
-      total;
+      o_scratch, total;
 };
 
 ws_status check_params(const ws_params* p) {
@@ -98,6 +103,10 @@ ws_status check_params(const ws_params* p) {
       return fail(WS_UNSUPPORTED_SIZE, "tile=%d must exceed support-1",
                   p->tile);
   }
+  if (!fft_supported(p->nu, p->precision == WS_FP64 ? 16 : 8))
+    return fail(WS_UNSUPPORTED_SIZE,
+                "nu=%d: a row must fit one workgroup's LDS (FP32 <= 16384, "
+                "FP64 <= 8192)", p->nu);
   if (p->chunk < 0 || p->chunk > (1 << 24))
     return fail(WS_INVALID_ARG, "chunk=%d out of range", p->chunk);
   const int64_t cells = (int64_t)p->nu * p->nv;
@@ -158,6 +167,10 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   L->o_split = take((size_t)(L->max_slots / 2 + 1) * 4);
   L->o_extra = take((size_t)L->max_extra * 8);
   L->o_partials = take((size_t)L->max_slots * L->T * L->T * L->elem);
+  // One plane of scratch for the natural-order output of ws_fft_planes
+  // when columns use the four-step transform.
+  L->o_scratch = take(p->nv > kOnePassCols
+                          ? (size_t)p->nu * p->nv * L->elem : (size_t)0);
   L->total = o;
   return WS_OK;
 }
@@ -314,34 +327,83 @@ ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
 }
 
 template <typename R>
-ws_status grid_impl(ws_plan* pl, int64_t m, const double* uvw, const void* vis,
-                    const float* weight, int64_t* n_dropped) {
+GridJob<R> make_job(ws_plan* pl, int accumulate) {
   const Layout& L = pl->L;
-  uint32_t max_items = 0;
-  WS_TRY(bin_records<R>(pl, m, uvw, vis, weight, 0, n_dropped, &max_items));
-  const int acc = pl->state == kGridded ? 1 : 0;
-  WS_TRY(launch(pl, "grid_tiles", [&] {
-    launch_grid_tiles<R>(pl->g, pl->w<uint32_t>(L.o_counts),
-                         pl->w<uint32_t>(L.o_counters), pl->w<uint2>(L.o_extra),
-                         pl->w<uint32_t>(L.o_chunks),
-                         pl->w<uint32_t>(L.o_slot), pl->w<uint32_t>(L.o_cell),
-                         pl->work + L.o_dxy, pl->work + L.o_val, L.chunk,
-                         pl->planes, pl->work + L.o_partials, acc, max_items,
-                         pl->cus, pl->stream);
-  }));
-  WS_TRY(launch(pl, "grid_merge", [&] {
+  GridJob<R> j;
+  j.g = pl->g;
+  j.pitch = grid_lds_pitch(L.T, pl->p.support);
+  j.offsets = pl->w<uint32_t>(L.o_counts);
+  j.counters = pl->w<uint32_t>(L.o_counters);
+  j.extra = pl->w<uint2>(L.o_extra);
+  j.tile_chunks = pl->w<uint32_t>(L.o_chunks);
+  j.tile_slot = pl->w<uint32_t>(L.o_slot);
+  j.rec_cell = pl->w<uint32_t>(L.o_cell);
+  j.rec_dxy = pl->w<cplx<R>>(L.o_dxy);
+  j.rec_val = pl->w<cplx<R>>(L.o_val);
+  j.chunk = L.chunk;
+  j.planes = static_cast<cplx<R>*>(pl->planes);
+  j.partials = pl->w<cplx<R>>(L.o_partials);
+  j.accumulate = accumulate;
+  return j;
+}
+
+template <typename R>
+ws_status merge_impl(ws_plan* pl, int acc) {
+  const Layout& L = pl->L;
+  return launch(pl, "grid_merge", [&] {
     launch_grid_merge<R>(pl->g, pl->w<uint32_t>(L.o_counters),
                          pl->w<uint32_t>(L.o_split),
                          pl->w<uint32_t>(L.o_chunks),
                          pl->w<uint32_t>(L.o_slot), pl->work + L.o_partials,
                          pl->planes, acc, L.max_slots / 2 + 1, pl->stream);
+  });
+}
+
+template <typename R>
+ws_status grid_impl(ws_plan* pl, int64_t m, const double* uvw, const void* vis,
+                    const float* weight, int64_t* n_dropped) {
+  uint32_t max_items = 0;
+  WS_TRY(bin_records<R>(pl, m, uvw, vis, weight, 0, n_dropped, &max_items));
+  const int acc = pl->state == kGridded ? 1 : 0;
+  const GridJob<R> j = make_job<R>(pl, acc);
+  WS_TRY(launch(pl, "grid_tiles", [&] {
+    launch_grid_tiles<R>(j, max_items, pl->cus, pl->stream);
   }));
+  WS_TRY(merge_impl<R>(pl, acc));
   pl->state = kGridded;
   return WS_OK;
 }
 
+// Column transform of every plane: one pass for columns up to
+// kOnePassCols, else the four-step transform, which leaves the rows in the
+// transposed order described by the returned geometry.
 template <typename R>
-ws_status fft_impl(ws_plan* pl, int sign) {
+ws_status cols_impl(ws_plan* pl, int sign, Geo* gout) {
+  const ws_params& p = pl->p;
+  bool ok = true;
+  Geo g = pl->g;
+  if (p.nv <= kOnePassCols) {
+    WS_TRY(launch(pl, "fft_cols", [&] {
+      ok = launch_fft_cols<R>(pl->planes, p.nv, p.nu, p.nw,
+                              pl->work + pl->L.o_tw_v, sign, pl->stream);
+    }));
+  } else {
+    WS_TRY(launch(pl, "fft_cols4", [&] {
+      ok = launch_fft_cols4<R>(pl->planes, p.nv, p.nu, p.nw,
+                               pl->work + pl->L.o_tw_v, sign, pl->stream);
+    }));
+    int lg = 0;
+    while ((1 << lg) < p.nv) ++lg;
+    g.perm_n1 = 1 << (lg / 2);
+    g.perm_n2 = p.nv / g.perm_n1;
+  }
+  if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no column FFT for nv=%d", p.nv);
+  *gout = g;
+  return WS_OK;
+}
+
+template <typename R>
+ws_status rows_impl(ws_plan* pl, int sign) {
   const ws_params& p = pl->p;
   bool ok = true;
   WS_TRY(launch(pl, "fft_rows", [&] {
@@ -349,29 +411,50 @@ ws_status fft_impl(ws_plan* pl, int sign) {
                             pl->work + pl->L.o_tw_u, sign, pl->stream);
   }));
   if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no row FFT for nu=%d", p.nu);
-  WS_TRY(launch(pl, "fft_cols", [&] {
-    ok = launch_fft_cols<R>(pl->planes, p.nv, p.nu, p.nw,
-                            pl->work + pl->L.o_tw_v, sign, pl->stream);
-  }));
-  if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no column FFT for nv=%d", p.nv);
+  return WS_OK;
+}
+
+template <typename R>
+ws_status fft_impl(ws_plan* pl, int sign) {
+  const ws_params& p = pl->p;
+  WS_TRY(rows_impl<R>(pl, sign));
+  Geo g;
+  WS_TRY(cols_impl<R>(pl, sign, &g));
+  if (g.perm_n1 != 0) {
+    // Natural row order for the caller: each plane through the scratch.
+    const size_t plane = (size_t)p.nu * p.nv * sizeof(cplx<R>);
+    for (int k = 0; k < p.nw; ++k) {
+      unsigned char* pk = static_cast<unsigned char*>(pl->planes) + k * plane;
+      WS_TRY(launch(pl, "unpermute_rows", [&] {
+        launch_unpermute_rows<R>(pk, pl->work + pl->L.o_scratch, g,
+                                 pl->stream);
+        hipMemcpyAsync(pk, pl->work + pl->L.o_scratch, plane,
+                       hipMemcpyDeviceToDevice, pl->stream);
+      }));
+    }
+  }
   return WS_OK;
 }
 
 template <typename R>
 ws_status image_impl(ws_plan* pl, void* image) {
   const ws_params& p = pl->p;
-  bool ok = true;
-  WS_TRY(launch(pl, "fft_cols", [&] {
-    ok = launch_fft_cols<R>(pl->planes, p.nv, p.nu, p.nw,
-                            pl->work + pl->L.o_tw_v, +1, pl->stream);
-  }));
-  if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no column FFT for nv=%d", p.nv);
-  WS_TRY(launch(pl, "row_screen_sum", [&] {
-    ok = launch_row_screen_sum<R>(pl->planes, image, pl->g,
-                                  pl->work + pl->L.o_tw_u, pl->stream);
-  }));
-  if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no fused row FFT for nu=%d", p.nu);
-  return WS_OK;
+  Geo g;
+  WS_TRY(cols_impl<R>(pl, +1, &g));
+  if (g.perm_n1 == 0 && p.nu <= kFusedRows) {
+    bool ok = true;
+    WS_TRY(launch(pl, "row_screen_sum", [&] {
+      ok = launch_row_screen_sum<R>(pl->planes, image, g,
+                                    pl->work + pl->L.o_tw_u, pl->stream);
+    }));
+    if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no fused row FFT for nu=%d",
+                         p.nu);
+    return WS_OK;
+  }
+  WS_TRY(rows_impl<R>(pl, +1));
+  return launch(pl, "wcorrect", [&] {
+    launch_wcorrect<R>(pl->planes, image, g, pl->stream);
+  });
 }
 
 template <typename R>
@@ -380,22 +463,28 @@ ws_status degrid_impl(ws_plan* pl, const void* image, int image_is_real,
                       void* vis_out) {
   const ws_params& p = pl->p;
   const Layout& L = pl->L;
-  bool ok = true;
-  WS_TRY(launch(pl, "screen_row_bcast", [&] {
-    ok = launch_screen_row_bcast<R>(image, image_is_real, pl->planes, pl->g,
-                                    pl->work + L.o_tw_u, pl->stream);
-  }));
-  if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no fused row FFT for nu=%d", p.nu);
-  WS_TRY(launch(pl, "fft_cols", [&] {
-    ok = launch_fft_cols<R>(pl->planes, p.nv, p.nu, p.nw,
-                            pl->work + L.o_tw_v, -1, pl->stream);
-  }));
-  if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no column FFT for nv=%d", p.nv);
+  Geo g = pl->g;
+  if (p.nv <= kOnePassCols && p.nu <= kFusedRows) {
+    bool ok = true;
+    WS_TRY(launch(pl, "screen_row_bcast", [&] {
+      ok = launch_screen_row_bcast<R>(image, image_is_real, pl->planes,
+                                      pl->g, pl->work + L.o_tw_u, pl->stream);
+    }));
+    if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no fused row FFT for nu=%d",
+                         p.nu);
+  } else {
+    WS_TRY(launch(pl, "screen_bcast", [&] {
+      launch_screen_bcast<R>(image, image_is_real, pl->planes, pl->g,
+                             pl->stream);
+    }));
+    WS_TRY(rows_impl<R>(pl, -1));
+  }
+  WS_TRY(cols_impl<R>(pl, -1, &g));
   if (m == 0) return WS_OK;
   uint32_t max_items = 0;
   WS_TRY(bin_records<R>(pl, m, uvw, nullptr, weight, 1, nullptr, &max_items));
   WS_TRY(launch(pl, "degrid_tiles", [&] {
-    launch_degrid_tiles<R>(pl->g, pl->w<uint32_t>(L.o_counts),
+    launch_degrid_tiles<R>(g, pl->w<uint32_t>(L.o_counts),
                            pl->w<uint32_t>(L.o_counters),
                            pl->w<uint2>(L.o_extra), pl->planes,
                            pl->w<uint32_t>(L.o_cell), pl->work + L.o_dxy,
@@ -427,6 +516,85 @@ ws_status check_vis_args(ws_plan* pl, int64_t m, const double* uvw,
   if (!aligned(uvw, 8) || !aligned(weight, 4))
     return fail(WS_INVALID_ARG, "misaligned uvw or weight");
   return WS_OK;
+}
+
+}  // namespace
+
+struct ws_batch {
+  int n;
+  std::vector<ws_plan*> plans;
+  unsigned char* work;
+  int precision;
+  int K;
+  size_t lds;
+  hipStream_t stream;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+namespace {
+
+size_t batch_jobs_bytes(int n) {
+  return align_up((size_t)n * sizeof(GridJob<double>), 256);
+}
+
+template <typename R>
+ws_status batch_image_impl(ws_batch* b, const int64_t* m,
+                           const double* const* uvw, const void* const* vis,
+                           const float* const* weight, void* const* images) {
+  uint32_t items = 0;
+  for (int i = 0; i < b->n; ++i) {
+    ws_plan* pl = b->plans[i];
+    pl->stream = b->stream;
+    pl->state = kEmpty;
+    uint32_t mi = 0;
+    WS_TRY(bin_records<R>(pl, m[i], uvw[i], vis[i], weight ? weight[i] : nullptr,
+                          0, nullptr, &mi));
+    items += mi;
+  }
+  ws_plan* p0 = b->plans[0];
+  uint32_t* queue = reinterpret_cast<uint32_t*>(b->work + batch_jobs_bytes(b->n));
+  WS_TRY(launch(p0, "zero_counts", [&] { launch_zero_u32(queue, 1, b->stream); }));
+  WS_TRY(launch(p0, "grid_batch", [&] {
+    launch_grid_batch<R>(reinterpret_cast<const GridJob<R>*>(b->work), b->n,
+                         b->K, b->lds, queue, items, p0->cus, b->stream);
+  }));
+  for (int i = 0; i < b->n; ++i) {
+    ws_plan* pl = b->plans[i];
+    WS_TRY(merge_impl<R>(pl, 0));
+    pl->state = kGridded;
+    ws_status st = image_impl<R>(pl, images[i]);
+    pl->state = kEmpty;
+    WS_TRY(st);
+  }
+  return WS_OK;
+}
+
+ws_status check_batch_args(ws_batch* b, const int64_t* m,
+                           const double* const* uvw, const void* const* vis,
+                           void* const* images) {
+  if (b == nullptr) return fail(WS_INVALID_ARG, "batch is NULL");
+  if (m == nullptr || uvw == nullptr || vis == nullptr || images == nullptr)
+    return fail(WS_INVALID_ARG, "batch argument arrays must not be NULL");
+  for (int i = 0; i < b->n; ++i) {
+    ws_plan* pl = b->plans[i];
+    if (m[i] < 0 || m[i] > pl->max_vis)
+      return fail(WS_WORKSPACE_TOO_SMALL, "plan %d: m=%lld outside [0, %lld]",
+                  i, (long long)m[i], (long long)pl->max_vis);
+    if (m[i] > 0 && (uvw[i] == nullptr || vis[i] == nullptr))
+      return fail(WS_INVALID_ARG, "plan %d: uvw or vis is NULL", i);
+    if (images[i] == nullptr)
+      return fail(WS_INVALID_ARG, "plan %d: image is NULL", i);
+  }
+  return WS_OK;
+}
+
+ws_status run_batch(ws_batch* b, const int64_t* m, const double* const* uvw,
+                    const void* const* vis, const float* const* weight,
+                    void* const* images) {
+  return b->precision == WS_FP64
+             ? batch_image_impl<double>(b, m, uvw, vis, weight, images)
+             : batch_image_impl<float>(b, m, uvw, vis, weight, images);
 }
 
 }  // namespace
@@ -642,6 +810,143 @@ ws_status ws_kernel_times(ws_plan* plan, int32_t cap, const char** names,
     for (auto& v : plan->launches) v = 0;
   }
   return WS_OK;
+}
+
+ws_status ws_batch_workspace_bytes(int32_t n, size_t* work_bytes) {
+  if (n < 1 || n > kMaxBatch)
+    return fail(WS_INVALID_ARG, "n=%d: a batch holds 1..%d plans", n,
+                kMaxBatch);
+  if (work_bytes) *work_bytes = batch_jobs_bytes(n) + 256;
+  return WS_OK;
+}
+
+ws_status ws_batch_create(int32_t n, ws_plan* const* plans, void* work,
+                          size_t work_bytes, ws_batch** out) {
+  if (out == nullptr) return fail(WS_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  size_t need = 0;
+  WS_TRY(ws_batch_workspace_bytes(n, &need));
+  if (plans == nullptr || work == nullptr)
+    return fail(WS_INVALID_ARG, "plans or work is NULL");
+  if (work_bytes < need)
+    return fail(WS_WORKSPACE_TOO_SMALL, "work: %zu bytes < %zu needed",
+                work_bytes, need);
+  if (!aligned(work, 256))
+    return fail(WS_INVALID_ARG, "work must be 256-byte aligned");
+  for (int i = 0; i < n; ++i) {
+    if (plans[i] == nullptr) return fail(WS_INVALID_ARG, "plan %d is NULL", i);
+    if (plans[i]->p.precision != plans[0]->p.precision ||
+        plans[i]->p.support != plans[0]->p.support ||
+        plans[i]->device != plans[0]->device)
+      return fail(WS_INVALID_ARG,
+                  "plan %d: all plans of a batch share precision, support "
+                  "and device", i);
+    for (int j2 = 0; j2 < i; ++j2)
+      if (plans[j2] == plans[i])
+        return fail(WS_INVALID_ARG, "plan %d appears twice", i);
+  }
+  WS_TRY(check_plan(plans[0]));
+  ws_batch* b = new (std::nothrow) ws_batch();
+  if (b == nullptr) return fail(WS_INVALID_ARG, "out of host memory");
+  b->n = n;
+  b->plans.assign(plans, plans + n);
+  b->work = static_cast<unsigned char*>(work);
+  b->precision = plans[0]->p.precision;
+  b->K = plans[0]->p.support;
+  b->stream = plans[0]->stream;
+  b->graph = nullptr;
+  b->exec = nullptr;
+  b->lds = 0;
+  std::vector<unsigned char> host(batch_jobs_bytes(n), 0);
+  for (int i = 0; i < n; ++i) {
+    const size_t lds = (size_t)2 * plans[i]->L.T *
+                       grid_lds_pitch(plans[i]->L.T, b->K) * sizeof(double);
+    if (lds > b->lds) b->lds = lds;
+    if (b->precision == WS_FP64) {
+      const GridJob<double> j = make_job<double>(plans[i], 0);
+      std::memcpy(host.data() + i * sizeof(GridJob<double>), &j, sizeof(j));
+    } else {
+      const GridJob<float> j = make_job<float>(plans[i], 0);
+      std::memcpy(host.data() + i * sizeof(GridJob<float>), &j, sizeof(j));
+    }
+  }
+  if (hipMemcpy(b->work, host.data(), host.size(), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    delete b;
+    return fail(WS_HIP_ERROR, "copying the batch job table failed");
+  }
+  *out = b;
+  return WS_OK;
+}
+
+ws_status ws_batch_image(ws_batch* b, const int64_t* m,
+                         const double* const* uvw, const void* const* vis,
+                         const float* const* weight, void* const* images) {
+  WS_TRY(check_batch_args(b, m, uvw, vis, images));
+  WS_TRY(check_plan(b->plans[0]));
+  return run_batch(b, m, uvw, vis, weight, images);
+}
+
+ws_status ws_batch_capture(ws_batch* b, const int64_t* m,
+                           const double* const* uvw, const void* const* vis,
+                           const float* const* weight, void* const* images) {
+  WS_TRY(check_batch_args(b, m, uvw, vis, images));
+  WS_TRY(check_plan(b->plans[0]));
+  if (b->stream == nullptr)
+    return fail(WS_BAD_STATE, "capture needs a non-null stream");
+  if (b->exec != nullptr) {
+    hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (b->graph != nullptr) {
+    hipGraphDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  std::vector<bool> prof(b->n);
+  for (int i = 0; i < b->n; ++i) {
+    prof[i] = b->plans[i]->profile;
+    b->plans[i]->profile = false;  // no event records inside the graph
+  }
+  if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) !=
+      hipSuccess)
+    return fail(WS_HIP_ERROR, "hipStreamBeginCapture failed");
+  ws_status st = run_batch(b, m, uvw, vis, weight, images);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &g);
+  for (int i = 0; i < b->n; ++i) b->plans[i]->profile = prof[i];
+  if (st != WS_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess || g == nullptr)
+    return fail(WS_HIP_ERROR, "hipStreamEndCapture failed: %s",
+                hipGetErrorString(e));
+  if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(g);
+    b->exec = nullptr;
+    return fail(WS_HIP_ERROR, "hipGraphInstantiate failed");
+  }
+  b->graph = g;
+  return WS_OK;
+}
+
+ws_status ws_batch_replay(ws_batch* b) {
+  if (b == nullptr) return fail(WS_INVALID_ARG, "batch is NULL");
+  if (b->exec == nullptr)
+    return fail(WS_BAD_STATE, "nothing captured: call ws_batch_capture");
+  WS_TRY(check_plan(b->plans[0]));
+  const hipError_t e = hipGraphLaunch(b->exec, b->stream);
+  if (e != hipSuccess)
+    return fail(WS_HIP_ERROR, "hipGraphLaunch failed: %s",
+                hipGetErrorString(e));
+  return WS_OK;
+}
+
+void ws_batch_destroy(ws_batch* b) {
+  if (b == nullptr) return;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  delete b;
 }
 
 void ws_plan_destroy(ws_plan* plan) {

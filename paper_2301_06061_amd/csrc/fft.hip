@@ -105,6 +105,22 @@ __device__ __forceinline__ Twiddles<R> load_twiddles(cplx<R>* s_lo,
   return Twiddles<R>{s_lo, s_hi};
 }
 
+// Tables of a length-n sub-transform inside a length-nfull table
+// (W_n^x = W_nfull^(x * nfull / n)), for the two steps of a four-step
+// transform.
+template <typename R>
+__device__ __forceinline__ Twiddles<R> load_twiddles_sub(cplx<R>* s_lo,
+                                                         cplx<R>* s_hi,
+                                                         const cplx<R>* tw,
+                                                         int n, int nfull) {
+  const int stride = nfull / n;
+  for (int i = threadIdx.x; i < kTwLo; i += blockDim.x)
+    s_lo[i] = tw[((i % n) * stride) & (nfull - 1)];
+  for (int i = threadIdx.x; i < (n + kTwLo - 1) / kTwLo; i += blockDim.x)
+    s_hi[i] = tw[(i * kTwLo * stride) & (nfull - 1)];
+  return Twiddles<R>{s_lo, s_hi};
+}
+
 // LDS slot of line element e: one padding slot after every 8 elements, so
 // that the strided stores of the first stages hit distinct banks.
 __device__ __forceinline__ constexpr int lslot(int e) { return e + (e >> 3); }
@@ -240,6 +256,95 @@ __global__ __launch_bounds__(NT) void k_fft_cols(cplx<R>* data, int ncols,
   fft_line<R, LOGN, BC, NT>(lds, ld, st, twl, s);
 }
 
+// ---- four-step column transform for long columns (N = N1 * N2) ---------
+//
+// Step A: for each n2, the length-N1 transform over rows n1*N2 + n2, times
+// W_N^(n2 k1), written back to row k1*N2 + n2.  Step B: for each k1, the
+// length-N2 transform over the contiguous rows k1*N2 + n2; output k2 is
+// frequency q = k1 + N1 k2 and is written back in place to row k1*N2 + k2.
+// Each step reads and writes the stack once with 16-column (128- or
+// 256-byte) row segments; the result has its rows in the transposed order
+// that stack_row() undoes.
+
+template <typename R>
+__device__ __forceinline__ cplx<R> twiddle_full(const cplx<R>* tw, int idx,
+                                                R s) {
+  const cplx<R> w = tw[idx];
+  return {w.re, s * w.im};
+}
+
+template <typename R, int LOG1, int LOG2, int BC, int NT>
+__global__ __launch_bounds__(NT) void k_fft_colA(cplx<R>* data, int ncols,
+                                                 int nplanes,
+                                                 const cplx<R>* __restrict__ tw,
+                                                 R s) {
+  constexpr int N1 = 1 << LOG1, N2 = 1 << LOG2, N = N1 * N2;
+  __shared__ cplx<R> lds[lds_line<N1>(BC)];
+  __shared__ cplx<R> s_lo[kTwLo], s_hi[(N1 + kTwLo - 1) / kTwLo];
+  const int ncb = ncols / BC;
+  const int nb = ncb * N2 * nplanes;
+  const int per_xcd = (nb + 7) / 8;
+  const int L = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (L >= nb) return;
+  const int cb = L % ncb;
+  const int rest = L / ncb;
+  const int n2 = rest % N2;
+  const int plane = rest / N2;
+  cplx<R>* base = data + (size_t)plane * N * ncols + (size_t)cb * BC;
+  const Twiddles<R> twl = load_twiddles_sub(s_lo, s_hi, tw, N1, N);
+  __syncthreads();
+  auto ld = [&](int e, int c, int, int) {
+    const int row = e * N2 + n2;
+    return checker(base[(size_t)row * ncols + c], row);
+  };
+  auto st = [&](int e, int c, int, int, cplx<R> v) {
+    const int row = e * N2 + n2;
+    base[(size_t)row * ncols + c] =
+        cmul(v, twiddle_full(tw, (n2 * e) & (N - 1), s));
+  };
+  fft_line<R, LOG1, BC, NT>(lds, ld, st, twl, s);
+}
+
+template <typename R, int LOG1, int LOG2, int BC, int NT>
+__global__ __launch_bounds__(NT) void k_fft_colB(cplx<R>* data, int ncols,
+                                                 int nplanes,
+                                                 const cplx<R>* __restrict__ tw,
+                                                 R s) {
+  constexpr int N1 = 1 << LOG1, N2 = 1 << LOG2, N = N1 * N2;
+  __shared__ cplx<R> lds[lds_line<N2>(BC)];
+  __shared__ cplx<R> s_lo[kTwLo], s_hi[(N2 + kTwLo - 1) / kTwLo];
+  const int ncb = ncols / BC;
+  const int nb = ncb * N1 * nplanes;
+  const int per_xcd = (nb + 7) / 8;
+  const int L = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (L >= nb) return;
+  const int cb = L % ncb;
+  const int rest = L / ncb;
+  const int k1 = rest % N1;
+  const int plane = rest / N1;
+  cplx<R>* base = data + (size_t)plane * N * ncols + (size_t)k1 * N2 * ncols +
+                  (size_t)cb * BC;
+  const Twiddles<R> twl = load_twiddles_sub(s_lo, s_hi, tw, N2, N);
+  __syncthreads();
+  auto ld = [&](int e, int c, int, int) { return base[(size_t)e * ncols + c]; };
+  auto st = [&](int e, int c, int, int, cplx<R> v) {
+    base[(size_t)e * ncols + c] = checker(v, k1 + N1 * e);
+  };
+  fft_line<R, LOG2, BC, NT>(lds, ld, st, twl, s);
+}
+
+// Undo the transposed row order of a four-step column transform: copy row
+// r of the plane to row q(r) of the scratch plane.
+template <typename R>
+__global__ __launch_bounds__(256) void k_unpermute_rows(
+    const cplx<R>* __restrict__ src, cplx<R>* __restrict__ dst, Geo g) {
+  const int r = blockIdx.y;
+  const int q = stack_freq(g, r);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.nu;
+       i += gridDim.x * blockDim.x)
+    dst[(size_t)q * g.nu + i] = src[(size_t)r * g.nu + i];
+}
+
 // ---- w-screen -------------------------------------------------------------
 
 // exp(2 pi i a) for a phase a in turns, reduced to [-1/2, 1/2] in FP64.
@@ -283,8 +388,9 @@ __global__ __launch_bounds__(256) void k_wcorrect(const cplx<R>* __restrict__ F,
   cplx<double> ph, step;
   screen_seed(g, p, q, false, ph, step);
   cplx<R> acc = {(R)0, (R)0};
+  const int64_t src = (int64_t)stack_row(g, q) * g.nu + p;
   for (int k = 0; k < g.nw; ++k) {
-    const cplx<R> f = F[(size_t)k * npix + pix];
+    const cplx<R> f = F[(size_t)k * npix + src];
     const cplx<R> w = {(R)ph.re, (R)ph.im};
     acc = cadd(acc, cmul(f, w));
     ph = cmul(ph, step);
@@ -316,9 +422,25 @@ __global__ __launch_bounds__(NT) void k_row_screen_sum(
       if (NB % NT == 0 || threadIdx.x + it * NT < NB)
         screen_seed(g, p, q, false, ph[it][r], step[it][r]);
     }
-  for (int k = 0; k < g.nw; ++k) {
+  // Row q of plane k + 1 is loaded into registers while plane k is being
+  // transformed, so the HBM reads overlap the LDS stages.
+  using F0 = Stage<R, LOGN, 1, NT, 0>;
+  constexpr int IT0 = F0::IT, RAD0 = F0::RAD, NB0 = F0::NB;
+  cplx<R> cur[IT0][RAD0], nxt[IT0][RAD0];
+  auto fetch = [&](int k, cplx<R> (&buf)[IT0][RAD0]) {
     const cplx<R>* line = planes + ((size_t)k * g.nv + q) * N;
-    auto ld = [&](int e, int, int, int) { return checker(line[e], e); };
+#pragma unroll
+    for (int it = 0; it < IT0; ++it)
+#pragma unroll
+      for (int r = 0; r < RAD0; ++r) {
+        const int j = threadIdx.x + it * NT;
+        if (NB0 % NT == 0 || j < NB0) buf[it][r] = line[j + r * NB0];
+      }
+  };
+  fetch(0, cur);
+  for (int k = 0; k < g.nw; ++k) {
+    if (k + 1 < g.nw) fetch(k + 1, nxt);
+    auto ld = [&](int e, int, int it, int r) { return checker(cur[it][r], e); };
     auto st = [&](int e, int, int it, int r, cplx<R> v) {
       v = checker(v, e);
       const cplx<R> w = {(R)ph[it][r].re, (R)ph[it][r].im};
@@ -326,6 +448,10 @@ __global__ __launch_bounds__(NT) void k_row_screen_sum(
       ph[it][r] = cmul(ph[it][r], step[it][r]);
     };
     fft_line<R, LOGN, 1, NT>(lds, ld, st, twl, (R)1);
+#pragma unroll
+    for (int it = 0; it < IT0; ++it)
+#pragma unroll
+      for (int r = 0; r < RAD0; ++r) cur[it][r] = nxt[it][r];
   }
   cplx<R>* out = img + (size_t)q * N;
 #pragma unroll
@@ -385,6 +511,27 @@ __global__ __launch_bounds__(NT) void k_screen_row_bcast(
   }
 }
 
+// Degridding, any grid size: plane k = image * conj(screen_k), natural
+// row order, one pixel per thread across all planes.
+template <typename R>
+__global__ __launch_bounds__(256) void k_screen_bcast(
+    const void* __restrict__ img, int img_real, cplx<R>* __restrict__ planes,
+    Geo g) {
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t npix = (int64_t)g.nu * g.nv;
+  if (pix >= npix) return;
+  const int q = (int)(pix / g.nu), p = (int)(pix - (int64_t)q * g.nu);
+  cplx<R> x = {(R)0, (R)0};
+  if (img_real) x.re = reinterpret_cast<const R*>(img)[pix];
+  else x = reinterpret_cast<const cplx<R>*>(img)[pix];
+  cplx<double> ph, step;
+  screen_seed(g, p, q, true, ph, step);
+  for (int k = 0; k < g.nw; ++k) {
+    planes[(size_t)k * npix + pix] = cmul(x, cplx<R>{(R)ph.re, (R)ph.im});
+    ph = cmul(ph, step);
+  }
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_fill_zero(cplx<R>* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -413,44 +560,93 @@ constexpr int row_threads(int logn) {
   return (1 << logn) / 8 < 64 ? 64 : ((1 << logn) / 8 > 512 ? 512 : (1 << logn) / 8);
 }
 
+// A whole line of 2^LOGN elements of type R fits one workgroup's LDS.
 template <typename R, int LOGN>
-void rows_t(cplx<R>* data, int64_t nrows, const cplx<R>* tw, R s,
-            hipStream_t st) {
-  constexpr int NT = row_threads(LOGN);
-  hipLaunchKernelGGL((k_fft_rows<R, LOGN, NT>), dim3((unsigned)nrows),
-                     dim3(NT), 0, st, data, nrows, tw, s);
+constexpr bool line_fits() {
+  return lds_line<(1 << LOGN)>(1) * (int)sizeof(cplx<R>) <= 150 * 1024;
 }
 
 template <typename R, int LOGN>
-void cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
+bool rows_t(cplx<R>* data, int64_t nrows, const cplx<R>* tw, R s,
             hipStream_t st) {
+  if constexpr (line_fits<R, LOGN>()) {
+    constexpr int NT = row_threads(LOGN);
+    hipLaunchKernelGGL((k_fft_rows<R, LOGN, NT>), dim3((unsigned)nrows),
+                       dim3(NT), 0, st, data, nrows, tw, s);
+    return true;
+  } else {
+    return false;
+  }
+}
+
+template <typename R, int LOGN>
+bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
+            hipStream_t st) {
+  if constexpr (LOGN > 12) {
+    return false;
+  } else {
   constexpr int N = 1 << LOGN;
   constexpr int ELEM = sizeof(cplx<R>);
   // Widest column block (<= 16) whose padded N x BC tile fits 150 KiB of
   // LDS (the twiddle tables take the rest).
   constexpr int BCMAX = (150 * 1024) / (lds_line<N>(1) * ELEM);
   constexpr int BC = BCMAX >= 16 ? 16 : (BCMAX >= 8 ? 8 : (BCMAX >= 4 ? 4 : (BCMAX >= 2 ? 2 : 1)));
-  constexpr int NT = (N * BC) / 16 < 64 ? 64 : ((N * BC) / 16 > 512 ? 512 : (N * BC) / 16);
+  constexpr int NT = (N * BC) / 8 < 64 ? 64 : ((N * BC) / 8 > 1024 ? 1024 : (N * BC) / 8);
   const int nb = (ncols / BC) * nplanes;
   const int grid = ((nb + 7) / 8) * 8;
   hipLaunchKernelGGL((k_fft_cols<R, LOGN, BC, NT>), dim3(grid), dim3(NT), 0,
                      st, data, ncols, nplanes, tw, s);
+  return true;
+  }
 }
 
 template <typename R, int LOGN>
-void row_screen_t(const cplx<R>* planes, cplx<R>* img, const Geo& g,
+bool cols4_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
+             hipStream_t st) {
+  if constexpr (LOGN < 6) {
+    return false;
+  } else {
+    constexpr int LOG1 = LOGN / 2, LOG2 = LOGN - LOG1;
+    constexpr int BC = 16;
+    constexpr int NTA = ((1 << LOG1) * BC) / 8;
+    constexpr int NTB = ((1 << LOG2) * BC) / 8;
+    const int ncb = ncols / BC;
+    const int nba = ncb * (1 << LOG2) * nplanes;
+    const int nbb = ncb * (1 << LOG1) * nplanes;
+    hipLaunchKernelGGL((k_fft_colA<R, LOG1, LOG2, BC, NTA>),
+                       dim3(((nba + 7) / 8) * 8), dim3(NTA), 0, st, data,
+                       ncols, nplanes, tw, s);
+    hipLaunchKernelGGL((k_fft_colB<R, LOG1, LOG2, BC, NTB>),
+                       dim3(((nbb + 7) / 8) * 8), dim3(NTB), 0, st, data,
+                       ncols, nplanes, tw, s);
+    return true;
+  }
+}
+
+template <typename R, int LOGN>
+bool row_screen_t(const cplx<R>* planes, cplx<R>* img, const Geo& g,
                   const cplx<R>* tw, hipStream_t st) {
-  constexpr int NT = row_threads(LOGN);
-  hipLaunchKernelGGL((k_row_screen_sum<R, LOGN, NT>), dim3(g.nv), dim3(NT), 0,
-                     st, planes, img, g, tw);
+  if constexpr (LOGN > 12) {
+    return false;
+  } else {
+    constexpr int NT = row_threads(LOGN);
+    hipLaunchKernelGGL((k_row_screen_sum<R, LOGN, NT>), dim3(g.nv), dim3(NT),
+                       0, st, planes, img, g, tw);
+    return true;
+  }
 }
 
 template <typename R, int LOGN>
-void screen_bcast_t(const void* img, int img_real, cplx<R>* planes,
+bool screen_bcast_t(const void* img, int img_real, cplx<R>* planes,
                     const Geo& g, const cplx<R>* tw, hipStream_t st) {
-  constexpr int NT = row_threads(LOGN);
-  hipLaunchKernelGGL((k_screen_row_bcast<R, LOGN, NT>), dim3(g.nv), dim3(NT),
-                     0, st, img, img_real, planes, g, tw);
+  if constexpr (LOGN > 12) {
+    return false;
+  } else {
+    constexpr int NT = row_threads(LOGN);
+    hipLaunchKernelGGL((k_screen_row_bcast<R, LOGN, NT>), dim3(g.nv),
+                       dim3(NT), 0, st, img, img_real, planes, g, tw);
+    return true;
+  }
 }
 
 int ilog2(int n) {
@@ -470,50 +666,84 @@ int ilog2(int n) {
     case 10: { constexpr int LG = 10; CALL; } break;                       \
     case 11: { constexpr int LG = 11; CALL; } break;                       \
     case 12: { constexpr int LG = 12; CALL; } break;                       \
+    case 13: { constexpr int LG = 13; CALL; } break;                       \
+    case 14: { constexpr int LG = 14; CALL; } break;                       \
     default: return false;                                                 \
   }
 
 }  // namespace
 
 bool fft_supported(int n, int elem_bytes) {
-  (void)elem_bytes;
-  return n >= 16 && n <= 4096 && (n & (n - 1)) == 0;
+  // Rows must fit one workgroup's LDS (150 KiB with padding).
+  return n >= 16 && (n & (n - 1)) == 0 && (size_t)(n + n / 8) * elem_bytes <= 150 * 1024;
 }
 
 template <typename R>
 bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw, int sign,
                      hipStream_t st) {
   const int lg = ilog2(n);
-  WS_LOGN_SWITCH(lg, (rows_t<R, LG>((cplx<R>*)data, nrows, (const cplx<R>*)tw,
-                                    (R)sign, st)));
-  return true;
+  bool ok = false;
+  WS_LOGN_SWITCH(lg, (ok = rows_t<R, LG>((cplx<R>*)data, nrows,
+                                         (const cplx<R>*)tw, (R)sign, st)));
+  return ok;
 }
 
 template <typename R>
 bool launch_fft_cols(void* data, int nrows, int ncols, int nplanes,
                      const void* tw, int sign, hipStream_t st) {
   const int lg = ilog2(nrows);
-  WS_LOGN_SWITCH(lg, (cols_t<R, LG>((cplx<R>*)data, ncols, nplanes,
-                                    (const cplx<R>*)tw, (R)sign, st)));
-  return true;
+  bool ok = false;
+  WS_LOGN_SWITCH(lg, (ok = cols_t<R, LG>((cplx<R>*)data, ncols, nplanes,
+                                         (const cplx<R>*)tw, (R)sign, st)));
+  return ok;
 }
 
 template <typename R>
 bool launch_row_screen_sum(const void* planes, void* img, const Geo& g,
                            const void* tw_u, hipStream_t st) {
   const int lg = ilog2(g.nu);
-  WS_LOGN_SWITCH(lg, (row_screen_t<R, LG>((const cplx<R>*)planes, (cplx<R>*)img,
-                                          g, (const cplx<R>*)tw_u, st)));
-  return true;
+  bool ok = false;
+  WS_LOGN_SWITCH(lg, (ok = row_screen_t<R, LG>((const cplx<R>*)planes,
+                                               (cplx<R>*)img, g,
+                                               (const cplx<R>*)tw_u, st)));
+  return ok;
 }
 
 template <typename R>
 bool launch_screen_row_bcast(const void* img, int img_real, void* planes,
                              const Geo& g, const void* tw_u, hipStream_t st) {
   const int lg = ilog2(g.nu);
-  WS_LOGN_SWITCH(lg, (screen_bcast_t<R, LG>(img, img_real, (cplx<R>*)planes, g,
-                                            (const cplx<R>*)tw_u, st)));
-  return true;
+  bool ok = false;
+  WS_LOGN_SWITCH(lg, (ok = screen_bcast_t<R, LG>(img, img_real,
+                                                 (cplx<R>*)planes, g,
+                                                 (const cplx<R>*)tw_u, st)));
+  return ok;
+}
+
+template <typename R>
+bool launch_fft_cols4(void* data, int nrows, int ncols, int nplanes,
+                      const void* tw, int sign, hipStream_t st) {
+  const int lg = ilog2(nrows);
+  bool ok = false;
+  WS_LOGN_SWITCH(lg, (ok = cols4_t<R, LG>((cplx<R>*)data, ncols, nplanes,
+                                          (const cplx<R>*)tw, (R)sign, st)));
+  return ok;
+}
+
+template <typename R>
+void launch_unpermute_rows(const void* src, void* dst, const Geo& g,
+                           hipStream_t st) {
+  const int bx = (g.nu + 255) / 256 < 16 ? (g.nu + 255) / 256 : 16;
+  hipLaunchKernelGGL(k_unpermute_rows<R>, dim3(bx, g.nv), dim3(256), 0, st,
+                     (const cplx<R>*)src, (cplx<R>*)dst, g);
+}
+
+template <typename R>
+void launch_screen_bcast(const void* img, int img_real, void* planes,
+                         const Geo& g, hipStream_t st) {
+  const int64_t npix = (int64_t)g.nu * g.nv;
+  hipLaunchKernelGGL(k_screen_bcast<R>, dim3((unsigned)((npix + 255) / 256)),
+                     dim3(256), 0, st, img, img_real, (cplx<R>*)planes, g);
 }
 
 template <typename R>
@@ -558,6 +788,12 @@ void launch_twiddles(void* tw, int n, hipStream_t st) {
                                            hipStream_t);                     \
   template void launch_wcorrect<R>(const void*, void*, const Geo&,           \
                                    hipStream_t);                             \
+  template bool launch_fft_cols4<R>(void*, int, int, int, const void*, int,  \
+                                    hipStream_t);                            \
+  template void launch_unpermute_rows<R>(const void*, void*, const Geo&,     \
+                                         hipStream_t);                       \
+  template void launch_screen_bcast<R>(const void*, int, void*, const Geo&,  \
+                                       hipStream_t);                         \
   template void launch_fill_zero<R>(void*, int64_t, hipStream_t);           \
   template void launch_twiddles<R>(void*, int, hipStream_t);
 WS_INST(float)

@@ -139,32 +139,54 @@ __device__ __forceinline__ uint32_t bcast_u(uint32_t x, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
 }
 
-// Gridding of one item.  Each wavefront loads 64 records with one coalesced
+// Gridding of one item (tile t, chunk c) of one job; called by all threads
+// of the workgroup.  Each wavefront loads 64 records with one coalesced
 // load per field, then takes them one at a time: its lanes cover the K*K
 // taps of the visibility (in ceil(K*K/64) rounds), so the LDS adds of one
 // instruction hit K*K distinct cells - no two lanes ever add to the same
 // accumulator at once, even where many visibilities share a cell.
 template <typename R, int K>
-__global__ __launch_bounds__(256) void k_grid_tiles(
-    Geo g, int pitch, const uint32_t* __restrict__ offsets,
-    uint32_t* __restrict__ counters, const uint2* __restrict__ extra,
-    const uint32_t* __restrict__ tile_chunks,
-    const uint32_t* __restrict__ tile_slot,
-    const uint32_t* __restrict__ rec_cell, const cplx<R>* __restrict__ rec_dxy,
-    const cplx<R>* __restrict__ rec_val, uint32_t chunk,
-    cplx<R>* __restrict__ planes, cplx<R>* __restrict__ partials,
-    int accumulate) {
+__device__ __forceinline__ void grid_item(const GridJob<R>& j, int t,
+                                          uint32_t c, double* s_re,
+                                          double* s_im) {
   constexpr int H = (K - 1) / 2;
   constexpr int KK = K * K;
   constexpr int ROUNDS = (KK + 63) / 64;
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_item;
-  double* s_re = reinterpret_cast<double*>(smem);
-  double* s_im = s_re + g.T * pitch;
+  const Geo& g = j.g;
   const int T = g.T;
+  const int pitch = j.pitch;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
+  const uint32_t nch = j.tile_chunks[t];
+  int k, oy, ox;
+  tile_origin(g, t, k, oy, ox);
+  cplx<R>* dst = j.planes + ((size_t)k * g.nv + oy) * g.nu + ox;
+  // Key ranges of the records that reach this tile; all offsets are loaded
+  // up front so that their latencies overlap.
+  uint32_t lo[10], hi[10], s0[10], len[10];
+  const int ns = tile_segments(g, t, lo, hi);
+  uint32_t work = 0;
+#pragma unroll
+  for (int s = 0; s < 10; ++s) {
+    s0[s] = 0;
+    len[s] = 0;
+    if (s < ns) {
+      s0[s] = j.offsets[lo[s]];
+      len[s] = j.offsets[hi[s]] - s0[s];
+    }
+    work += len[s];
+  }
+  if (work == 0) {
+    // Empty tile: the first gridding call writes its zeros; later calls
+    // have nothing to add.
+    if (!j.accumulate) zero_tile(T, dst, (size_t)g.nu);
+    return;
+  }
+  for (int i = threadIdx.x; i < T * pitch; i += blockDim.x) {
+    s_re[i] = 0.0;
+    s_im[i] = 0.0;
+  }
   int ta[ROUNDS], tb[ROUNDS];
 #pragma unroll
   for (int q = 0; q < ROUNDS; ++q) {
@@ -172,90 +194,113 @@ __global__ __launch_bounds__(256) void k_grid_tiles(
     ta[q] = tt % K - H;
     tb[q] = tt / K - H;
   }
-  int t;
-  uint32_t c;
-  while (next_item(g, counters, extra, &s_item, t, c)) {
-    const uint32_t nch = tile_chunks[t];
-    int k, oy, ox;
-    tile_origin(g, t, k, oy, ox);
-    cplx<R>* dst = planes + ((size_t)k * g.nv + oy) * g.nu + ox;
-    // Key ranges of the records that reach this tile; all offsets are
-    // loaded up front so that their latencies overlap.
-    uint32_t lo[10], hi[10], s0[10], len[10];
-    const int ns = tile_segments(g, t, lo, hi);
-    uint32_t work = 0;
-#pragma unroll
-    for (int s = 0; s < 10; ++s) {
-      s0[s] = 0;
-      len[s] = 0;
-      if (s < ns) {
-        s0[s] = offsets[lo[s]];
-        len[s] = offsets[hi[s]] - s0[s];
-      }
-      work += len[s];
-    }
-    if (work == 0) {
-      // Empty tile: the first gridding call writes its zeros; later calls
-      // have nothing to add.
-      if (!accumulate) zero_tile(T, dst, (size_t)g.nu);
+  __syncthreads();
+  // This item's records: [c * chunk, (c + 1) * chunk) of the concatenated
+  // segments; a tile gridded by a single item takes all of them.
+  uint32_t skip = c * j.chunk;
+  uint32_t left = nch == 1 ? work : j.chunk;
+  for (int s = 0; s < ns && left > 0; ++s) {
+    if (skip >= len[s]) {
+      skip -= len[s];
       continue;
     }
-    for (int i = threadIdx.x; i < T * pitch; i += blockDim.x) {
-      s_re[i] = 0.0;
-      s_im[i] = 0.0;
-    }
-    __syncthreads();
-    // This item's records: [c * chunk, (c + 1) * chunk) of the concatenated
-    // segments; a tile gridded by a single item takes all of them.
-    uint32_t skip = c * chunk;
-    uint32_t left = nch == 1 ? work : chunk;
-    for (int s = 0; s < ns && left > 0; ++s) {
-      if (skip >= len[s]) {
-        skip -= len[s];
-        continue;
+    const uint32_t start = s0[s] + skip;
+    const uint32_t n = (len[s] - skip) < left ? (len[s] - skip) : left;
+    skip = 0;
+    left -= n;
+    for (uint32_t b0 = (uint32_t)wave * 64; b0 < n;
+         b0 += (uint32_t)nwaves * 64) {
+      const uint32_t my = b0 + lane;
+      uint32_t cell = 0;
+      cplx<R> dxy = {(R)0, (R)0}, val = {(R)0, (R)0};
+      if (my < n) {
+        cell = j.rec_cell[start + my];
+        dxy = j.rec_dxy[start + my];
+        val = j.rec_val[start + my];
       }
-      const uint32_t start = s0[s] + skip;
-      const uint32_t n = (len[s] - skip) < left ? (len[s] - skip) : left;
-      skip = 0;
-      left -= n;
-      for (uint32_t b0 = (uint32_t)wave * 64; b0 < n;
-           b0 += (uint32_t)nwaves * 64) {
-        const uint32_t my = b0 + lane;
-        uint32_t cell = 0;
-        cplx<R> dxy = {(R)0, (R)0}, val = {(R)0, (R)0};
-        if (my < n) {
-          cell = rec_cell[start + my];
-          dxy = rec_dxy[start + my];
-          val = rec_val[start + my];
-        }
-        const int cnt = (n - b0) < 64u ? (int)(n - b0) : 64;
-        for (int r = 0; r < cnt; ++r) {
-          const uint32_t cc = bcast_u(cell, r);
-          const R dx = bcast(dxy.re, r), dy = bcast(dxy.im, r);
-          const R vr = bcast(val.re, r), vi = bcast(val.im, r);
-          const int ci = cell_i(cc) - ox, cj = cell_j(cc) - oy;
+      const int cnt = (n - b0) < 64u ? (int)(n - b0) : 64;
+      for (int r = 0; r < cnt; ++r) {
+        const uint32_t cc = bcast_u(cell, r);
+        const R dx = bcast(dxy.re, r), dy = bcast(dxy.im, r);
+        const R vr = bcast(val.re, r), vi = bcast(val.im, r);
+        const int ci = cell_i(cc) - ox, cj = cell_j(cc) - oy;
 #pragma unroll
-          for (int q = 0; q < ROUNDS; ++q) {
-            if (KK % 64 == 0 || lane + 64 * q < KK) {
-              const int li = ci + ta[q], lj = cj + tb[q];
-              if ((unsigned)li < (unsigned)T && (unsigned)lj < (unsigned)T) {
-                const R w = gauss1(g, (R)ta[q] - dx) * gauss1(g, (R)tb[q] - dy);
-                atomicAdd(s_re + lj * pitch + li, (double)(w * vr));
-                atomicAdd(s_im + lj * pitch + li, (double)(w * vi));
-              }
+        for (int q = 0; q < ROUNDS; ++q) {
+          if (KK % 64 == 0 || lane + 64 * q < KK) {
+            const int li = ci + ta[q], lj = cj + tb[q];
+            if ((unsigned)li < (unsigned)T && (unsigned)lj < (unsigned)T) {
+              const R w = gauss1(g, (R)ta[q] - dx) * gauss1(g, (R)tb[q] - dy);
+              atomicAdd(s_re + lj * pitch + li, (double)(w * vr));
+              atomicAdd(s_im + lj * pitch + li, (double)(w * vi));
             }
           }
         }
       }
     }
-    __syncthreads();
-    if (nch == 1) {
-      store_tile(s_re, s_im, pitch, T, g.cnorm, dst, (size_t)g.nu,
-                 accumulate != 0);
-    } else {
-      cplx<R>* part = partials + (size_t)(tile_slot[t] + c) * T * T;
-      store_tile(s_re, s_im, pitch, T, 1.0, part, (size_t)T, false);
+  }
+  __syncthreads();
+  if (nch == 1) {
+    store_tile(s_re, s_im, pitch, T, g.cnorm, dst, (size_t)g.nu,
+               j.accumulate != 0);
+  } else {
+    cplx<R>* part = j.partials + (size_t)(j.tile_slot[t] + c) * T * T;
+    store_tile(s_re, s_im, pitch, T, 1.0, part, (size_t)T, false);
+  }
+}
+
+template <typename R, int K>
+__global__ __launch_bounds__(256) void k_grid_tiles(GridJob<R> j) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_item;
+  double* s_re = reinterpret_cast<double*>(smem);
+  double* s_im = s_re + j.g.T * j.pitch;
+  int t;
+  uint32_t c;
+  while (next_item(j.g, j.counters, j.extra, &s_item, t, c))
+    grid_item<R, K>(j, t, c, s_re, s_im);
+}
+
+// Batched gridding: one persistent launch drains a single queue holding the
+// work items of every job (plan), job after job; the LDS tile is sized for
+// the largest tile of the batch.
+template <typename R, int K>
+__global__ __launch_bounds__(256) void k_grid_batch(
+    const GridJob<R>* __restrict__ jobs, int njobs,
+    uint32_t* __restrict__ queue) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_base[kMaxBatch + 1];
+  double* s_re = reinterpret_cast<double*>(smem);
+  if (threadIdx.x == 0) {
+    uint32_t b = 0;
+    for (int p = 0; p < njobs; ++p) {
+      s_base[p] = b;
+      b += jobs[p].counters[2] + (uint32_t)jobs[p].g.ntiles;
     }
+    s_base[njobs] = b;
+  }
+  while (true) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
+    __syncthreads();
+    const uint32_t item = s_item;
+    if (item >= s_base[njobs]) break;
+    int p = 0;
+    while (item >= s_base[p + 1]) ++p;
+    const GridJob<R> j = jobs[p];
+    const uint32_t local = item - s_base[p];
+    const uint32_t nextra = j.counters[2];
+    int t;
+    uint32_t c;
+    if (local < nextra) {
+      const uint2 tc = j.extra[local];
+      t = (int)tc.x;
+      c = tc.y;
+    } else {
+      t = (int)(local - nextra);
+      c = 0;
+    }
+    grid_item<R, K>(j, t, c, s_re, s_re + j.g.T * j.pitch);
   }
 }
 
@@ -330,7 +375,7 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(
       const int gr = oy - H + lr, gc = ox - H + lc;
       cplx<R> v = {(R)0, (R)0};
       if ((unsigned)gr < (unsigned)g.nv && (unsigned)gc < (unsigned)g.nu)
-        v = src[(size_t)gr * g.nu + gc];
+        v = src[(size_t)stack_row(g, gr) * g.nu + gc];
       s_q[i] = v;
     }
     __syncthreads();
@@ -382,20 +427,21 @@ uint32_t persistent_groups(size_t lds_bytes, int cus, uint32_t max_items) {
 }
 
 template <typename R, int K>
-void grid_k(const Geo& g, const uint32_t* offsets, uint32_t* counters,
-            const uint2* extra, const uint32_t* tile_chunks,
-            const uint32_t* tile_slot, const uint32_t* rec_cell,
-            const void* rec_dxy, const void* rec_val, uint32_t chunk,
-            void* planes, void* partials, int accumulate, uint32_t max_items,
-            int cus, hipStream_t st) {
-  const int pitch = grid_lds_pitch(g.T, K);
-  const size_t lds = (size_t)2 * g.T * pitch * sizeof(double);
+void grid_k(const GridJob<R>& j, uint32_t max_items, int cus,
+            hipStream_t st) {
+  const size_t lds = (size_t)2 * j.g.T * j.pitch * sizeof(double);
   hipLaunchKernelGGL((k_grid_tiles<R, K>),
                      dim3(persistent_groups(lds, cus, max_items)), dim3(256),
-                     lds, st, g, pitch, offsets, counters, extra, tile_chunks,
-                     tile_slot, rec_cell, (const cplx<R>*)rec_dxy,
-                     (const cplx<R>*)rec_val, chunk, (cplx<R>*)planes,
-                     (cplx<R>*)partials, accumulate);
+                     lds, st, j);
+}
+
+template <typename R, int K>
+void grid_batch_k(const GridJob<R>* jobs, int njobs, size_t lds,
+                  uint32_t* queue, uint32_t max_items, int cus,
+                  hipStream_t st) {
+  hipLaunchKernelGGL((k_grid_batch<R, K>),
+                     dim3(persistent_groups(lds, cus, max_items)), dim3(256),
+                     lds, st, jobs, njobs, queue);
 }
 
 template <typename R, int K>
@@ -436,17 +482,17 @@ int grid_lds_pitch(int T, int K) {
   }
 
 template <typename R>
-void launch_grid_tiles(const Geo& g, const uint32_t* offsets,
-                       uint32_t* counters, const uint2* extra,
-                       const uint32_t* tile_chunks, const uint32_t* tile_slot,
-                       const uint32_t* rec_cell, const void* rec_dxy,
-                       const void* rec_val, uint32_t chunk, void* planes,
-                       void* partials, int accumulate, uint32_t max_items,
-                       int cus, hipStream_t st) {
-  WS_K_SWITCH(g.K, (grid_k<R, KK>(g, offsets, counters, extra, tile_chunks,
-                                  tile_slot, rec_cell, rec_dxy, rec_val,
-                                  chunk, planes, partials, accumulate,
-                                  max_items, cus, st)));
+void launch_grid_tiles(const GridJob<R>& j, uint32_t max_items, int cus,
+                       hipStream_t st) {
+  WS_K_SWITCH(j.g.K, (grid_k<R, KK>(j, max_items, cus, st)));
+}
+
+template <typename R>
+void launch_grid_batch(const GridJob<R>* jobs, int njobs, int K, size_t lds,
+                       uint32_t* queue, uint32_t max_items, int cus,
+                       hipStream_t st) {
+  WS_K_SWITCH(K, (grid_batch_k<R, KK>(jobs, njobs, lds, queue, max_items,
+                                      cus, st)));
 }
 
 template <typename R>
@@ -481,11 +527,11 @@ size_t degrid_lds_bytes(int T, int K, int elem_bytes) {
 }
 
 #define WS_INST(R)                                                          \
-  template void launch_grid_tiles<R>(                                      \
-      const Geo&, const uint32_t*, uint32_t*, const uint2*,                \
-      const uint32_t*, const uint32_t*, const uint32_t*, const void*,      \
-      const void*, uint32_t, void*, void*, int, uint32_t, int,             \
-      hipStream_t);                                                        \
+  template void launch_grid_tiles<R>(const GridJob<R>&, uint32_t, int,     \
+                                     hipStream_t);                         \
+  template void launch_grid_batch<R>(const GridJob<R>*, int, int, size_t,  \
+                                     uint32_t*, uint32_t, int,             \
+                                     hipStream_t);                         \
   template void launch_grid_merge<R>(const Geo&, const uint32_t*,          \
                                      const uint32_t*, const uint32_t*,     \
                                      const uint32_t*, const void*, void*,  \

@@ -52,7 +52,21 @@ struct Geo {
   double inv2s2;       // 1 / (2 sigma^2), FP64
   float kappa;         // log2(e) / (2 sigma^2), FP32 (exp2 form)
   double cnorm;        // 1 / (2 pi sigma^2)
+  // Row order of a transformed stack: 0 = natural; otherwise the columns
+  // went through a four-step transform of nv = perm_n1 * perm_n2 and row
+  // k1 * perm_n2 + k2 holds column frequency k1 + perm_n1 * k2.
+  int perm_n1, perm_n2;
 };
+
+// Row of the stack that holds column frequency q.
+__host__ __device__ inline int stack_row(const Geo& g, int q) {
+  return g.perm_n1 == 0 ? q : (q % g.perm_n1) * g.perm_n2 + q / g.perm_n1;
+}
+
+// Column frequency held by row r of the stack.
+__host__ __device__ inline int stack_freq(const Geo& g, int r) {
+  return g.perm_n1 == 0 ? r : r / g.perm_n2 + g.perm_n1 * (r % g.perm_n2);
+}
 
 // FP64 placement of one visibility.  Contraction is off so that the cell
 // position and the plane index round exactly as the separate IEEE multiply,

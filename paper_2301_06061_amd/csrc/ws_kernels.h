@@ -33,14 +33,34 @@ void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
 // gridding and degridding (grid.hip)
 int grid_lds_pitch(int T, int K);
 size_t degrid_lds_bytes(int T, int K, int elem_bytes);
+// Everything one gridding launch needs for one plan (passed by value, or
+// as an array in device memory for a batch).
+constexpr int kMaxBatch = 64;
 template <typename R>
-void launch_grid_tiles(const Geo& g, const uint32_t* offsets,
-                       uint32_t* counters, const uint2* extra,
-                       const uint32_t* tile_chunks, const uint32_t* tile_slot,
-                       const uint32_t* rec_cell, const void* rec_dxy,
-                       const void* rec_val, uint32_t chunk, void* planes,
-                       void* partials, int accumulate, uint32_t max_items,
-                       int cus, hipStream_t st);
+struct GridJob {
+  Geo g;
+  int pitch;                  // LDS row pitch of the tile (FP64 words)
+  const uint32_t* offsets;    // record offset of every key (+ total)
+  uint32_t* counters;         // [1] split tiles, [2] extra items, [3] queue
+  const uint2* extra;         // (tile, chunk) of the further chunks
+  const uint32_t* tile_chunks;
+  const uint32_t* tile_slot;
+  const uint32_t* rec_cell;
+  const cplx<R>* rec_dxy;
+  const cplx<R>* rec_val;
+  uint32_t chunk;
+  cplx<R>* planes;
+  cplx<R>* partials;
+  int accumulate;
+};
+
+template <typename R>
+void launch_grid_tiles(const GridJob<R>& j, uint32_t max_items, int cus,
+                       hipStream_t st);
+template <typename R>
+void launch_grid_batch(const GridJob<R>* jobs, int njobs, int K, size_t lds,
+                       uint32_t* queue, uint32_t max_items, int cus,
+                       hipStream_t st);
 template <typename R>
 void launch_grid_merge(const Geo& g, const uint32_t* counters,
                        const uint32_t* split_list, const uint32_t* tile_chunks,
@@ -70,6 +90,15 @@ bool launch_row_screen_sum(const void* planes, void* img, const Geo& g,
 template <typename R>
 bool launch_screen_row_bcast(const void* img, int img_real, void* planes,
                              const Geo& g, const void* tw_u, hipStream_t st);
+template <typename R>
+bool launch_fft_cols4(void* data, int nrows, int ncols, int nplanes,
+                      const void* tw, int sign, hipStream_t st);
+template <typename R>
+void launch_unpermute_rows(const void* src, void* dst, const Geo& g,
+                           hipStream_t st);
+template <typename R>
+void launch_screen_bcast(const void* img, int img_real, void* planes,
+                         const Geo& g, hipStream_t st);
 template <typename R>
 void launch_wcorrect(const void* F, void* img, const Geo& g, hipStream_t st);
 template <typename R>

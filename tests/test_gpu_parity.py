@@ -100,10 +100,18 @@ def test_grid_matches_oracle(precision, ci):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("shape", [(16, 16, 1), (64, 32, 3), (512, 512, 2),
-                                   (32, 4096, 1), (4096, 16, 1)])
+                                   (32, 4096, 1), (4096, 16, 1),
+                                   (16, 8192, 2), (32, 16384, 1),
+                                   (8192, 16, 1), (16384, 16, 1)])
 @pytest.mark.parametrize("direction", [1, -1])
 def test_fft_planes_matches_oracle(precision, shape, direction):
+    """One-pass and four-step columns, LDS rows up to 16384 (FP32)."""
     nu, nv, nw = shape
+    if precision == "fp64" and nu > 8192:
+        with pytest.raises(ws.WStackError):
+            ws.WStackPlan(nu, nv, nw, 0.02, 0.02, -1.0, 1.0, 7,
+                          precision=precision, max_vis=16, tile=16)
+        return
     rng = np.random.default_rng(nu + nv + nw)
     cdt = np.complex128 if precision == "fp64" else np.complex64
     data = (rng.standard_normal((nw, nv, nu)) +
@@ -141,6 +149,33 @@ def test_wcorrect_matches_oracle(precision, fov_deg):
     plan.wcorrect(img)
     ref = o.wcorrect(p, data.astype(np.complex128)) + 1.0
     assert_close(host(img), ref, precision == "fp64", "wcorrect")
+
+
+LARGE = [dict(n=16, nv=8192, nw=2, support=7, m=2000, law="core"),
+         dict(n=32, nv=16384, nw=3, support=9, m=2000, law="gauss"),
+         dict(n=8192, nv=16, nw=2, support=5, m=2000, law="core")]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("ci", range(len(LARGE)))
+def test_large_grid_image_and_degrid(precision, fused, ci):
+    """Grids beyond the one-pass column FFT (four-step columns, transposed
+    row order undone by the screen and gather kernels)."""
+    c = LARGE[ci]
+    wl = _case(c, precision, seed=21)
+    p = o.Params.of(wl)
+    plan = plan_for(wl)
+    uvw, vis, wt = dev(wl)
+    img = plan.dirty_image(uvw, vis, wt, fused=fused)
+    assert_close(host(img), o.image(p, wl.uvw, wl.vis, wl.weight),
+                 precision == "fp64", "large image")
+    rng = np.random.default_rng(ci)
+    x = rng.standard_normal((wl.nv, wl.nu))
+    xt = torch.from_numpy(x).to("cuda").to(plan.rdtype)
+    got = host(plan.degrid(xt, uvw, wt))
+    assert_close(got, o.degrid(p, x, wl.uvw, wl.weight), precision == "fp64",
+                 "large degrid")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
