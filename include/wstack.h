@@ -70,8 +70,7 @@ typedef int32_t ws_status;
                      precision, Sec. 4.2 memory model) */
 
 /* Imaging geometry and kernel.
- *   nu, nv   grid size, each a power of two in [16, 16384]; on the FP64
- *            path nu <= 8192 (one grid row must fit a workgroup's LDS)
+ *   nu, nv   grid size, each a power of two in [16, 16384]
  *   nw       number of w-planes, >= 1
  *   fov_l, fov_m  full field of view in radians, > 0, with
  *            (fov_l/2)^2 + (fov_m/2)^2 < 1

@@ -59,8 +59,8 @@ struct Layout {
   size_t planes_bytes;
   // workspace offsets
   size_t o_tw_u, o_tw_v, o_counts, o_sums, o_keyrank, o_cell, o_dxy, o_val,
-      o_idx, o_chunks, o_slot, o_counters, o_split, o_extra, o_partials,
-      o_scratch, total;
+      o_idx, o_chunks, o_slot, o_counters, o_split, o_extra, o_busy, o_idle,
+      o_partials, o_scratch, total;
 };
 
 ws_status check_params(const ws_params* p) {
@@ -166,6 +166,8 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   L->o_counters = take(64);
   L->o_split = take((size_t)(L->max_slots / 2 + 1) * 4);
   L->o_extra = take((size_t)L->max_extra * 8);
+  L->o_busy = take((size_t)L->ntiles * 4);
+  L->o_idle = take((size_t)L->ntiles * 4);
   L->o_partials = take((size_t)L->max_slots * L->T * L->T * L->elem);
   // One plane of scratch for the natural-order output of ws_fft_planes
   // when columns use the four-step transform.
@@ -316,7 +318,8 @@ ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
   }));
   WS_TRY(launch(pl, "tile_work", [&] {
     launch_tile_work(g, counts, degrid, chunk, chunks, slot, counters, split,
-                     L.max_slots, pl->w<uint2>(L.o_extra), L.max_extra, st);
+                     L.max_slots, pl->w<uint2>(L.o_extra), L.max_extra,
+                     pl->w<uint32_t>(L.o_busy), pl->w<uint32_t>(L.o_idle), st);
   }));
   // Items: one per tile plus the further chunks of split tiles.
   const int64_t reads = degrid ? m : 4 * m;
@@ -335,6 +338,8 @@ GridJob<R> make_job(ws_plan* pl, int accumulate) {
   j.offsets = pl->w<uint32_t>(L.o_counts);
   j.counters = pl->w<uint32_t>(L.o_counters);
   j.extra = pl->w<uint2>(L.o_extra);
+  j.busy = pl->w<uint32_t>(L.o_busy);
+  j.idle = pl->w<uint32_t>(L.o_idle);
   j.tile_chunks = pl->w<uint32_t>(L.o_chunks);
   j.tile_slot = pl->w<uint32_t>(L.o_slot);
   j.rec_cell = pl->w<uint32_t>(L.o_cell);
@@ -486,7 +491,8 @@ ws_status degrid_impl(ws_plan* pl, const void* image, int image_is_real,
   WS_TRY(launch(pl, "degrid_tiles", [&] {
     launch_degrid_tiles<R>(g, pl->w<uint32_t>(L.o_counts),
                            pl->w<uint32_t>(L.o_counters),
-                           pl->w<uint2>(L.o_extra), pl->planes,
+                           pl->w<uint2>(L.o_extra),
+                           pl->w<uint32_t>(L.o_busy), pl->planes,
                            pl->w<uint32_t>(L.o_cell), pl->work + L.o_dxy,
                            pl->work + L.o_val, pl->w<uint32_t>(L.o_idx),
                            L.chunk_degrid, vis_out, max_items, pl->cus,

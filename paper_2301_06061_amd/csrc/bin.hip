@@ -212,24 +212,47 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
   }
 }
 
+// Appends to a list with one atomic per wavefront: returns this lane's slot
+// (lanes with pred false get an unspecified value).
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
+  const unsigned long long mask = __ballot(pred);
+  const int lane = threadIdx.x & 63;
+  const int leader = mask ? (__ffsll((long long)mask) - 1) : 0;
+  uint32_t base = 0;
+  if (mask != 0 && lane == leader)
+    base = atomicAdd(counter, (uint32_t)__popcll(mask));
+  base = (uint32_t)__shfl((int)base, leader, 64);
+  const unsigned long long below = mask & ((1ull << lane) - 1ull);
+  return base + (uint32_t)__popcll(below);
+}
+
 __global__ __launch_bounds__(256) void k_tile_work(
     Geo g, const uint32_t* __restrict__ offsets, int mode_degrid,
     uint32_t chunk, uint32_t* __restrict__ tile_chunks,
     uint32_t* __restrict__ tile_slot, uint32_t* __restrict__ counters,
     uint32_t* __restrict__ split_list, uint32_t max_slots,
-    uint2* __restrict__ extra, uint32_t max_extra) {
-  // counters[0]: scratch slots taken, [1]: split tiles, [2]: extra items.
+    uint2* __restrict__ extra, uint32_t max_extra,
+    uint32_t* __restrict__ busy, uint32_t* __restrict__ idle) {
+  // counters[0]: scratch slots taken, [1]: split tiles, [2]: extra items,
+  // [4]: tiles with records (listed in busy), [5]: tiles without (idle).
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.ntiles) return;
+  const bool live = t < g.ntiles;
   uint32_t work = 0;
-  if (mode_degrid) {
-    work = offsets[(uint32_t)t * kRegions + kRegions] -
-           offsets[(uint32_t)t * kRegions];
-  } else {
-    uint32_t lo[10], hi[10];
-    const int ns = tile_segments(g, t, lo, hi);
-    for (int s = 0; s < ns; ++s) work += offsets[hi[s]] - offsets[lo[s]];
+  if (live) {
+    if (mode_degrid) {
+      work = offsets[(uint32_t)t * kRegions + kRegions] -
+             offsets[(uint32_t)t * kRegions];
+    } else {
+      uint32_t lo[10], hi[10];
+      const int ns = tile_segments(g, t, lo, hi);
+      for (int s = 0; s < ns; ++s) work += offsets[hi[s]] - offsets[lo[s]];
+    }
   }
+  const uint32_t ib = wave_append(&counters[4], live && work > 0);
+  const uint32_t ii = wave_append(&counters[5], live && work == 0);
+  if (!live) return;
+  if (work > 0) busy[ib] = (uint32_t)t;
+  else idle[ii] = (uint32_t)t;
   uint32_t nch = work == 0 ? 1u : (work + chunk - 1) / chunk;
   tile_slot[t] = 0;
   if (nch > 1 && !mode_degrid) {
@@ -304,11 +327,12 @@ void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t chunk, uint32_t* tile_chunks,
                       uint32_t* tile_slot, uint32_t* counters,
                       uint32_t* split_list, uint32_t max_slots, uint2* extra,
-                      uint32_t max_extra, hipStream_t st) {
+                      uint32_t max_extra, uint32_t* busy, uint32_t* idle,
+                      hipStream_t st) {
   const int nb = (g.ntiles + 255) / 256;
   hipLaunchKernelGGL(k_tile_work, dim3(nb), dim3(256), 0, st, g, offsets,
                      mode_degrid, chunk, tile_chunks, tile_slot, counters,
-                     split_list, max_slots, extra, max_extra);
+                     split_list, max_slots, extra, max_extra, busy, idle);
 }
 
 }  // namespace ws

@@ -227,6 +227,56 @@ __global__ __launch_bounds__(NT) void k_fft_rows(cplx<R>* data, int64_t nrows,
   fft_line<R, LOGN, 1, NT>(lds, ld, st, twl, s);
 }
 
+template <typename R>
+__device__ __forceinline__ cplx<R> twiddle_full(const cplx<R>* tw, int idx,
+                                                R s) {
+  const cplx<R> w = tw[idx];
+  return {w.re, s * w.im};
+}
+
+// Rows too long for one workgroup's LDS (2N elements of FP64 at N = 16384):
+// one radix-2 decimation-in-frequency step in registers, then two LDS
+// transforms of half length.  With x' = (-1)^n x (centring),
+//   X[2k]   = DFT_{N/2}( x'[n] + x'[n + N/2] )
+//   X[2k+1] = DFT_{N/2}( (x'[n] - x'[n + N/2]) W_N^n ).
+// Both halves of the row are read once (coalesced); the difference terms
+// wait in registers while the sum terms are transformed, and the two
+// outputs of each k are written together.
+template <typename R, int LOGH, int NT>
+__global__ __launch_bounds__(NT) void k_fft_rows_split(
+    cplx<R>* data, int64_t nrows, const cplx<R>* __restrict__ tw, R s) {
+  constexpr int NH = 1 << LOGH;  // half length
+  constexpr int N = 2 * NH;
+  __shared__ cplx<R> lds[lds_line<NH>(1)];
+  __shared__ cplx<R> s_lo[kTwLo], s_hi[(NH + kTwLo - 1) / kTwLo];
+  using F0 = Stage<R, LOGH, 1, NT, 0>;
+  using FL = Stage<R, LOGH, 1, NT, F0::NPASS - 1>;
+  const int64_t row = blockIdx.x;
+  if (row >= nrows) return;
+  cplx<R>* line = data + row * N;
+  const Twiddles<R> twl = load_twiddles_sub(s_lo, s_hi, tw, NH, N);
+  __syncthreads();
+  cplx<R> diff[F0::IT][F0::RAD];
+  cplx<R> even[FL::IT][FL::RAD];
+  auto ld_sum = [&](int e, int, int it, int r) {
+    const cplx<R> a = checker(line[e], e);
+    const cplx<R> b = checker(line[e + NH], e + NH);
+    diff[it][r] = cmul(csub(a, b), twiddle_full(tw, e, s));
+    return cadd(a, b);
+  };
+  auto st_even = [&](int, int, int it, int r, cplx<R> v) { even[it][r] = v; };
+  fft_line<R, LOGH, 1, NT>(lds, ld_sum, st_even, twl, s);
+  auto ld_diff = [&](int, int, int it, int r) { return diff[it][r]; };
+  auto st_odd = [&](int e, int, int it, int r, cplx<R> v) {
+    // output 2e is even (sign +1), 2e + 1 is odd (sign -1)
+    const cplx<R> lo = even[it][r];
+    const cplx<R> hi = {-v.re, -v.im};
+    line[2 * e] = lo;
+    line[2 * e + 1] = hi;
+  };
+  fft_line<R, LOGH, 1, NT>(lds, ld_diff, st_odd, twl, s);
+}
+
 template <typename R, int LOGN, int BC, int NT>
 __global__ __launch_bounds__(NT) void k_fft_cols(cplx<R>* data, int ncols,
                                                  int nplanes,
@@ -265,13 +315,6 @@ __global__ __launch_bounds__(NT) void k_fft_cols(cplx<R>* data, int ncols,
 // Each step reads and writes the stack once with 16-column (128- or
 // 256-byte) row segments; the result has its rows in the transposed order
 // that stack_row() undoes.
-
-template <typename R>
-__device__ __forceinline__ cplx<R> twiddle_full(const cplx<R>* tw, int idx,
-                                                R s) {
-  const cplx<R> w = tw[idx];
-  return {w.re, s * w.im};
-}
 
 template <typename R, int LOG1, int LOG2, int BC, int NT>
 __global__ __launch_bounds__(NT) void k_fft_colA(cplx<R>* data, int ncols,
@@ -574,6 +617,12 @@ bool rows_t(cplx<R>* data, int64_t nrows, const cplx<R>* tw, R s,
     hipLaunchKernelGGL((k_fft_rows<R, LOGN, NT>), dim3((unsigned)nrows),
                        dim3(NT), 0, st, data, nrows, tw, s);
     return true;
+  } else if constexpr (line_fits<R, LOGN - 1>()) {
+    constexpr int NT = row_threads(LOGN - 1);
+    hipLaunchKernelGGL((k_fft_rows_split<R, LOGN - 1, NT>),
+                       dim3((unsigned)nrows), dim3(NT), 0, st, data, nrows,
+                       tw, s);
+    return true;
   } else {
     return false;
   }
@@ -674,8 +723,9 @@ int ilog2(int n) {
 }  // namespace
 
 bool fft_supported(int n, int elem_bytes) {
-  // Rows must fit one workgroup's LDS (150 KiB with padding).
-  return n >= 16 && (n & (n - 1)) == 0 && (size_t)(n + n / 8) * elem_bytes <= 150 * 1024;
+  // Half a row must fit one workgroup's LDS (150 KiB with padding).
+  return n >= 16 && n <= 16384 && (n & (n - 1)) == 0 &&
+         (size_t)(n / 2 + n / 16) * elem_bytes <= 150 * 1024;
 }
 
 template <typename R>

@@ -27,6 +27,8 @@ namespace ws {
 
 namespace {
 
+constexpr int kGridThreads = 512;
+
 // One-dimensional kernel factor g(d) = exp(-d^2 / (2 sigma^2)); FP32 uses
 // the hardware base-2 exponential (v_exp_f32) with a pre-scaled argument.
 // Arguments never approach the denormal range that would need rescaling:
@@ -38,29 +40,69 @@ __device__ __forceinline__ double gauss1(const Geo& g, double d) {
   return exp(-g.inv2s2 * (d * d));
 }
 
-// Next work item of this workgroup from the plan's queue (counters[3]):
-// items [0, nextra) are the further chunks of split tiles, as listed by the
-// tile-work kernel, then one item per tile.  Returns false when the queue
-// is drained.  Contains the barriers that order LDS reuse between items.
-__device__ __forceinline__ bool next_item(const Geo& g,
-                                          uint32_t* __restrict__ counters,
-                                          const uint2* __restrict__ extra,
-                                          uint32_t* s_item, int& tile,
-                                          uint32_t& chunk) {
+// Two-dimensional tap weight g(dx) g(dy) = exp(-(dx^2 + dy^2)/(2 sigma^2))
+// from the squared distance: one exponential per tap.
+__device__ __forceinline__ float gauss2(const Geo& g, float d2) {
+  return __builtin_amdgcn_exp2f(-g.kappa * d2);
+}
+__device__ __forceinline__ double gauss2(const Geo& g, double d2) {
+  return exp(-g.inv2s2 * d2);
+}
+
+// Work items of one plan, in queue order: the further chunks of split
+// (hot) tiles, then the first chunk of every tile that has records, then -
+// when idle tiles must be written - groups of kZeroGroup tiles without
+// records, which only get zeros.
+constexpr int kZeroGroup = 8;
+
+struct Item {
+  int zero;        // 1: a group of idle tiles to zero
+  int tile;
+  uint32_t chunk;  // chunk of the tile, or the group index
+};
+
+__device__ __forceinline__ uint32_t item_total(const uint32_t* counters,
+                                               bool with_zero) {
+  const uint32_t n = counters[2] + counters[4];
+  return with_zero ? n + (counters[5] + kZeroGroup - 1) / kZeroGroup : n;
+}
+
+__device__ __forceinline__ Item resolve_item(uint32_t item,
+                                             const uint32_t* counters,
+                                             const uint2* extra,
+                                             const uint32_t* busy) {
+  const uint32_t nextra = counters[2], nbusy = counters[4];
+  Item it;
+  if (item < nextra) {
+    const uint2 tc = extra[item];
+    it.zero = 0;
+    it.tile = (int)tc.x;
+    it.chunk = tc.y;
+  } else if (item < nextra + nbusy) {
+    it.zero = 0;
+    it.tile = (int)busy[item - nextra];
+    it.chunk = 0;
+  } else {
+    it.zero = 1;
+    it.tile = 0;
+    it.chunk = item - nextra - nbusy;
+  }
+  return it;
+}
+
+// Pop the next item of a plan's own queue (counters[3]).  Contains the
+// barriers that order LDS reuse between items.
+__device__ __forceinline__ bool next_item(const uint32_t* counters_ro,
+                                          uint32_t* counters,
+                                          const uint2* extra,
+                                          const uint32_t* busy, bool with_zero,
+                                          uint32_t* s_item, Item& it) {
   __syncthreads();
   if (threadIdx.x == 0) *s_item = atomicAdd(&counters[3], 1u);
   __syncthreads();
   const uint32_t item = *s_item;
-  const uint32_t nextra = counters[2];
-  if (item >= nextra + (uint32_t)g.ntiles) return false;
-  if (item < nextra) {
-    const uint2 tc = extra[item];
-    tile = (int)tc.x;
-    chunk = tc.y;
-  } else {
-    tile = (int)(item - nextra);
-    chunk = 0;
-  }
+  if (item >= item_total(counters_ro, with_zero)) return false;
+  it = resolve_item(item, counters_ro, extra, busy);
   return true;
 }
 
@@ -146,14 +188,26 @@ __device__ __forceinline__ uint32_t bcast_u(uint32_t x, int lane) {
 // instruction hit K*K distinct cells - no two lanes ever add to the same
 // accumulator at once, even where many visibilities share a cell.
 template <typename R, int K>
-__device__ __forceinline__ void grid_item(const GridJob<R>& j, int t,
-                                          uint32_t c, double* s_re,
-                                          double* s_im) {
+__device__ __forceinline__ void grid_item(const GridJob<R>& j, const Item& it,
+                                          double* s_re, double* s_im) {
   constexpr int H = (K - 1) / 2;
   constexpr int KK = K * K;
   constexpr int ROUNDS = (KK + 63) / 64;
   const Geo& g = j.g;
   const int T = g.T;
+  if (it.zero) {
+    const uint32_t nidle = j.counters[5];
+    for (uint32_t z = it.chunk * kZeroGroup;
+         z < nidle && z < (it.chunk + 1) * kZeroGroup; ++z) {
+      int k, oy, ox;
+      tile_origin(g, (int)j.idle[z], k, oy, ox);
+      zero_tile(T, j.planes + ((size_t)k * g.nv + oy) * g.nu + ox,
+                (size_t)g.nu);
+    }
+    return;
+  }
+  const int t = it.tile;
+  const uint32_t c = it.chunk;
   const int pitch = j.pitch;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -229,7 +283,8 @@ __device__ __forceinline__ void grid_item(const GridJob<R>& j, int t,
           if (KK % 64 == 0 || lane + 64 * q < KK) {
             const int li = ci + ta[q], lj = cj + tb[q];
             if ((unsigned)li < (unsigned)T && (unsigned)lj < (unsigned)T) {
-              const R w = gauss1(g, (R)ta[q] - dx) * gauss1(g, (R)tb[q] - dy);
+              const R ex = (R)ta[q] - dx, ey = (R)tb[q] - dy;
+              const R w = gauss2(g, ex * ex + ey * ey);
               atomicAdd(s_re + lj * pitch + li, (double)(w * vr));
               atomicAdd(s_im + lj * pitch + li, (double)(w * vi));
             }
@@ -249,22 +304,22 @@ __device__ __forceinline__ void grid_item(const GridJob<R>& j, int t,
 }
 
 template <typename R, int K>
-__global__ __launch_bounds__(256) void k_grid_tiles(GridJob<R> j) {
+__global__ __launch_bounds__(kGridThreads) void k_grid_tiles(GridJob<R> j) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_item;
   double* s_re = reinterpret_cast<double*>(smem);
   double* s_im = s_re + j.g.T * j.pitch;
-  int t;
-  uint32_t c;
-  while (next_item(j.g, j.counters, j.extra, &s_item, t, c))
-    grid_item<R, K>(j, t, c, s_re, s_im);
+  Item it;
+  while (next_item(j.counters, j.counters, j.extra, j.busy, !j.accumulate,
+                   &s_item, it))
+    grid_item<R, K>(j, it, s_re, s_im);
 }
 
 // Batched gridding: one persistent launch drains a single queue holding the
 // work items of every job (plan), job after job; the LDS tile is sized for
 // the largest tile of the batch.
 template <typename R, int K>
-__global__ __launch_bounds__(256) void k_grid_batch(
+__global__ __launch_bounds__(kGridThreads) void k_grid_batch(
     const GridJob<R>* __restrict__ jobs, int njobs,
     uint32_t* __restrict__ queue) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -275,7 +330,7 @@ __global__ __launch_bounds__(256) void k_grid_batch(
     uint32_t b = 0;
     for (int p = 0; p < njobs; ++p) {
       s_base[p] = b;
-      b += jobs[p].counters[2] + (uint32_t)jobs[p].g.ntiles;
+      b += item_total(jobs[p].counters, !jobs[p].accumulate);
     }
     s_base[njobs] = b;
   }
@@ -288,19 +343,8 @@ __global__ __launch_bounds__(256) void k_grid_batch(
     int p = 0;
     while (item >= s_base[p + 1]) ++p;
     const GridJob<R> j = jobs[p];
-    const uint32_t local = item - s_base[p];
-    const uint32_t nextra = j.counters[2];
-    int t;
-    uint32_t c;
-    if (local < nextra) {
-      const uint2 tc = j.extra[local];
-      t = (int)tc.x;
-      c = tc.y;
-    } else {
-      t = (int)(local - nextra);
-      c = 0;
-    }
-    grid_item<R, K>(j, t, c, s_re, s_re + j.g.T * j.pitch);
+    const Item it = resolve_item(item - s_base[p], j.counters, j.extra, j.busy);
+    grid_item<R, K>(j, it, s_re, s_re + j.g.T * j.pitch);
   }
 }
 
@@ -348,6 +392,7 @@ template <typename R, int K>
 __global__ __launch_bounds__(256) void k_degrid_tiles(
     Geo g, const uint32_t* __restrict__ offsets,
     uint32_t* __restrict__ counters, const uint2* __restrict__ extra,
+    const uint32_t* __restrict__ busy,
     const cplx<R>* __restrict__ planes, const uint32_t* __restrict__ rec_cell,
     const cplx<R>* __restrict__ rec_dxy, const cplx<R>* __restrict__ rec_val,
     const uint32_t* __restrict__ rec_idx, uint32_t chunk,
@@ -359,9 +404,10 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(
   const int T = g.T;
   const int W = T + 2 * H;
   const R cn = (R)g.cnorm;
-  int t;
-  uint32_t c;
-  while (next_item(g, counters, extra, &s_item, t, c)) {
+  Item it;
+  while (next_item(counters, counters, extra, busy, false, &s_item, it)) {
+    const int t = it.tile;
+    const uint32_t c = it.chunk;
     int k, oy, ox;
     tile_origin(g, t, k, oy, ox);
     const uint32_t r0 = offsets[(uint32_t)t * kRegions];
@@ -431,8 +477,8 @@ void grid_k(const GridJob<R>& j, uint32_t max_items, int cus,
             hipStream_t st) {
   const size_t lds = (size_t)2 * j.g.T * j.pitch * sizeof(double);
   hipLaunchKernelGGL((k_grid_tiles<R, K>),
-                     dim3(persistent_groups(lds, cus, max_items)), dim3(256),
-                     lds, st, j);
+                     dim3(persistent_groups(lds, cus, max_items)),
+                     dim3(kGridThreads), lds, st, j);
 }
 
 template <typename R, int K>
@@ -440,13 +486,13 @@ void grid_batch_k(const GridJob<R>* jobs, int njobs, size_t lds,
                   uint32_t* queue, uint32_t max_items, int cus,
                   hipStream_t st) {
   hipLaunchKernelGGL((k_grid_batch<R, K>),
-                     dim3(persistent_groups(lds, cus, max_items)), dim3(256),
-                     lds, st, jobs, njobs, queue);
+                     dim3(persistent_groups(lds, cus, max_items)),
+                     dim3(kGridThreads), lds, st, jobs, njobs, queue);
 }
 
 template <typename R, int K>
 void degrid_k(const Geo& g, const uint32_t* offsets, uint32_t* counters,
-              const uint2* extra, const void* planes,
+              const uint2* extra, const uint32_t* busy, const void* planes,
               const uint32_t* rec_cell, const void* rec_dxy,
               const void* rec_val, const uint32_t* rec_idx, uint32_t chunk,
               void* vis_out, uint32_t max_items, int cus, hipStream_t st) {
@@ -454,7 +500,7 @@ void degrid_k(const Geo& g, const uint32_t* offsets, uint32_t* counters,
   const size_t lds = (size_t)W * W * sizeof(cplx<R>);
   hipLaunchKernelGGL((k_degrid_tiles<R, K>),
                      dim3(persistent_groups(lds, cus, max_items)), dim3(256),
-                     lds, st, g, offsets, counters, extra,
+                     lds, st, g, offsets, counters, extra, busy,
                      (const cplx<R>*)planes, rec_cell,
                      (const cplx<R>*)rec_dxy, (const cplx<R>*)rec_val,
                      rec_idx, chunk, (cplx<R>*)vis_out);
@@ -509,12 +555,14 @@ void launch_grid_merge(const Geo& g, const uint32_t* counters,
 template <typename R>
 void launch_degrid_tiles(const Geo& g, const uint32_t* offsets,
                          uint32_t* counters, const uint2* extra,
-                         const void* planes, const uint32_t* rec_cell,
+                         const uint32_t* busy, const void* planes,
+                         const uint32_t* rec_cell,
                          const void* rec_dxy, const void* rec_val,
                          const uint32_t* rec_idx, uint32_t chunk,
                          void* vis_out, uint32_t max_items, int cus,
                          hipStream_t st) {
-  WS_K_SWITCH(g.K, (degrid_k<R, KK>(g, offsets, counters, extra, planes,
+  WS_K_SWITCH(g.K, (degrid_k<R, KK>(g, offsets, counters, extra, busy,
+                                    planes,
                                     rec_cell, rec_dxy, rec_val, rec_idx,
                                     chunk, vis_out, max_items, cus, st)));
 }
@@ -537,7 +585,8 @@ size_t degrid_lds_bytes(int T, int K, int elem_bytes) {
                                      const uint32_t*, const void*, void*,  \
                                      int, uint32_t, hipStream_t);          \
   template void launch_degrid_tiles<R>(                                    \
-      const Geo&, const uint32_t*, uint32_t*, const uint2*, const void*,   \
+      const Geo&, const uint32_t*, uint32_t*, const uint2*,                \
+      const uint32_t*, const void*,                                        \
       const uint32_t*, const void*, const void*, const uint32_t*,          \
       uint32_t, void*, uint32_t, int, hipStream_t);
 WS_INST(float)

@@ -28,7 +28,8 @@ void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t chunk, uint32_t* tile_chunks,
                       uint32_t* tile_slot, uint32_t* counters,
                       uint32_t* split_list, uint32_t max_slots, uint2* extra,
-                      uint32_t max_extra, hipStream_t st);
+                      uint32_t max_extra, uint32_t* busy, uint32_t* idle,
+                      hipStream_t st);
 
 // gridding and degridding (grid.hip)
 int grid_lds_pitch(int T, int K);
@@ -41,8 +42,11 @@ struct GridJob {
   Geo g;
   int pitch;                  // LDS row pitch of the tile (FP64 words)
   const uint32_t* offsets;    // record offset of every key (+ total)
-  uint32_t* counters;         // [1] split tiles, [2] extra items, [3] queue
+  uint32_t* counters;         // [1] split tiles, [2] extra items, [3] queue,
+                              // [4] busy tiles, [5] idle tiles
   const uint2* extra;         // (tile, chunk) of the further chunks
+  const uint32_t* busy;       // tiles with records ([4] of them)
+  const uint32_t* idle;       // tiles without ([5]), zeroed in groups
   const uint32_t* tile_chunks;
   const uint32_t* tile_slot;
   const uint32_t* rec_cell;
@@ -70,7 +74,8 @@ void launch_grid_merge(const Geo& g, const uint32_t* counters,
 template <typename R>
 void launch_degrid_tiles(const Geo& g, const uint32_t* offsets,
                          uint32_t* counters, const uint2* extra,
-                         const void* planes, const uint32_t* rec_cell,
+                         const uint32_t* busy, const void* planes,
+                         const uint32_t* rec_cell,
                          const void* rec_dxy, const void* rec_val,
                          const uint32_t* rec_idx, uint32_t chunk,
                          void* vis_out, uint32_t max_items, int cus,

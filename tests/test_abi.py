@@ -66,7 +66,6 @@ def test_workspace_grows_with_max_vis():
     (dict(nu=500), _abi.WS_UNSUPPORTED_SIZE),
     (dict(nv=8), _abi.WS_UNSUPPORTED_SIZE),
     (dict(nu=32768), _abi.WS_UNSUPPORTED_SIZE),
-    (dict(nu=16384, precision="fp64"), _abi.WS_UNSUPPORTED_SIZE),
     (dict(nw=0), _abi.WS_INVALID_ARG),
     (dict(support=6), _abi.WS_UNSUPPORTED_SIZE),
     (dict(support=17), _abi.WS_UNSUPPORTED_SIZE),
@@ -91,7 +90,7 @@ def test_valid_edge_params_accepted():
     ws.validate(_p(nu=16, nv=16, support=15))
     ws.validate(_p(nu=4096, nv=16, support=1, tile=16))
     ws.validate(_p(nu=16384, nv=16384, precision="fp32"))
-    ws.validate(_p(nu=8192, nv=16384, precision="fp64"))
+    ws.validate(_p(nu=16384, nv=16384, precision="fp64"))
 
 
 def test_max_vis_bounds():

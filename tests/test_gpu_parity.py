@@ -105,13 +105,9 @@ def test_grid_matches_oracle(precision, ci):
                                    (8192, 16, 1), (16384, 16, 1)])
 @pytest.mark.parametrize("direction", [1, -1])
 def test_fft_planes_matches_oracle(precision, shape, direction):
-    """One-pass and four-step columns, LDS rows up to 16384 (FP32)."""
+    """One-pass and four-step columns; rows in LDS, or split in two halves
+    when a row exceeds LDS (FP64 at 16384)."""
     nu, nv, nw = shape
-    if precision == "fp64" and nu > 8192:
-        with pytest.raises(ws.WStackError):
-            ws.WStackPlan(nu, nv, nw, 0.02, 0.02, -1.0, 1.0, 7,
-                          precision=precision, max_vis=16, tile=16)
-        return
     rng = np.random.default_rng(nu + nv + nw)
     cdt = np.complex128 if precision == "fp64" else np.complex64
     data = (rng.standard_normal((nw, nv, nu)) +
@@ -153,7 +149,8 @@ def test_wcorrect_matches_oracle(precision, fov_deg):
 
 LARGE = [dict(n=16, nv=8192, nw=2, support=7, m=2000, law="core"),
          dict(n=32, nv=16384, nw=3, support=9, m=2000, law="gauss"),
-         dict(n=8192, nv=16, nw=2, support=5, m=2000, law="core")]
+         dict(n=8192, nv=16, nw=2, support=5, m=2000, law="core"),
+         dict(n=16384, nv=16, nw=2, support=7, m=1000, law="gauss")]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
