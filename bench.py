@@ -131,6 +131,73 @@ def cpu_baseline(wl, budget_s=12.0):
     }
 
 
+def bench_degrid(args, torch, ws, synth):
+    """Config 5: A x (degrid) and A^H (A x - V) (grid) for a sparse 4096^2
+    sky and 1e7 visibilities, FP32; one step = forward + backward."""
+    from paper_2301_06061_amd.autograd import imaging_op
+    dev = torch.device("cuda", 0)
+    wl, x = synth.config5(m=args.m)
+    plan = ws.WStackPlan.from_workload(wl)
+    uvw = torch.from_numpy(wl.uvw).to(dev)
+    vis = torch.from_numpy(wl.vis).to(dev)
+    wt = torch.from_numpy(wl.weight).to(dev)
+    xt = torch.from_numpy(x).to(dev).requires_grad_(True)
+
+    def step():
+        xt.grad = None
+        loss = (imaging_op(xt, plan, uvw, wt) - vis).abs().pow(2).sum()
+        loss.backward()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    plan.kernel_times(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    kt = plan.kernel_times(reset=True)
+    plan.set_profiling(False)
+    deg = sum(v[0] for k, v in kt.items()
+              if k in ("screen_row_bcast", "degrid_tiles", "bin_count",
+                       "bin_scatter", "scan_keys", "tile_work",
+                       "zero_counts")) / args.steps
+    log(f"config5 forward+backward: {sec * 1e3:.3f} ms/step")
+    return {"ms_per_step": sec * 1e3, "mvis_per_s": wl.m / sec / 1e6,
+            "kernels": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
+            "note": "degrid forward + grid/FFT/screen backward; kernel "
+                    "times include both directions' shared binning"}
+
+
+def bench_batch(args, torch, ws, synth):
+    """Config 4: 64 channels (1e5-5e6 visibilities each, 1024^2-4096^2
+    grids, 16-32 planes) imaged as one batch replayed from a HIP graph."""
+    from paper_2301_06061_amd.batch import BatchedImager
+    dev = torch.device("cuda", 0)
+    wls = synth.config4()
+    uvw = [torch.from_numpy(w.uvw).to(dev) for w in wls]
+    vis = [torch.from_numpy(w.vis).to(dev) for w in wls]
+    wt = [torch.from_numpy(w.weight).to(dev) for w in wls]
+    b = BatchedImager(wls, uvw, vis, wt, precision="fp32")
+    for _ in range(args.warmup):
+        b.run()
+    b.capture()
+    b.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.replay()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    m = sum(w.m for w in wls)
+    log(f"config4 batch of {len(wls)}: {sec * 1e3:.3f} ms/step")
+    b.close()
+    return {"ms_per_step": sec * 1e3, "mvis_per_s": m / sec / 1e6,
+            "channels": len(wls), "visibilities": m}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +206,14 @@ def main(argv=None):
     ap.add_argument("--m", type=int, default=10_000_000)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (a reference "
+                         "for HBM byte counters)")
+    ap.add_argument("--degrid", action="store_true",
+                    help="also time the differentiable operator on the "
+                         "config-5 workload (degrid forward + grid backward)")
+    ap.add_argument("--batch", action="store_true",
+                    help="also time 64 batched channels (config-4 workload)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; "
@@ -150,6 +225,12 @@ def main(argv=None):
     import synth
 
     dev = torch.device("cuda", 0)
+    if args.probe_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     t = time.perf_counter()
     wl = synth.config2(m=args.m, precision=0)
     log(f"workload: {wl.m} vis, {wl.nu}^2 x {wl.nw} planes, K={wl.support} "
@@ -217,6 +298,12 @@ def main(argv=None):
         gb = {"avg_ms": g_ms, "achieved_gbs": gab / (g_ms / 1e3) / 1e9,
               "frac": gab / (g_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 
+    extra = {}
+    if args.degrid:
+        extra["degrid_config5"] = bench_degrid(args, torch, ws, synth)
+    if args.batch:
+        extra["batch_config4"] = bench_batch(args, torch, ws, synth)
+
     cpu = None
     if not args.no_cpu_baseline:
         t = time.perf_counter()
@@ -251,6 +338,7 @@ def main(argv=None):
         "cpu_baseline": cpu,
     }
     out.update(res)
+    out.update(extra)
     print(json.dumps(out))
     return 0
 
