@@ -243,9 +243,11 @@ __global__ __launch_bounds__(256) void k_tile_work(
       work = offsets[(uint32_t)t * kRegions + kRegions] -
              offsets[(uint32_t)t * kRegions];
     } else {
-      uint32_t lo[10], hi[10];
-      const int ns = tile_segments(g, t, lo, hi);
-      for (int s = 0; s < ns; ++s) work += offsets[hi[s]] - offsets[lo[s]];
+      uint32_t lo[kSegments], hi[kSegments];
+      tile_segments(g, t, lo, hi);
+#pragma unroll
+      for (int s = 0; s < kSegments; ++s)
+        work += offsets[hi[s]] - offsets[lo[s]];
     }
   }
   const uint32_t ib = wave_append(&counters[4], live && work > 0);

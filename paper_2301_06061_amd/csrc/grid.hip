@@ -1,22 +1,31 @@
 // Gridding (Eq. 3) and degridding (its adjoint) over binned records.
 //
 // Gridding: persistent workgroups (as many as fit on the device) take work
-// items (tile, chunk) from a queue in device memory.  A tile lives in LDS
-// as separate real and imaginary rows of FP64 accumulators on both
-// precision paths: on this part LDS FP64 atomic adds run about 20x faster
-// than FP32 ones (measured, 6.6 vs 0.33 lanes per clock per CU), so the
-// FP32 path computes its taps in FP32 and sums them in FP64 before rounding
-// the finished tile to FP32.  A wavefront takes one visibility at a time
-// and its lanes cover the K x K kernel taps, so the adds of one LDS
-// instruction hit distinct cells (no same-address serialisation, even in a
-// dense core where many visibilities share a cell); the LDS row pitch is
-// T + K (odd), so they also fall in distinct banks.
+// items from a queue in device memory.  A tile lives in LDS as separate
+// real and imaginary rows of FP64 accumulators on both precision paths: on
+// this part LDS FP64 atomic adds run about 20x faster than FP32 ones
+// (measured, 6.6 vs 0.33 lanes per clock per CU), so the FP32 path computes
+// its taps in FP32 and sums them in FP64 before rounding the finished tile
+// to FP32.  A wavefront takes one visibility at a time and its lanes cover
+// the K x K kernel taps, so the adds of one LDS instruction hit distinct
+// cells (no same-address serialisation, even in a dense core where many
+// visibilities share a cell); the LDS row pitch is T + K (odd), so they
+// also fall in distinct banks.
+//
+// Latency hiding: the records of a tile come from up to ten key ranges
+// (its own bins and its neighbours' edge strips); they are read as one
+// concatenated list, 64 per wavefront and all wavefronts at once, with the
+// next batch loaded while the current one is accumulated.  The next work
+// item is taken from the queue, and its key ranges are loaded, while the
+// current tile is written out; writing a tile also clears its LDS, so no
+// separate clearing pass is needed.
+//
 // A tile is written to HBM once, zeros included, with 16-byte row stores;
 // tiles with more records than one chunk are split over several items
-// whose partial tiles a merge kernel sums in a fixed order.  Records of a
-// neighbouring tile whose footprint crosses the tile edge are read from
-// that tile's edge-strip bins, so no record is stored twice.  The queue
-// hands out the extra chunks of split (hot) tiles first.
+// whose partial tiles a merge kernel sums in a fixed order.  The queue
+// hands out the extra chunks of split (hot) tiles first, then one item per
+// tile with records, then groups of tiles without records, which only get
+// zeros.
 //
 // Degridding: persistent workgroups take (tile, chunk) items; each loads
 // the transformed plane's tile plus an h-cell halo into LDS once, and each
@@ -49,10 +58,7 @@ __device__ __forceinline__ double gauss2(const Geo& g, double d2) {
   return exp(-g.inv2s2 * d2);
 }
 
-// Work items of one plan, in queue order: the further chunks of split
-// (hot) tiles, then the first chunk of every tile that has records, then -
-// when idle tiles must be written - groups of kZeroGroup tiles without
-// records, which only get zeros.
+// Idle tiles are zeroed kZeroGroup to a work item.
 constexpr int kZeroGroup = 8;
 
 struct Item {
@@ -90,8 +96,8 @@ __device__ __forceinline__ Item resolve_item(uint32_t item,
   return it;
 }
 
-// Pop the next item of a plan's own queue (counters[3]).  Contains the
-// barriers that order LDS reuse between items.
+// Pop the next item of a plan's own queue (counters[3]); used by the
+// degridder.  Contains the barriers that order LDS reuse between items.
 __device__ __forceinline__ bool next_item(const uint32_t* counters_ro,
                                           uint32_t* counters,
                                           const uint2* extra,
@@ -126,22 +132,25 @@ __device__ __forceinline__ void store16(cplx<double>* p,
 
 // Store (or add) a T x T tile of FP64 LDS accumulators, held as separate
 // real and imaginary rows, into a row-major complex destination of the
-// path precision, 16 bytes per store.
+// path precision, 16 bytes per store; the LDS cells read are cleared.
 template <typename R>
-__device__ __forceinline__ void store_tile(const double* s_re,
-                                           const double* s_im, int pitch,
-                                           int T, double scale, cplx<R>* dst,
-                                           size_t dst_pitch,
-                                           bool accumulate) {
+__device__ __forceinline__ void store_tile_clear(double* s_re, double* s_im,
+                                                 int pitch, int T,
+                                                 double scale, cplx<R>* dst,
+                                                 size_t dst_pitch,
+                                                 bool accumulate) {
   constexpr int V = 16 / sizeof(cplx<R>);  // complex values per store
   const int per_row = T / V;
   for (int i = threadIdx.x; i < T * per_row; i += blockDim.x) {
     const int lj = i / per_row, li = (i - lj * per_row) * V;
     cplx<R> v[V];
 #pragma unroll
-    for (int e = 0; e < V; ++e)
-      v[e] = {(R)(scale * s_re[lj * pitch + li + e]),
-              (R)(scale * s_im[lj * pitch + li + e])};
+    for (int e = 0; e < V; ++e) {
+      const int a = lj * pitch + li + e;
+      v[e] = {(R)(scale * s_re[a]), (R)(scale * s_im[a])};
+      s_re[a] = 0.0;
+      s_im[a] = 0.0;
+    }
     cplx<R>* p = dst + (size_t)lj * dst_pitch + li;
     if (accumulate) {
 #pragma unroll
@@ -180,150 +189,245 @@ __device__ __forceinline__ double bcast<double>(double x, int lane) {
 __device__ __forceinline__ uint32_t bcast_u(uint32_t x, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
 }
+__device__ __forceinline__ uint32_t uniform(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
 
-// Gridding of one item (tile t, chunk c) of one job; called by all threads
-// of the workgroup.  Each wavefront loads 64 records with one coalesced
-// load per field, then takes them one at a time: its lanes cover the K*K
-// taps of the visibility (in ceil(K*K/64) rounds), so the LDS adds of one
-// instruction hit K*K distinct cells - no two lanes ever add to the same
-// accumulator at once, even where many visibilities share a cell.
+// A work item resolved for gridding (the same in every thread).  The
+// records of a tile are the concatenation of its key ranges; position f of
+// that list is record f + off0 + the sum of step[s] over the ranges s >= 1
+// with cum[s] <= f.  The item covers positions [f0, f1).
+struct GridItem {
+  int valid;
+  int zero;
+  int tile;        // tile index, or the zero group index
+  uint32_t nch;    // items the tile is split into
+  uint32_t chunk;  // which of them
+  uint32_t f0, f1;
+  uint32_t off0;
+  uint32_t cum[kSegments];
+  uint32_t step[kSegments];
+};
+
+template <typename R>
+__device__ __forceinline__ GridItem prepare_item(const GridJob<R>& j,
+                                                 uint32_t local,
+                                                 uint32_t nextra,
+                                                 uint32_t nbusy,
+                                                 uint32_t total) {
+  GridItem x;
+  x.valid = local < total;
+  x.zero = local >= nextra + nbusy;
+  x.tile = 0;
+  x.chunk = 0;
+  if (x.valid && local < nextra) {
+    const uint2 tc = j.extra[local];
+    x.tile = (int)uniform(tc.x);
+    x.chunk = uniform(tc.y);
+  } else if (x.valid && !x.zero) {
+    x.tile = (int)uniform(j.busy[local - nextra]);
+  } else if (x.valid) {
+    x.tile = (int)(local - nextra - nbusy);
+  }
+  const bool live = x.valid && !x.zero;
+  x.nch = live ? uniform(j.tile_chunks[x.tile]) : 1u;
+  uint32_t lo[kSegments], hi[kSegments];
+  tile_segments(j.g, live ? x.tile : 0, lo, hi);
+  uint32_t cum = 0, prev = 0;
+#pragma unroll
+  for (int s = 0; s < kSegments; ++s) {
+    const uint32_t a = live ? uniform(j.offsets[lo[s]]) : 0u;
+    const uint32_t b = live ? uniform(j.offsets[hi[s]]) : 0u;
+    const uint32_t off = a - cum;
+    x.cum[s] = cum;
+    x.step[s] = off - prev;
+    if (s == 0) x.off0 = off;
+    prev = off;
+    cum += b - a;
+  }
+  x.f0 = x.chunk * j.chunk;
+  x.f1 = x.nch == 1 ? cum : min(cum, x.f0 + j.chunk);
+  return x;
+}
+
+// Record index of list position f of item x (a sum of selects, so that
+// the per-range values stay in registers).
+__device__ __forceinline__ uint32_t record_at(const GridItem& x, uint32_t f) {
+  uint32_t r = f + x.off0;
+#pragma unroll
+  for (int s = 1; s < kSegments; ++s) r += f >= x.cum[s] ? x.step[s] : 0u;
+  return r;
+}
+
+template <typename R>
+struct RecBatch {
+  uint32_t cell;
+  cplx<R> dxy, val;
+};
+
+// Loads list position f of the item; positions past the end re-read the
+// last record (so the loads need no branch) and give a zero value.
+template <typename R>
+__device__ __forceinline__ RecBatch<R> load_batch(const GridJob<R>& j,
+                                                  const GridItem& x,
+                                                  uint32_t f) {
+  const bool in = f < x.f1;
+  const uint32_t r = record_at(x, in ? f : x.f1 - 1);
+  RecBatch<R> b;
+  b.cell = j.rec_cell[r];
+  b.dxy = j.rec_dxy[r];
+  b.val = j.rec_val[r];
+  if (!in) b.val = {(R)0, (R)0};
+  return b;
+}
+
+// Accumulates the item's records into the LDS tile.  Every wavefront takes
+// batches of 64 list positions, strided by the workgroup; the next batch
+// is in flight while the current one is added.
 template <typename R, int K>
-__device__ __forceinline__ void grid_item(const GridJob<R>& j, const Item& it,
-                                          double* s_re, double* s_im) {
+__device__ __forceinline__ void accumulate_item(const GridJob<R>& j,
+                                                const GridItem& x,
+                                                double* s_re, double* s_im) {
   constexpr int H = (K - 1) / 2;
   constexpr int KK = K * K;
   constexpr int ROUNDS = (KK + 63) / 64;
-  const Geo& g = j.g;
-  const int T = g.T;
-  if (it.zero) {
-    const uint32_t nidle = j.counters[5];
-    for (uint32_t z = it.chunk * kZeroGroup;
-         z < nidle && z < (it.chunk + 1) * kZeroGroup; ++z) {
-      int k, oy, ox;
-      tile_origin(g, (int)j.idle[z], k, oy, ox);
-      zero_tile(T, j.planes + ((size_t)k * g.nv + oy) * g.nu + ox,
-                (size_t)g.nu);
-    }
-    return;
-  }
-  const int t = it.tile;
-  const uint32_t c = it.chunk;
+  const int T = j.g.T;
   const int pitch = j.pitch;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int nwaves = blockDim.x >> 6;
-  const uint32_t nch = j.tile_chunks[t];
+  const uint32_t step = (uint32_t)(blockDim.x >> 6) * 64u;
   int k, oy, ox;
-  tile_origin(g, t, k, oy, ox);
-  cplx<R>* dst = j.planes + ((size_t)k * g.nv + oy) * g.nu + ox;
-  // Key ranges of the records that reach this tile; all offsets are loaded
-  // up front so that their latencies overlap.
-  uint32_t lo[10], hi[10], s0[10], len[10];
-  const int ns = tile_segments(g, t, lo, hi);
-  uint32_t work = 0;
-#pragma unroll
-  for (int s = 0; s < 10; ++s) {
-    s0[s] = 0;
-    len[s] = 0;
-    if (s < ns) {
-      s0[s] = j.offsets[lo[s]];
-      len[s] = j.offsets[hi[s]] - s0[s];
-    }
-    work += len[s];
-  }
-  if (work == 0) {
-    // Empty tile: the first gridding call writes its zeros; later calls
-    // have nothing to add.
-    if (!j.accumulate) zero_tile(T, dst, (size_t)g.nu);
-    return;
-  }
-  for (int i = threadIdx.x; i < T * pitch; i += blockDim.x) {
-    s_re[i] = 0.0;
-    s_im[i] = 0.0;
-  }
-  int ta[ROUNDS], tb[ROUNDS];
+  tile_origin(j.g, x.tile, k, oy, ox);
+  int ta[ROUNDS], tb[ROUNDS], toff[ROUNDS];
 #pragma unroll
   for (int q = 0; q < ROUNDS; ++q) {
     const int tt = lane + 64 * q;
     ta[q] = tt % K - H;
     tb[q] = tt / K - H;
+    toff[q] = tb[q] * pitch + ta[q];
   }
-  __syncthreads();
-  // This item's records: [c * chunk, (c + 1) * chunk) of the concatenated
-  // segments; a tile gridded by a single item takes all of them.
-  uint32_t skip = c * j.chunk;
-  uint32_t left = nch == 1 ? work : j.chunk;
-  for (int s = 0; s < ns && left > 0; ++s) {
-    if (skip >= len[s]) {
-      skip -= len[s];
-      continue;
-    }
-    const uint32_t start = s0[s] + skip;
-    const uint32_t n = (len[s] - skip) < left ? (len[s] - skip) : left;
-    skip = 0;
-    left -= n;
-    for (uint32_t b0 = (uint32_t)wave * 64; b0 < n;
-         b0 += (uint32_t)nwaves * 64) {
-      const uint32_t my = b0 + lane;
-      uint32_t cell = 0;
-      cplx<R> dxy = {(R)0, (R)0}, val = {(R)0, (R)0};
-      if (my < n) {
-        cell = j.rec_cell[start + my];
-        dxy = j.rec_dxy[start + my];
-        val = j.rec_val[start + my];
-      }
-      const int cnt = (n - b0) < 64u ? (int)(n - b0) : 64;
-      for (int r = 0; r < cnt; ++r) {
-        const uint32_t cc = bcast_u(cell, r);
-        const R dx = bcast(dxy.re, r), dy = bcast(dxy.im, r);
-        const R vr = bcast(val.re, r), vi = bcast(val.im, r);
-        const int ci = cell_i(cc) - ox, cj = cell_j(cc) - oy;
+  uint32_t b0 = x.f0 + (uint32_t)wave * 64u;
+  RecBatch<R> cur = load_batch(j, x, b0 + lane);
+  while (b0 < x.f1) {
+    const uint32_t b1 = b0 + step;
+    const RecBatch<R> nxt = load_batch(j, x, b1 + lane);
+    const int cnt = (x.f1 - b0) < 64u ? (int)(x.f1 - b0) : 64;
+    for (int r = 0; r < cnt; ++r) {
+      const uint32_t cc = bcast_u(cur.cell, r);
+      const R dx = bcast(cur.dxy.re, r), dy = bcast(cur.dxy.im, r);
+      const R vr = bcast(cur.val.re, r), vi = bcast(cur.val.im, r);
+      const int ci = cell_i(cc) - ox, cj = cell_j(cc) - oy;
+      const int base = cj * pitch + ci;
 #pragma unroll
-        for (int q = 0; q < ROUNDS; ++q) {
-          if (KK % 64 == 0 || lane + 64 * q < KK) {
-            const int li = ci + ta[q], lj = cj + tb[q];
-            if ((unsigned)li < (unsigned)T && (unsigned)lj < (unsigned)T) {
-              const R ex = (R)ta[q] - dx, ey = (R)tb[q] - dy;
-              const R w = gauss2(g, ex * ex + ey * ey);
-              atomicAdd(s_re + lj * pitch + li, (double)(w * vr));
-              atomicAdd(s_im + lj * pitch + li, (double)(w * vi));
-            }
+      for (int q = 0; q < ROUNDS; ++q) {
+        if (KK % 64 == 0 || lane + 64 * q < KK) {
+          const int li = ci + ta[q], lj = cj + tb[q];
+          if ((unsigned)li < (unsigned)T && (unsigned)lj < (unsigned)T) {
+            const R ex = (R)ta[q] - dx, ey = (R)tb[q] - dy;
+            const R w = gauss2(j.g, ex * ex + ey * ey);
+            atomicAdd(s_re + base + toff[q], (double)(w * vr));
+            atomicAdd(s_im + base + toff[q], (double)(w * vi));
           }
         }
       }
     }
+    cur = nxt;
+    b0 = b1;
   }
-  __syncthreads();
-  if (nch == 1) {
-    store_tile(s_re, s_im, pitch, T, g.cnorm, dst, (size_t)g.nu,
-               j.accumulate != 0);
+}
+
+// Writes a finished item: the whole tile (scaled by the kernel norm), or
+// one partial tile of a split tile.  Clears the LDS cells it reads.
+template <typename R>
+__device__ __forceinline__ void store_item(const GridJob<R>& j,
+                                           const GridItem& x, double* s_re,
+                                           double* s_im) {
+  const int T = j.g.T;
+  if (x.nch == 1) {
+    int k, oy, ox;
+    tile_origin(j.g, x.tile, k, oy, ox);
+    cplx<R>* dst = j.planes + ((size_t)k * j.g.nv + oy) * j.g.nu + ox;
+    store_tile_clear(s_re, s_im, j.pitch, T, j.g.cnorm, dst,
+                     (size_t)j.g.nu, j.accumulate != 0);
   } else {
-    cplx<R>* part = j.partials + (size_t)(j.tile_slot[t] + c) * T * T;
-    store_tile(s_re, s_im, pitch, T, 1.0, part, (size_t)T, false);
+    cplx<R>* part =
+        j.partials + (size_t)(j.tile_slot[x.tile] + x.chunk) * T * T;
+    store_tile_clear(s_re, s_im, j.pitch, T, 1.0, part, (size_t)T, false);
   }
+}
+
+template <typename R>
+__device__ __forceinline__ void zero_group(const GridJob<R>& j, int group) {
+  const uint32_t nidle = j.counters[5];
+  const uint32_t z0 = (uint32_t)group * kZeroGroup;
+  const uint32_t z1 = min(nidle, z0 + kZeroGroup);
+  for (uint32_t z = z0; z < z1; ++z) {
+    int k, oy, ox;
+    tile_origin(j.g, (int)j.idle[z], k, oy, ox);
+    zero_tile(j.g.T, j.planes + ((size_t)k * j.g.nv + oy) * j.g.nu + ox,
+              (size_t)j.g.nu);
+  }
+}
+
+__device__ __forceinline__ void clear_lds(double* s, uint32_t words) {
+  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) s[i] = 0.0;
+}
+
+// The first half of a work item: zero a group of idle tiles, or add the
+// item's records into the LDS tile (written out after the next barrier).
+template <typename R, int K>
+__device__ __forceinline__ void do_item(const GridJob<R>& j, const GridItem& x,
+                                        double* s_re, double* s_im) {
+  if (x.zero) {
+    zero_group(j, x.tile);
+    return;
+  }
+  if (x.f1 > x.f0) accumulate_item<R, K>(j, x, s_re, s_im);
 }
 
 template <typename R, int K>
 __global__ __launch_bounds__(kGridThreads) void k_grid_tiles(GridJob<R> j) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_next;
   double* s_re = reinterpret_cast<double*>(smem);
   double* s_im = s_re + j.g.T * j.pitch;
-  Item it;
-  while (next_item(j.counters, j.counters, j.extra, j.busy, !j.accumulate,
-                   &s_item, it))
-    grid_item<R, K>(j, it, s_re, s_im);
+  const bool with_zero = !j.accumulate;
+  const uint32_t nextra = j.counters[2], nbusy = j.counters[4];
+  const uint32_t total = item_total(j.counters, with_zero);
+  uint32_t* queue = &j.counters[3];
+  clear_lds(s_re, 2u * (uint32_t)(j.g.T * j.pitch));
+  if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
+  __syncthreads();
+  GridItem x = prepare_item(j, uniform(s_next), nextra, nbusy, total);
+  while (x.valid) {
+    __syncthreads();  // every thread has read s_next
+    if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
+    do_item<R, K>(j, x, s_re, s_im);
+    __syncthreads();  // LDS sums complete; s_next visible
+    const GridItem nx = prepare_item(j, uniform(s_next), nextra, nbusy, total);
+    if (!x.zero) {
+      if (x.f1 > x.f0)
+        store_item(j, x, s_re, s_im);
+      else if (x.nch == 1 && !j.accumulate) {
+        int k, oy, ox;
+        tile_origin(j.g, x.tile, k, oy, ox);
+        zero_tile(j.g.T, j.planes + ((size_t)k * j.g.nv + oy) * j.g.nu + ox,
+                  (size_t)j.g.nu);
+      }
+    }
+    x = nx;
+  }
 }
 
 // Batched gridding: one persistent launch drains a single queue holding the
 // work items of every job (plan), job after job; the LDS tile is sized for
-// the largest tile of the batch.
+// the largest tile of the batch (lds_words FP64 words in all).
 template <typename R, int K>
 __global__ __launch_bounds__(kGridThreads) void k_grid_batch(
     const GridJob<R>* __restrict__ jobs, int njobs,
-    uint32_t* __restrict__ queue) {
+    uint32_t* __restrict__ queue, uint32_t lds_words) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_item;
+  __shared__ uint32_t s_next;
   __shared__ uint32_t s_base[kMaxBatch + 1];
   double* s_re = reinterpret_cast<double*>(smem);
   if (threadIdx.x == 0) {
@@ -333,18 +437,46 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_batch(
       b += item_total(jobs[p].counters, !jobs[p].accumulate);
     }
     s_base[njobs] = b;
+    s_next = atomicAdd(queue, 1u);
   }
-  while (true) {
+  clear_lds(s_re, lds_words);
+  __syncthreads();
+  // Resolve a queue number to (job, item of that job); jobs are read in
+  // place (uniform loads), never copied.
+  auto resolve = [&](uint32_t item, int& p) -> GridItem {
+    item = uniform(item);
+    p = 0;
+    const bool live = item < s_base[njobs];
+    if (live)
+      while (item >= s_base[p + 1]) ++p;
+    const GridJob<R>& jj = jobs[p];
+    const uint32_t total = live ? item_total(jj.counters, !jj.accumulate) : 0u;
+    return prepare_item(jj, live ? item - s_base[p] : 0u, jj.counters[2],
+                        jj.counters[4], total);
+  };
+  int p = 0;
+  GridItem x = resolve(s_next, p);
+  while (x.valid) {
     __syncthreads();
-    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
+    if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
+    const GridJob<R>& j = jobs[p];
+    double* s_im = s_re + j.g.T * j.pitch;
+    do_item<R, K>(j, x, s_re, s_im);
     __syncthreads();
-    const uint32_t item = s_item;
-    if (item >= s_base[njobs]) break;
-    int p = 0;
-    while (item >= s_base[p + 1]) ++p;
-    const GridJob<R> j = jobs[p];
-    const Item it = resolve_item(item - s_base[p], j.counters, j.extra, j.busy);
-    grid_item<R, K>(j, it, s_re, s_re + j.g.T * j.pitch);
+    int pn = 0;
+    const GridItem nx = resolve(s_next, pn);
+    if (!x.zero) {
+      if (x.f1 > x.f0)
+        store_item(j, x, s_re, s_im);
+      else if (x.nch == 1 && !j.accumulate) {
+        int k, oy, ox;
+        tile_origin(j.g, x.tile, k, oy, ox);
+        zero_tile(j.g.T, j.planes + ((size_t)k * j.g.nv + oy) * j.g.nu + ox,
+                  (size_t)j.g.nu);
+      }
+    }
+    x = nx;
+    p = pn;
   }
 }
 
@@ -487,7 +619,8 @@ void grid_batch_k(const GridJob<R>* jobs, int njobs, size_t lds,
                   hipStream_t st) {
   hipLaunchKernelGGL((k_grid_batch<R, K>),
                      dim3(persistent_groups(lds, cus, max_items)),
-                     dim3(kGridThreads), lds, st, jobs, njobs, queue);
+                     dim3(kGridThreads), lds, st, jobs, njobs, queue,
+                     (uint32_t)(lds / sizeof(double)));
 }
 
 template <typename R, int K>

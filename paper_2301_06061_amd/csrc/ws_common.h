@@ -156,11 +156,13 @@ __host__ __device__ inline int cell_j(uint32_t c) {
 
 // The key ranges (in units of keys) of the records whose kernel footprint
 // reaches tile t: its own nine regions plus the facing strips and corners
-// of its up to eight neighbours.  Writes up to 10 [lo, hi) pairs; returns
-// the count.
-__host__ __device__ inline int tile_segments(const Geo& g, int t,
-                                             uint32_t lo[10],
-                                             uint32_t hi[10]) {
+// of its up to eight neighbours.  Always writes kSegments [lo, hi) pairs in
+// fixed slots (a missing neighbour leaves its slot empty, lo == hi), so
+// that callers can keep them in registers.
+constexpr int kSegments = 10;
+__host__ __device__ inline void tile_segments(const Geo& g, int t,
+                                              uint32_t lo[kSegments],
+                                              uint32_t hi[kSegments]) {
   const int per_plane = g.tiles_u * g.tiles_v;
   const int k = t / per_plane;
   const int rem = t - k * per_plane;
@@ -170,27 +172,24 @@ __host__ __device__ inline int tile_segments(const Geo& g, int t,
   auto key0 = [&](int yy, int xx) {
     return (base + (uint32_t)(yy * g.tiles_u + xx)) * kRegions;
   };
-  int n = 0;
-  auto add = [&](uint32_t a, uint32_t b) {
-    lo[n] = a;
-    hi[n] = b;
-    ++n;
-  };
-  add(key0(ty, tx), key0(ty, tx) + 9);
   const bool L = tx > 0, Rt = tx + 1 < g.tiles_u;
   const bool A = ty > 0, B = ty + 1 < g.tiles_v;
-  if (Rt) {  // right neighbour's low-u strip: regions 6, 7 and 0
-    add(key0(ty, tx + 1) + 6, key0(ty, tx + 1) + 8);
-    add(key0(ty, tx + 1) + 0, key0(ty, tx + 1) + 1);
-  }
-  if (L) add(key0(ty, tx - 1) + 2, key0(ty, tx - 1) + 5);  // high-u strip
-  if (B) add(key0(ty + 1, tx) + 0, key0(ty + 1, tx) + 3);  // low-v strip
-  if (A) add(key0(ty - 1, tx) + 4, key0(ty - 1, tx) + 7);  // high-v strip
-  if (Rt && B) add(key0(ty + 1, tx + 1) + 0, key0(ty + 1, tx + 1) + 1);
-  if (L && B) add(key0(ty + 1, tx - 1) + 2, key0(ty + 1, tx - 1) + 3);
-  if (Rt && A) add(key0(ty - 1, tx + 1) + 6, key0(ty - 1, tx + 1) + 7);
-  if (L && A) add(key0(ty - 1, tx - 1) + 4, key0(ty - 1, tx - 1) + 5);
-  return n;
+  // slot: (present, neighbour row, neighbour column, first region, end)
+  auto put = [&](int s, bool on, int yy, int xx, uint32_t r0, uint32_t r1) {
+    const uint32_t k0 = on ? key0(yy, xx) : 0u;
+    lo[s] = on ? k0 + r0 : 0u;
+    hi[s] = on ? k0 + r1 : 0u;
+  };
+  put(0, true, ty, tx, 0, 9);
+  put(1, Rt, ty, tx + 1, 6, 8);   // right neighbour's low-u strip: 6, 7
+  put(2, Rt, ty, tx + 1, 0, 1);   //   ... and 0
+  put(3, L, ty, tx - 1, 2, 5);    // left neighbour's high-u strip
+  put(4, B, ty + 1, tx, 0, 3);    // next row's low-v strip
+  put(5, A, ty - 1, tx, 4, 7);    // previous row's high-v strip
+  put(6, Rt && B, ty + 1, tx + 1, 0, 1);
+  put(7, L && B, ty + 1, tx - 1, 2, 3);
+  put(8, Rt && A, ty - 1, tx + 1, 6, 7);
+  put(9, L && A, ty - 1, tx - 1, 4, 5);
 }
 
 }  // namespace ws

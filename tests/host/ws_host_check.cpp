@@ -45,8 +45,9 @@ int main(int argc, char** argv) {
                 dropped, ri, rj);
   }
   for (int t = 0; t < g.ntiles; ++t) {
-    unsigned lo[10], hi[10];
-    const int n = ws::tile_segments(g, t, lo, hi);
+    unsigned lo[ws::kSegments], hi[ws::kSegments];
+    ws::tile_segments(g, t, lo, hi);
+    const int n = ws::kSegments;
     std::printf("T %d %d", t, n);
     for (int s = 0; s < n; ++s) std::printf(" %u %u", lo[s], hi[s]);
     std::printf("\n");

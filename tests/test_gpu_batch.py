@@ -30,6 +30,9 @@ def _channels(precision, seed=0):
             wl.weight = wl.weight[:0]
         if nw == 1:
             wl.w_max = wl.w_min
+        elif m <= 1:
+            # one visibility: the data give no w range of their own
+            wl.w_max = wl.w_min + 1.0
         wls.append(wl)
     return wls
 

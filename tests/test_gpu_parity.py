@@ -147,8 +147,10 @@ def test_wcorrect_matches_oracle(precision, fov_deg):
     assert_close(host(img), ref, precision == "fp64", "wcorrect")
 
 
-LARGE = [dict(n=16, nv=8192, nw=2, support=7, m=2000, law="core"),
-         dict(n=32, nv=16384, nw=3, support=9, m=2000, law="gauss"),
+LARGE = [dict(n=16, nv=8192, nw=2, support=7, m=2000, law="core",
+              fov_deg=0.005),
+         dict(n=32, nv=16384, nw=3, support=9, m=2000, law="gauss",
+              fov_deg=0.005),
          dict(n=8192, nv=16, nw=2, support=5, m=2000, law="core"),
          dict(n=16384, nv=16, nw=2, support=7, m=1000, law="gauss")]
 
