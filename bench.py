@@ -207,8 +207,9 @@ def main(argv=None):
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe-copy", action="store_true",
-                    help="also run one plain 1 GiB device copy (a reference "
-                         "for HBM byte counters)")
+                    help="also run one plain elementwise kernel that reads "
+                         "1 GiB and writes 1 GiB (a reference for HBM byte "
+                         "counters)")
     ap.add_argument("--degrid", action="store_true",
                     help="also time the differentiable operator on the "
                          "config-5 workload (degrid forward + grid backward)")
@@ -228,7 +229,7 @@ def main(argv=None):
     if args.probe_copy:
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)  # one elementwise kernel: 1 GiB in, 1 GiB out
         torch.cuda.synchronize()
         del a, b
     t = time.perf_counter()

@@ -406,19 +406,51 @@ __device__ __forceinline__ double n_minus_one(const Geo& g, int p, int q) {
   return -r2 / (1.0 + sqrt(1.0 - r2));
 }
 
-// Screen phasor of plane 0 and the plane-to-plane step at pixel (p, q);
-// conj = true gives the conjugate screen.
-__device__ __forceinline__ void screen_seed(const Geo& g, int p, int q,
-                                            bool conj, cplx<double>& ph,
-                                            cplx<double>& step) {
-  const double nm1 = n_minus_one(g, p, q);
-  ph = turns_phasor(g.w0 * nm1);
-  step = turns_phasor(g.dw * nm1);
-  if (conj) {
-    ph.im = -ph.im;
-    step.im = -step.im;
+// Screen phasor exp(+-2 pi i w_k (n - 1)) of pixel (p, q), handed out plane
+// by plane (k = 0, 1, ... in order).  The phase w_k (n - 1) is formed and
+// reduced to [-1/2, 1/2] turn in FP64 on both paths.  The FP64 path seeds
+// an FP64 phasor with sincospi and advances it by an FP64 complex multiply
+// per plane; the FP32 path evaluates each plane's phasor directly with
+// FP32 sincospi of the reduced phase (error about 1e-7, the order of the
+// FP32 transform's own), which keeps two registers of state per pixel
+// instead of eight.
+template <typename R>
+struct Screen;
+
+template <>
+struct Screen<double> {
+  cplx<double> ph, step;
+  __device__ __forceinline__ void init(const Geo& g, int p, int q, bool conj) {
+    const double nm1 = n_minus_one(g, p, q);
+    ph = turns_phasor(g.w0 * nm1);
+    step = turns_phasor(g.dw * nm1);
+    if (conj) {
+      ph.im = -ph.im;
+      step.im = -step.im;
+    }
   }
-}
+  __device__ __forceinline__ cplx<double> next(const Geo&, int) {
+    const cplx<double> w = ph;
+    ph = cmul(ph, step);
+    return w;
+  }
+};
+
+template <>
+struct Screen<float> {
+  double nm1;  // negated for the conjugate screen
+  __device__ __forceinline__ void init(const Geo& g, int p, int q, bool conj) {
+    nm1 = n_minus_one(g, p, q);
+    if (conj) nm1 = -nm1;
+  }
+  __device__ __forceinline__ cplx<float> next(const Geo& g, int k) {
+    const double a = (g.w0 + (double)k * g.dw) * nm1;
+    const float f = (float)(a - rint(a));
+    float sn, cs;
+    sincospif(2.0f * f, &sn, &cs);
+    return {cs, sn};
+  }
+};
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_wcorrect(const cplx<R>* __restrict__ F,
@@ -428,22 +460,20 @@ __global__ __launch_bounds__(256) void k_wcorrect(const cplx<R>* __restrict__ F,
   const int64_t npix = (int64_t)g.nu * g.nv;
   if (pix >= npix) return;
   const int q = (int)(pix / g.nu), p = (int)(pix - (int64_t)q * g.nu);
-  cplx<double> ph, step;
-  screen_seed(g, p, q, false, ph, step);
+  Screen<R> sc;
+  sc.init(g, p, q, false);
   cplx<R> acc = {(R)0, (R)0};
   const int64_t src = (int64_t)stack_row(g, q) * g.nu + p;
   for (int k = 0; k < g.nw; ++k) {
     const cplx<R> f = F[(size_t)k * npix + src];
-    const cplx<R> w = {(R)ph.re, (R)ph.im};
-    acc = cadd(acc, cmul(f, w));
-    ph = cmul(ph, step);
+    acc = cadd(acc, cmul(f, sc.next(g, k)));
   }
   img[pix] = cadd(img[pix], acc);
 }
 
 // Row transform of every plane + screen + plane sum into image row q.
 template <typename R, int LOGN, int NT>
-__global__ __launch_bounds__(NT) void k_row_screen_sum(
+__global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
     const cplx<R>* __restrict__ planes, cplx<R>* __restrict__ img, Geo g,
     const cplx<R>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
@@ -455,7 +485,7 @@ __global__ __launch_bounds__(NT) void k_row_screen_sum(
   const Twiddles<R> twl = load_twiddles(s_lo, s_hi, tw, N);
   __syncthreads();
   cplx<R> acc[IT][RAD];
-  cplx<double> ph[IT][RAD], step[IT][RAD];
+  Screen<R> sc[IT][RAD];
 #pragma unroll
   for (int it = 0; it < IT; ++it)
 #pragma unroll
@@ -463,12 +493,15 @@ __global__ __launch_bounds__(NT) void k_row_screen_sum(
       const int p = threadIdx.x + it * NT + r * NB;
       acc[it][r] = {(R)0, (R)0};
       if (NB % NT == 0 || threadIdx.x + it * NT < NB)
-        screen_seed(g, p, q, false, ph[it][r], step[it][r]);
+        sc[it][r].init(g, p, q, false);
     }
-  // Row q of plane k + 1 is loaded into registers while plane k is being
-  // transformed, so the HBM reads overlap the LDS stages.
+  // Row q of plane k + 1 can be loaded into registers while plane k is
+  // being transformed, so the HBM reads overlap the LDS stages.
   using F0 = Stage<R, LOGN, 1, NT, 0>;
   constexpr int IT0 = F0::IT, RAD0 = F0::RAD, NB0 = F0::NB;
+  // FP32: two workgroups per CU (register-capped) overlap each other's
+  // loads, so no register prefetch; FP64 runs one and prefetches.
+  constexpr bool kPrefetch = sizeof(R) == 8;
   cplx<R> cur[IT0][RAD0], nxt[IT0][RAD0];
   auto fetch = [&](int k, cplx<R> (&buf)[IT0][RAD0]) {
     const cplx<R>* line = planes + ((size_t)k * g.nv + q) * N;
@@ -480,21 +513,23 @@ __global__ __launch_bounds__(NT) void k_row_screen_sum(
         if (NB0 % NT == 0 || j < NB0) buf[it][r] = line[j + r * NB0];
       }
   };
-  fetch(0, cur);
+  if (kPrefetch) fetch(0, cur);
   for (int k = 0; k < g.nw; ++k) {
-    if (k + 1 < g.nw) fetch(k + 1, nxt);
+    if (kPrefetch && k + 1 < g.nw) fetch(k + 1, nxt);
+    if (!kPrefetch) fetch(k, cur);
     auto ld = [&](int e, int, int it, int r) { return checker(cur[it][r], e); };
     auto st = [&](int e, int, int it, int r, cplx<R> v) {
       v = checker(v, e);
-      const cplx<R> w = {(R)ph[it][r].re, (R)ph[it][r].im};
-      acc[it][r] = cadd(acc[it][r], cmul(v, w));
-      ph[it][r] = cmul(ph[it][r], step[it][r]);
+      const auto w = sc[it][r].next(g, k);
+      acc[it][r] = cadd(acc[it][r], cmul(v, cplx<R>{(R)w.re, (R)w.im}));
     };
     fft_line<R, LOGN, 1, NT>(lds, ld, st, twl, (R)1);
+    if (kPrefetch) {
 #pragma unroll
-    for (int it = 0; it < IT0; ++it)
+      for (int it = 0; it < IT0; ++it)
 #pragma unroll
-      for (int r = 0; r < RAD0; ++r) cur[it][r] = nxt[it][r];
+        for (int r = 0; r < RAD0; ++r) cur[it][r] = nxt[it][r];
+    }
   }
   cplx<R>* out = img + (size_t)q * N;
 #pragma unroll
@@ -512,7 +547,7 @@ __global__ __launch_bounds__(NT) void k_row_screen_sum(
 // Degridding counterpart: image row q times each plane's conjugate screen,
 // then the row transform (sign -1), written to row q of every plane.
 template <typename R, int LOGN, int NT>
-__global__ __launch_bounds__(NT) void k_screen_row_bcast(
+__global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_screen_row_bcast(
     const void* __restrict__ img, int img_real, cplx<R>* __restrict__ planes,
     Geo g, const cplx<R>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
@@ -524,7 +559,7 @@ __global__ __launch_bounds__(NT) void k_screen_row_bcast(
   const Twiddles<R> twl = load_twiddles(s_lo, s_hi, tw, N);
   __syncthreads();
   cplx<R> x[IT][RAD];
-  cplx<double> ph[IT][RAD], step[IT][RAD];
+  Screen<R> sc[IT][RAD];
 #pragma unroll
   for (int it = 0; it < IT; ++it)
 #pragma unroll
@@ -538,15 +573,14 @@ __global__ __launch_bounds__(NT) void k_screen_row_bcast(
         } else {
           x[it][r] = reinterpret_cast<const cplx<R>*>(img)[(size_t)q * N + p];
         }
-        screen_seed(g, p, q, true, ph[it][r], step[it][r]);
+        sc[it][r].init(g, p, q, true);
       }
     }
   for (int k = 0; k < g.nw; ++k) {
     cplx<R>* line = planes + ((size_t)k * g.nv + q) * N;
     auto ld = [&](int e, int, int it, int r) {
-      const cplx<R> w = {(R)ph[it][r].re, (R)ph[it][r].im};
-      const cplx<R> v = cmul(x[it][r], w);
-      ph[it][r] = cmul(ph[it][r], step[it][r]);
+      const auto w = sc[it][r].next(g, k);
+      const cplx<R> v = cmul(x[it][r], cplx<R>{(R)w.re, (R)w.im});
       return checker(v, e);
     };
     auto st = [&](int e, int, int, int, cplx<R> v) { line[e] = checker(v, e); };
@@ -567,11 +601,11 @@ __global__ __launch_bounds__(256) void k_screen_bcast(
   cplx<R> x = {(R)0, (R)0};
   if (img_real) x.re = reinterpret_cast<const R*>(img)[pix];
   else x = reinterpret_cast<const cplx<R>*>(img)[pix];
-  cplx<double> ph, step;
-  screen_seed(g, p, q, true, ph, step);
+  Screen<R> sc;
+  sc.init(g, p, q, true);
   for (int k = 0; k < g.nw; ++k) {
-    planes[(size_t)k * npix + pix] = cmul(x, cplx<R>{(R)ph.re, (R)ph.im});
-    ph = cmul(ph, step);
+    const auto w = sc.next(g, k);
+    planes[(size_t)k * npix + pix] = cmul(x, cplx<R>{(R)w.re, (R)w.im});
   }
 }
 

@@ -38,6 +38,16 @@ namespace {
 
 constexpr int kGridThreads = 512;
 
+// Workgroup barrier that orders LDS only.  The persistent kernels below
+// never read, within one launch, global memory that another workgroup
+// writes, so their barriers need not wait for outstanding global stores:
+// a tile's stores drain while the workgroup goes on to the next item.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // One-dimensional kernel factor g(d) = exp(-d^2 / (2 sigma^2)); FP32 uses
 // the hardware base-2 exponential (v_exp_f32) with a pre-scaled argument.
 // Arguments never approach the denormal range that would need rescaling:
@@ -103,9 +113,9 @@ __device__ __forceinline__ bool next_item(const uint32_t* counters_ro,
                                           const uint2* extra,
                                           const uint32_t* busy, bool with_zero,
                                           uint32_t* s_item, Item& it) {
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x == 0) *s_item = atomicAdd(&counters[3], 1u);
-  __syncthreads();
+  lds_barrier();
   const uint32_t item = *s_item;
   if (item >= item_total(counters_ro, with_zero)) return false;
   it = resolve_item(item, counters_ro, extra, busy);
@@ -209,6 +219,9 @@ struct GridItem {
   uint32_t step[kSegments];
 };
 
+// Loads are unconditional (with indices that are valid whatever the item)
+// and results are selected afterwards, so that the compiler issues them
+// back to back instead of one guarded load and wait at a time.
 template <typename R>
 __device__ __forceinline__ GridItem prepare_item(const GridJob<R>& j,
                                                  uint32_t local,
@@ -218,33 +231,38 @@ __device__ __forceinline__ GridItem prepare_item(const GridJob<R>& j,
   GridItem x;
   x.valid = local < total;
   x.zero = local >= nextra + nbusy;
-  x.tile = 0;
-  x.chunk = 0;
-  if (x.valid && local < nextra) {
-    const uint2 tc = j.extra[local];
-    x.tile = (int)uniform(tc.x);
-    x.chunk = uniform(tc.y);
-  } else if (x.valid && !x.zero) {
-    x.tile = (int)uniform(j.busy[local - nextra]);
-  } else if (x.valid) {
-    x.tile = (int)(local - nextra - nbusy);
-  }
+  const bool is_extra = local < nextra;
   const bool live = x.valid && !x.zero;
-  x.nch = live ? uniform(j.tile_chunks[x.tile]) : 1u;
-  uint32_t lo[kSegments], hi[kSegments];
-  tile_segments(j.g, live ? x.tile : 0, lo, hi);
+  // First level: which tile (and chunk) the item is.
+  const uint2 tc = j.extra[is_extra ? local : 0u];
+  const uint32_t bt = j.busy[live && !is_extra ? local - nextra : 0u];
+  uint32_t tile = is_extra ? tc.x : bt;
+  x.chunk = uniform(is_extra ? tc.y : 0u);
+  if (!live) tile = 0;
+  x.tile = (int)uniform(tile);
+  // Second level: the tile's split count and key ranges.
+  const uint32_t nch = j.tile_chunks[x.tile];
+  uint32_t lo[kSegments], hi[kSegments], a[kSegments], b[kSegments];
+  tile_segments(j.g, x.tile, lo, hi);
+#pragma unroll
+  for (int s = 0; s < kSegments; ++s) {
+    a[s] = j.offsets[lo[s]];
+    b[s] = j.offsets[hi[s]];
+  }
+  x.nch = live ? uniform(nch) : 1u;
   uint32_t cum = 0, prev = 0;
 #pragma unroll
   for (int s = 0; s < kSegments; ++s) {
-    const uint32_t a = live ? uniform(j.offsets[lo[s]]) : 0u;
-    const uint32_t b = live ? uniform(j.offsets[hi[s]]) : 0u;
-    const uint32_t off = a - cum;
+    const uint32_t as = live ? uniform(a[s]) : 0u;
+    const uint32_t bs = live ? uniform(b[s]) : 0u;
+    const uint32_t off = as - cum;
     x.cum[s] = cum;
     x.step[s] = off - prev;
     if (s == 0) x.off0 = off;
     prev = off;
-    cum += b - a;
+    cum += bs - as;
   }
+  if (x.valid && x.zero) x.tile = (int)(local - nextra - nbusy);
   x.f0 = x.chunk * j.chunk;
   x.f1 = x.nch == 1 ? cum : min(cum, x.f0 + j.chunk);
   return x;
@@ -360,10 +378,19 @@ template <typename R>
 __device__ __forceinline__ void zero_group(const GridJob<R>& j, int group) {
   const uint32_t nidle = j.counters[5];
   const uint32_t z0 = (uint32_t)group * kZeroGroup;
-  const uint32_t z1 = min(nidle, z0 + kZeroGroup);
-  for (uint32_t z = z0; z < z1; ++z) {
+  // All tile numbers first (unconditional loads of valid entries), so
+  // that their loads overlap.
+  uint32_t t[kZeroGroup];
+#pragma unroll
+  for (int z = 0; z < kZeroGroup; ++z) {
+    const uint32_t v = j.idle[z0 + z < nidle ? z0 + z : 0u];
+    t[z] = z0 + z < nidle ? uniform(v) : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int z = 0; z < kZeroGroup; ++z) {
+    if (t[z] == 0xFFFFFFFFu) continue;
     int k, oy, ox;
-    tile_origin(j.g, (int)j.idle[z], k, oy, ox);
+    tile_origin(j.g, (int)t[z], k, oy, ox);
     zero_tile(j.g.T, j.planes + ((size_t)k * j.g.nv + oy) * j.g.nu + ox,
               (size_t)j.g.nu);
   }
@@ -397,13 +424,13 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_tiles(GridJob<R> j) {
   uint32_t* queue = &j.counters[3];
   clear_lds(s_re, 2u * (uint32_t)(j.g.T * j.pitch));
   if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
-  __syncthreads();
+  lds_barrier();
   GridItem x = prepare_item(j, uniform(s_next), nextra, nbusy, total);
   while (x.valid) {
-    __syncthreads();  // every thread has read s_next
+    lds_barrier();  // every thread has read s_next
     if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
     do_item<R, K>(j, x, s_re, s_im);
-    __syncthreads();  // LDS sums complete; s_next visible
+    lds_barrier();  // LDS sums complete; s_next visible
     const GridItem nx = prepare_item(j, uniform(s_next), nextra, nbusy, total);
     if (!x.zero) {
       if (x.f1 > x.f0)
@@ -440,7 +467,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_batch(
     s_next = atomicAdd(queue, 1u);
   }
   clear_lds(s_re, lds_words);
-  __syncthreads();
+  lds_barrier();
   // Resolve a queue number to (job, item of that job); jobs are read in
   // place (uniform loads), never copied.
   auto resolve = [&](uint32_t item, int& p) -> GridItem {
@@ -457,12 +484,12 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_batch(
   int p = 0;
   GridItem x = resolve(s_next, p);
   while (x.valid) {
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
     const GridJob<R>& j = jobs[p];
     double* s_im = s_re + j.g.T * j.pitch;
     do_item<R, K>(j, x, s_re, s_im);
-    __syncthreads();
+    lds_barrier();
     int pn = 0;
     const GridItem nx = resolve(s_next, pn);
     if (!x.zero) {
@@ -556,7 +583,7 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(
         v = src[(size_t)stack_row(g, gr) * g.nu + gc];
       s_q[i] = v;
     }
-    __syncthreads();
+    lds_barrier();
     for (uint32_t r = start + threadIdx.x; r < end; r += blockDim.x) {
       const uint32_t cc = rec_cell[r];
       const cplx<R> dxy = rec_dxy[r];
