@@ -371,6 +371,12 @@ ws_status grid_impl(ws_plan* pl, int64_t m, const double* uvw, const void* vis,
   WS_TRY(bin_records<R>(pl, m, uvw, vis, weight, 0, n_dropped, &max_items));
   const int acc = pl->state == kGridded ? 1 : 0;
   const GridJob<R> j = make_job<R>(pl, acc);
+  if (!acc) {
+    // First call since the reset: tiles without records get their zeros.
+    WS_TRY(launch(pl, "zero_idle", [&] {
+      launch_zero_idle<R>(pl->g, j.counters, j.idle, pl->planes, pl->stream);
+    }));
+  }
   WS_TRY(launch(pl, "grid_tiles", [&] {
     launch_grid_tiles<R>(j, max_items, pl->cus, pl->stream);
   }));
@@ -561,6 +567,12 @@ ws_status batch_image_impl(ws_batch* b, const int64_t* m,
   ws_plan* p0 = b->plans[0];
   uint32_t* queue = reinterpret_cast<uint32_t*>(b->work + batch_jobs_bytes(b->n));
   WS_TRY(launch(p0, "zero_counts", [&] { launch_zero_u32(queue, 1, b->stream); }));
+  uint64_t tiles = 0;
+  for (int i = 0; i < b->n; ++i) tiles += (uint64_t)b->plans[i]->g.ntiles;
+  WS_TRY(launch(p0, "zero_idle", [&] {
+    launch_zero_idle_batch<R>(reinterpret_cast<const GridJob<R>*>(b->work),
+                              b->n, tiles, b->stream);
+  }));
   WS_TRY(launch(p0, "grid_batch", [&] {
     launch_grid_batch<R>(reinterpret_cast<const GridJob<R>*>(b->work), b->n,
                          b->K, b->lds, queue, items, p0->cus, b->stream);

@@ -68,40 +68,30 @@ __device__ __forceinline__ double gauss2(const Geo& g, double d2) {
   return exp(-g.inv2s2 * d2);
 }
 
-// Idle tiles are zeroed kZeroGroup to a work item.
-constexpr int kZeroGroup = 8;
-
 struct Item {
-  int zero;        // 1: a group of idle tiles to zero
   int tile;
-  uint32_t chunk;  // chunk of the tile, or the group index
+  uint32_t chunk;  // chunk of the tile
 };
 
-__device__ __forceinline__ uint32_t item_total(const uint32_t* counters,
-                                               bool with_zero) {
-  const uint32_t n = counters[2] + counters[4];
-  return with_zero ? n + (counters[5] + kZeroGroup - 1) / kZeroGroup : n;
+// Work items of one plan, in queue order: the further chunks of split
+// (hot) tiles, then the first chunk of every tile that has records.
+__device__ __forceinline__ uint32_t item_total(const uint32_t* counters) {
+  return counters[2] + counters[4];
 }
 
 __device__ __forceinline__ Item resolve_item(uint32_t item,
                                              const uint32_t* counters,
                                              const uint2* extra,
                                              const uint32_t* busy) {
-  const uint32_t nextra = counters[2], nbusy = counters[4];
+  const uint32_t nextra = counters[2];
   Item it;
   if (item < nextra) {
     const uint2 tc = extra[item];
-    it.zero = 0;
     it.tile = (int)tc.x;
     it.chunk = tc.y;
-  } else if (item < nextra + nbusy) {
-    it.zero = 0;
+  } else {
     it.tile = (int)busy[item - nextra];
     it.chunk = 0;
-  } else {
-    it.zero = 1;
-    it.tile = 0;
-    it.chunk = item - nextra - nbusy;
   }
   return it;
 }
@@ -111,13 +101,13 @@ __device__ __forceinline__ Item resolve_item(uint32_t item,
 __device__ __forceinline__ bool next_item(const uint32_t* counters_ro,
                                           uint32_t* counters,
                                           const uint2* extra,
-                                          const uint32_t* busy, bool with_zero,
+                                          const uint32_t* busy,
                                           uint32_t* s_item, Item& it) {
   lds_barrier();
   if (threadIdx.x == 0) *s_item = atomicAdd(&counters[3], 1u);
   lds_barrier();
   const uint32_t item = *s_item;
-  if (item >= item_total(counters_ro, with_zero)) return false;
+  if (item >= item_total(counters_ro)) return false;
   it = resolve_item(item, counters_ro, extra, busy);
   return true;
 }
@@ -203,91 +193,49 @@ __device__ __forceinline__ uint32_t uniform(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
 }
 
-// A work item resolved for gridding (the same in every thread).  The
-// records of a tile are the concatenation of its key ranges; position f of
-// that list is record f + off0 + the sum of step[s] over the ranges s >= 1
-// with cum[s] <= f.  The item covers positions [f0, f1).
-struct GridItem {
-  int valid;
-  int zero;
-  int tile;        // tile index, or the zero group index
-  uint32_t nch;    // items the tile is split into
-  uint32_t chunk;  // which of them
-  uint32_t f0, f1;
-  uint32_t off0;
-  uint32_t cum[kSegments];
-  uint32_t step[kSegments];
-};
-
-// Loads are unconditional (with indices that are valid whatever the item)
-// and results are selected afterwards, so that the compiler issues them
-// back to back instead of one guarded load and wait at a time.
-template <typename R>
-__device__ __forceinline__ GridItem prepare_item(const GridJob<R>& j,
-                                                 uint32_t local,
-                                                 uint32_t nextra,
-                                                 uint32_t nbusy,
-                                                 uint32_t total) {
-  GridItem x;
-  x.valid = local < total;
-  x.zero = local >= nextra + nbusy;
-  const bool is_extra = local < nextra;
-  const bool live = x.valid && !x.zero;
-  // First level: which tile (and chunk) the item is.
-  const uint2 tc = j.extra[is_extra ? local : 0u];
-  const uint32_t bt = j.busy[live && !is_extra ? local - nextra : 0u];
-  uint32_t tile = is_extra ? tc.x : bt;
-  x.chunk = uniform(is_extra ? tc.y : 0u);
-  if (!live) tile = 0;
-  x.tile = (int)uniform(tile);
-  // Second level: the tile's split count and key ranges.
-  const uint32_t nch = j.tile_chunks[x.tile];
-  uint32_t lo[kSegments], hi[kSegments], a[kSegments], b[kSegments];
-  tile_segments(j.g, x.tile, lo, hi);
-#pragma unroll
-  for (int s = 0; s < kSegments; ++s) {
-    a[s] = j.offsets[lo[s]];
-    b[s] = j.offsets[hi[s]];
-  }
-  x.nch = live ? uniform(nch) : 1u;
-  uint32_t cum = 0, prev = 0;
-#pragma unroll
-  for (int s = 0; s < kSegments; ++s) {
-    const uint32_t as = live ? uniform(a[s]) : 0u;
-    const uint32_t bs = live ? uniform(b[s]) : 0u;
-    const uint32_t off = as - cum;
-    x.cum[s] = cum;
-    x.step[s] = off - prev;
-    if (s == 0) x.off0 = off;
-    prev = off;
-    cum += bs - as;
-  }
-  if (x.valid && x.zero) x.tile = (int)(local - nextra - nbusy);
-  x.f0 = x.chunk * j.chunk;
-  x.f1 = x.nch == 1 ? cum : min(cum, x.f0 + j.chunk);
-  return x;
-}
-
-// Record index of list position f of item x (a sum of selects, so that
-// the per-range values stay in registers).
-__device__ __forceinline__ uint32_t record_at(const GridItem& x, uint32_t f) {
-  uint32_t r = f + x.off0;
-#pragma unroll
-  for (int s = 1; s < kSegments; ++s) r += f >= x.cum[s] ? x.step[s] : 0u;
-  return r;
-}
-
 template <typename R>
 struct RecBatch {
   uint32_t cell;
   cplx<R> dxy, val;
 };
 
+// A work item resolved for gridding (uniform across the workgroup except
+// `first`).  The records of a tile are the concatenation of its key
+// ranges; position f of that list is record f + off0 + the sum of step[s]
+// over the ranges s >= 1 with cum[s] <= f.  The item covers positions
+// [f0, f1).  `first` is this thread's share of the item's first batch of
+// records, loaded while the previous item is still being written out
+// (loads and stores complete in order, so a load issued after a tile's
+// stores would wait for them).
+template <typename R>
+struct GridItem {
+  int valid;
+  int tile;
+  uint32_t nch;    // items the tile is split into
+  uint32_t chunk;  // which of them
+  uint32_t f0, f1;
+  uint32_t off0;
+  uint32_t cum[kSegments];
+  uint32_t step[kSegments];
+  RecBatch<R> first;
+};
+
+// Record index of list position f of item x (a sum of selects, so that
+// the per-range values stay in registers).
+template <typename R>
+__device__ __forceinline__ uint32_t record_at(const GridItem<R>& x,
+                                              uint32_t f) {
+  uint32_t r = f + x.off0;
+#pragma unroll
+  for (int s = 1; s < kSegments; ++s) r += f >= x.cum[s] ? x.step[s] : 0u;
+  return r;
+}
+
 // Loads list position f of the item; positions past the end re-read the
 // last record (so the loads need no branch) and give a zero value.
 template <typename R>
 __device__ __forceinline__ RecBatch<R> load_batch(const GridJob<R>& j,
-                                                  const GridItem& x,
+                                                  const GridItem<R>& x,
                                                   uint32_t f) {
   const bool in = f < x.f1;
   const uint32_t r = record_at(x, in ? f : x.f1 - 1);
@@ -299,12 +247,64 @@ __device__ __forceinline__ RecBatch<R> load_batch(const GridJob<R>& j,
   return b;
 }
 
-// Accumulates the item's records into the LDS tile.  Every wavefront takes
-// batches of 64 list positions, strided by the workgroup; the next batch
-// is in flight while the current one is added.
+// Resolves queue entry `local` of job j.  The loads are unconditional
+// (indices valid whatever the data), so the compiler issues them back to
+// back; the only branch is on a uniform value.
+template <typename R>
+__device__ __forceinline__ GridItem<R> prepare_item(const GridJob<R>& j,
+                                                    uint32_t local,
+                                                    uint32_t nextra,
+                                                    uint32_t total) {
+  GridItem<R> x;
+  x.valid = local < total;
+  x.tile = 0;
+  x.chunk = 0;
+  x.nch = 1;
+  x.f0 = x.f1 = 0;
+  x.off0 = 0;
+#pragma unroll
+  for (int s = 0; s < kSegments; ++s) x.cum[s] = x.step[s] = 0;
+  x.first.cell = 0;
+  x.first.dxy = x.first.val = {(R)0, (R)0};
+  if (!x.valid) return x;
+  const bool is_extra = local < nextra;
+  const uint2 tc = j.extra[is_extra ? local : 0u];
+  const uint32_t bt = j.busy[is_extra ? 0u : local - nextra];
+  x.tile = (int)uniform(is_extra ? tc.x : bt);
+  x.chunk = uniform(is_extra ? tc.y : 0u);
+  const uint32_t nch = j.tile_chunks[x.tile];
+  uint32_t lo[kSegments], hi[kSegments], a[kSegments], b[kSegments];
+  tile_segments(j.g, x.tile, lo, hi);
+#pragma unroll
+  for (int s = 0; s < kSegments; ++s) {
+    a[s] = j.offsets[lo[s]];
+    b[s] = j.offsets[hi[s]];
+  }
+  x.nch = uniform(nch);
+  uint32_t cum = 0, prev = 0;
+#pragma unroll
+  for (int s = 0; s < kSegments; ++s) {
+    const uint32_t as = uniform(a[s]), bs = uniform(b[s]);
+    const uint32_t off = as - cum;
+    x.cum[s] = cum;
+    x.step[s] = off - prev;
+    if (s == 0) x.off0 = off;
+    prev = off;
+    cum += bs - as;
+  }
+  x.f0 = x.chunk * j.chunk;
+  x.f1 = x.nch == 1 ? cum : min(cum, x.f0 + j.chunk);
+  if (x.f1 > x.f0)
+    x.first = load_batch(j, x, x.f0 + threadIdx.x);
+  return x;
+}
+
+// Accumulates the item's records into the LDS tile.  Wavefront w takes
+// list positions [f0 + 64 w, f0 + 64 w + 64), then strides by the
+// workgroup; the next batch is in flight while the current one is added.
 template <typename R, int K>
 __device__ __forceinline__ void accumulate_item(const GridJob<R>& j,
-                                                const GridItem& x,
+                                                const GridItem<R>& x,
                                                 double* s_re, double* s_im) {
   constexpr int H = (K - 1) / 2;
   constexpr int KK = K * K;
@@ -313,7 +313,7 @@ __device__ __forceinline__ void accumulate_item(const GridJob<R>& j,
   const int pitch = j.pitch;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const uint32_t step = (uint32_t)(blockDim.x >> 6) * 64u;
+  const uint32_t step = (uint32_t)blockDim.x;
   int k, oy, ox;
   tile_origin(j.g, x.tile, k, oy, ox);
   int ta[ROUNDS], tb[ROUNDS], toff[ROUNDS];
@@ -325,7 +325,7 @@ __device__ __forceinline__ void accumulate_item(const GridJob<R>& j,
     toff[q] = tb[q] * pitch + ta[q];
   }
   uint32_t b0 = x.f0 + (uint32_t)wave * 64u;
-  RecBatch<R> cur = load_batch(j, x, b0 + lane);
+  RecBatch<R> cur = x.first;
   while (b0 < x.f1) {
     const uint32_t b1 = b0 + step;
     const RecBatch<R> nxt = load_batch(j, x, b1 + lane);
@@ -356,15 +356,19 @@ __device__ __forceinline__ void accumulate_item(const GridJob<R>& j,
 
 // Writes a finished item: the whole tile (scaled by the kernel norm), or
 // one partial tile of a split tile.  Clears the LDS cells it reads.
+// A tile whose item has no records (possible only when a later call adds
+// to a tile left empty) gets zeros on a first call and nothing otherwise.
 template <typename R>
 __device__ __forceinline__ void store_item(const GridJob<R>& j,
-                                           const GridItem& x, double* s_re,
+                                           const GridItem<R>& x, double* s_re,
                                            double* s_im) {
   const int T = j.g.T;
-  if (x.nch == 1) {
-    int k, oy, ox;
-    tile_origin(j.g, x.tile, k, oy, ox);
-    cplx<R>* dst = j.planes + ((size_t)k * j.g.nv + oy) * j.g.nu + ox;
+  int k, oy, ox;
+  tile_origin(j.g, x.tile, k, oy, ox);
+  cplx<R>* dst = j.planes + ((size_t)k * j.g.nv + oy) * j.g.nu + ox;
+  if (x.f1 <= x.f0) {
+    if (x.nch == 1 && !j.accumulate) zero_tile(T, dst, (size_t)j.g.nu);
+  } else if (x.nch == 1) {
     store_tile_clear(s_re, s_im, j.pitch, T, j.g.cnorm, dst,
                      (size_t)j.g.nu, j.accumulate != 0);
   } else {
@@ -374,81 +378,58 @@ __device__ __forceinline__ void store_item(const GridJob<R>& j,
   }
 }
 
-template <typename R>
-__device__ __forceinline__ void zero_group(const GridJob<R>& j, int group) {
-  const uint32_t nidle = j.counters[5];
-  const uint32_t z0 = (uint32_t)group * kZeroGroup;
-  // All tile numbers first (unconditional loads of valid entries), so
-  // that their loads overlap.
-  uint32_t t[kZeroGroup];
-#pragma unroll
-  for (int z = 0; z < kZeroGroup; ++z) {
-    const uint32_t v = j.idle[z0 + z < nidle ? z0 + z : 0u];
-    t[z] = z0 + z < nidle ? uniform(v) : 0xFFFFFFFFu;
-  }
-#pragma unroll
-  for (int z = 0; z < kZeroGroup; ++z) {
-    if (t[z] == 0xFFFFFFFFu) continue;
-    int k, oy, ox;
-    tile_origin(j.g, (int)t[z], k, oy, ox);
-    zero_tile(j.g.T, j.planes + ((size_t)k * j.g.nv + oy) * j.g.nu + ox,
-              (size_t)j.g.nu);
-  }
-}
-
 __device__ __forceinline__ void clear_lds(double* s, uint32_t words) {
   for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) s[i] = 0.0;
 }
 
-// The first half of a work item: zero a group of idle tiles, or add the
-// item's records into the LDS tile (written out after the next barrier).
-template <typename R, int K>
-__device__ __forceinline__ void do_item(const GridJob<R>& j, const GridItem& x,
-                                        double* s_re, double* s_im) {
-  if (x.zero) {
-    zero_group(j, x.tile);
-    return;
+// Persistent loop over the items of a queue: thread 0 pops queue numbers
+// into *s_next; `resolve(n, job)` turns a number into an item and its job.
+// The next item is resolved (all its loads issued) after this item's
+// accumulation and before its global stores, which then drain while the
+// next item starts; the barriers order LDS only.
+template <typename R, int K, class Job, class Resolve>
+__device__ __forceinline__ void item_loop(double* s_lds, uint32_t* queue,
+                                          uint32_t* s_next, Job job0,
+                                          Resolve resolve) {
+  if (threadIdx.x == 0) *s_next = atomicAdd(queue, 1u);
+  lds_barrier();
+  Job job = job0;
+  GridItem<R> x = resolve(uniform(*s_next), job);
+  while (x.valid) {
+    lds_barrier();  // every thread has read *s_next; LDS is clear
+    if (threadIdx.x == 0) *s_next = atomicAdd(queue, 1u);
+    const GridJob<R>& j = *job;
+    double* s_re = s_lds;
+    double* s_im = s_lds + j.g.T * j.pitch;
+    if (x.f1 > x.f0) accumulate_item<R, K>(j, x, s_re, s_im);
+    lds_barrier();  // LDS sums complete; *s_next visible
+    Job nj = job;
+    const GridItem<R> nx = resolve(uniform(*s_next), nj);
+    store_item(j, x, s_re, s_im);
+    x = nx;
+    job = nj;
   }
-  if (x.f1 > x.f0) accumulate_item<R, K>(j, x, s_re, s_im);
 }
 
 template <typename R, int K>
 __global__ __launch_bounds__(kGridThreads) void k_grid_tiles(GridJob<R> j) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_next;
-  double* s_re = reinterpret_cast<double*>(smem);
-  double* s_im = s_re + j.g.T * j.pitch;
-  const bool with_zero = !j.accumulate;
-  const uint32_t nextra = j.counters[2], nbusy = j.counters[4];
-  const uint32_t total = item_total(j.counters, with_zero);
-  uint32_t* queue = &j.counters[3];
-  clear_lds(s_re, 2u * (uint32_t)(j.g.T * j.pitch));
-  if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
-  lds_barrier();
-  GridItem x = prepare_item(j, uniform(s_next), nextra, nbusy, total);
-  while (x.valid) {
-    lds_barrier();  // every thread has read s_next
-    if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
-    do_item<R, K>(j, x, s_re, s_im);
-    lds_barrier();  // LDS sums complete; s_next visible
-    const GridItem nx = prepare_item(j, uniform(s_next), nextra, nbusy, total);
-    if (!x.zero) {
-      if (x.f1 > x.f0)
-        store_item(j, x, s_re, s_im);
-      else if (x.nch == 1 && !j.accumulate) {
-        int k, oy, ox;
-        tile_origin(j.g, x.tile, k, oy, ox);
-        zero_tile(j.g.T, j.planes + ((size_t)k * j.g.nv + oy) * j.g.nu + ox,
-                  (size_t)j.g.nu);
-      }
-    }
-    x = nx;
-  }
+  double* s_lds = reinterpret_cast<double*>(smem);
+  const uint32_t nextra = j.counters[2];
+  const uint32_t total = item_total(j.counters);
+  clear_lds(s_lds, 2u * (uint32_t)(j.g.T * j.pitch));
+  const GridJob<R>* jp = &j;
+  item_loop<R, K>(s_lds, &j.counters[3], &s_next, jp,
+                  [&](uint32_t n, const GridJob<R>*&) {
+                    return prepare_item(j, n, nextra, total);
+                  });
 }
 
 // Batched gridding: one persistent launch drains a single queue holding the
 // work items of every job (plan), job after job; the LDS tile is sized for
-// the largest tile of the batch (lds_words FP64 words in all).
+// the largest tile of the batch (lds_words FP64 words in all).  Jobs are
+// read in place (uniform loads), never copied.
 template <typename R, int K>
 __global__ __launch_bounds__(kGridThreads) void k_grid_batch(
     const GridJob<R>* __restrict__ jobs, int njobs,
@@ -456,55 +437,66 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_batch(
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_next;
   __shared__ uint32_t s_base[kMaxBatch + 1];
-  double* s_re = reinterpret_cast<double*>(smem);
+  double* s_lds = reinterpret_cast<double*>(smem);
   if (threadIdx.x == 0) {
     uint32_t b = 0;
     for (int p = 0; p < njobs; ++p) {
       s_base[p] = b;
-      b += item_total(jobs[p].counters, !jobs[p].accumulate);
+      b += item_total(jobs[p].counters);
     }
     s_base[njobs] = b;
-    s_next = atomicAdd(queue, 1u);
   }
-  clear_lds(s_re, lds_words);
+  clear_lds(s_lds, lds_words);
   lds_barrier();
-  // Resolve a queue number to (job, item of that job); jobs are read in
-  // place (uniform loads), never copied.
-  auto resolve = [&](uint32_t item, int& p) -> GridItem {
-    item = uniform(item);
-    p = 0;
-    const bool live = item < s_base[njobs];
-    if (live)
-      while (item >= s_base[p + 1]) ++p;
-    const GridJob<R>& jj = jobs[p];
-    const uint32_t total = live ? item_total(jj.counters, !jj.accumulate) : 0u;
-    return prepare_item(jj, live ? item - s_base[p] : 0u, jj.counters[2],
-                        jj.counters[4], total);
-  };
+  item_loop<R, K>(s_lds, queue, &s_next, jobs,
+                  [&](uint32_t n, const GridJob<R>*& jp) {
+                    int p = 0;
+                    const bool live = n < s_base[njobs];
+                    if (live)
+                      while (n >= s_base[p + 1]) ++p;
+                    jp = jobs + p;
+                    const GridJob<R>& jj = *jp;
+                    const uint32_t total =
+                        live ? item_total(jj.counters) : 0u;
+                    return prepare_item(jj, live ? n - s_base[p] : 0u,
+                                        jj.counters[2], total);
+                  });
+}
+
+// Zeros of the tiles without records (first gridding call of a plan):
+// one workgroup per idle tile, 16-byte row stores.  Launched before the
+// gridding kernel; a separate kernel keeps these HBM-bound stores at full
+// rate, free of the gridder's per-item synchronisation.
+template <typename R>
+__device__ __forceinline__ void zero_idle_tile(const Geo& g,
+                                               const uint32_t* idle,
+                                               uint32_t i, cplx<R>* planes) {
+  int k, oy, ox;
+  tile_origin(g, (int)idle[i], k, oy, ox);
+  zero_tile(g.T, planes + ((size_t)k * g.nv + oy) * g.nu + ox, (size_t)g.nu);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_zero_idle(
+    Geo g, const uint32_t* __restrict__ counters,
+    const uint32_t* __restrict__ idle, cplx<R>* __restrict__ planes) {
+  if (blockIdx.x >= counters[5]) return;
+  zero_idle_tile(g, idle, blockIdx.x, planes);
+}
+
+// Batched form: block b is idle entry b - base(p) of job p, where base(p)
+// sums the tile counts of the jobs before p.
+template <typename R>
+__global__ __launch_bounds__(256) void k_zero_idle_batch(
+    const GridJob<R>* __restrict__ jobs, int njobs) {
+  uint32_t b = blockIdx.x;
   int p = 0;
-  GridItem x = resolve(s_next, p);
-  while (x.valid) {
-    lds_barrier();
-    if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
-    const GridJob<R>& j = jobs[p];
-    double* s_im = s_re + j.g.T * j.pitch;
-    do_item<R, K>(j, x, s_re, s_im);
-    lds_barrier();
-    int pn = 0;
-    const GridItem nx = resolve(s_next, pn);
-    if (!x.zero) {
-      if (x.f1 > x.f0)
-        store_item(j, x, s_re, s_im);
-      else if (x.nch == 1 && !j.accumulate) {
-        int k, oy, ox;
-        tile_origin(j.g, x.tile, k, oy, ox);
-        zero_tile(j.g.T, j.planes + ((size_t)k * j.g.nv + oy) * j.g.nu + ox,
-                  (size_t)j.g.nu);
-      }
-    }
-    x = nx;
-    p = pn;
+  while (p < njobs && b >= (uint32_t)jobs[p].g.ntiles) {
+    b -= (uint32_t)jobs[p].g.ntiles;
+    ++p;
   }
+  if (p >= njobs || b >= jobs[p].counters[5]) return;
+  zero_idle_tile(jobs[p].g, jobs[p].idle, b, jobs[p].planes);
 }
 
 template <typename R>
@@ -564,7 +556,7 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(
   const int W = T + 2 * H;
   const R cn = (R)g.cnorm;
   Item it;
-  while (next_item(counters, counters, extra, busy, false, &s_item, it)) {
+  while (next_item(counters, counters, extra, busy, &s_item, it)) {
     const int t = it.tile;
     const uint32_t c = it.chunk;
     int k, oy, ox;
@@ -702,6 +694,22 @@ void launch_grid_batch(const GridJob<R>* jobs, int njobs, int K, size_t lds,
 }
 
 template <typename R>
+void launch_zero_idle(const Geo& g, const uint32_t* counters,
+                      const uint32_t* idle, void* planes, hipStream_t st) {
+  if (g.ntiles <= 0) return;
+  hipLaunchKernelGGL(k_zero_idle<R>, dim3((unsigned)g.ntiles), dim3(256), 0,
+                     st, g, counters, idle, (cplx<R>*)planes);
+}
+
+template <typename R>
+void launch_zero_idle_batch(const GridJob<R>* jobs, int njobs,
+                            uint64_t total_tiles, hipStream_t st) {
+  if (total_tiles == 0) return;
+  hipLaunchKernelGGL(k_zero_idle_batch<R>, dim3((unsigned)total_tiles),
+                     dim3(256), 0, st, jobs, njobs);
+}
+
+template <typename R>
 void launch_grid_merge(const Geo& g, const uint32_t* counters,
                        const uint32_t* split_list, const uint32_t* tile_chunks,
                        const uint32_t* tile_slot, const void* partials,
@@ -740,6 +748,10 @@ size_t degrid_lds_bytes(int T, int K, int elem_bytes) {
   template void launch_grid_batch<R>(const GridJob<R>*, int, int, size_t,  \
                                      uint32_t*, uint32_t, int,             \
                                      hipStream_t);                         \
+  template void launch_zero_idle<R>(const Geo&, const uint32_t*,           \
+                                    const uint32_t*, void*, hipStream_t);  \
+  template void launch_zero_idle_batch<R>(const GridJob<R>*, int, uint64_t, \
+                                          hipStream_t);                    \
   template void launch_grid_merge<R>(const Geo&, const uint32_t*,          \
                                      const uint32_t*, const uint32_t*,     \
                                      const uint32_t*, const void*, void*,  \

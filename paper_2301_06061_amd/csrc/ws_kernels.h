@@ -46,7 +46,7 @@ struct GridJob {
                               // [4] busy tiles, [5] idle tiles
   const uint2* extra;         // (tile, chunk) of the further chunks
   const uint32_t* busy;       // tiles with records ([4] of them)
-  const uint32_t* idle;       // tiles without ([5]), zeroed in groups
+  const uint32_t* idle;       // tiles without ([5]), zeroed separately
   const uint32_t* tile_chunks;
   const uint32_t* tile_slot;
   const uint32_t* rec_cell;
@@ -65,6 +65,12 @@ template <typename R>
 void launch_grid_batch(const GridJob<R>* jobs, int njobs, int K, size_t lds,
                        uint32_t* queue, uint32_t max_items, int cus,
                        hipStream_t st);
+template <typename R>
+void launch_zero_idle(const Geo& g, const uint32_t* counters,
+                      const uint32_t* idle, void* planes, hipStream_t st);
+template <typename R>
+void launch_zero_idle_batch(const GridJob<R>* jobs, int njobs,
+                            uint64_t total_tiles, hipStream_t st);
 template <typename R>
 void launch_grid_merge(const Geo& g, const uint32_t* counters,
                        const uint32_t* split_list, const uint32_t* tile_chunks,
