@@ -60,7 +60,7 @@ struct Layout {
   // workspace offsets
   size_t o_tw_u, o_tw_v, o_counts, o_sums, o_keyrank, o_cell, o_dxy, o_val,
       o_idx, o_chunks, o_slot, o_counters, o_split, o_extra, o_busy, o_idle,
-      o_partials, o_scratch, total;
+      o_strips, o_partials, o_scratch, total;
 };
 
 ws_status check_params(const ws_params* p) {
@@ -168,6 +168,9 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   L->o_extra = take((size_t)L->max_extra * 8);
   L->o_busy = take((size_t)L->ntiles * 4);
   L->o_idle = take((size_t)L->ntiles * 4);
+  // Column strips (T columns of one plane) that some gridding call since
+  // the reset wrote records into.
+  L->o_strips = take((size_t)p->nw * (p->nu / L->T) * 4);
   L->o_partials = take((size_t)L->max_slots * L->T * L->T * L->elem);
   // One plane of scratch for the natural-order output of ws_fft_planes
   // when columns use the four-step transform.
@@ -284,10 +287,13 @@ ws_status zero_planes(ws_plan* pl) {
 
 // Binning shared by gridding and degridding: counts, offsets, records and
 // the per-tile work items.  Returns the grid size bound for the item kernel.
+// For gridding, `strips` (cleared first when clear_strips) gets a mark for
+// every column strip that holds a tile with records.
 template <typename R>
 ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
                       const void* vis, const float* weight, int degrid,
-                      int64_t* n_dropped, uint32_t* max_items) {
+                      int64_t* n_dropped, uint32_t* max_items,
+                      uint32_t* strips = nullptr, bool clear_strips = false) {
   const Layout& L = pl->L;
   const Geo& g = pl->g;
   hipStream_t st = pl->stream;
@@ -302,6 +308,8 @@ ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
   WS_TRY(launch(pl, "zero_counts", [&] {
     launch_zero_u32(counts, L.nkeys + 1, st);
     launch_zero_u32(counters, 16, st);
+    if (strips != nullptr && clear_strips)
+      launch_zero_u32(strips, (int64_t)g.nw * g.tiles_u, st);
   }));
   WS_TRY(launch(pl, "bin_count", [&] {
     launch_bin_count(g, uvw, m, counts, keyrank,
@@ -319,7 +327,8 @@ ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
   WS_TRY(launch(pl, "tile_work", [&] {
     launch_tile_work(g, counts, degrid, chunk, chunks, slot, counters, split,
                      L.max_slots, pl->w<uint2>(L.o_extra), L.max_extra,
-                     pl->w<uint32_t>(L.o_busy), pl->w<uint32_t>(L.o_idle), st);
+                     pl->w<uint32_t>(L.o_busy), pl->w<uint32_t>(L.o_idle),
+                     strips, st);
   }));
   // Items: one per tile plus the further chunks of split tiles.
   const int64_t reads = degrid ? m : 4 * m;
@@ -368,8 +377,9 @@ template <typename R>
 ws_status grid_impl(ws_plan* pl, int64_t m, const double* uvw, const void* vis,
                     const float* weight, int64_t* n_dropped) {
   uint32_t max_items = 0;
-  WS_TRY(bin_records<R>(pl, m, uvw, vis, weight, 0, n_dropped, &max_items));
   const int acc = pl->state == kGridded ? 1 : 0;
+  WS_TRY(bin_records<R>(pl, m, uvw, vis, weight, 0, n_dropped, &max_items,
+                        pl->w<uint32_t>(pl->L.o_strips), !acc));
   const GridJob<R> j = make_job<R>(pl, acc);
   if (!acc) {
     // First call since the reset: tiles without records get their zeros.
@@ -388,20 +398,26 @@ ws_status grid_impl(ws_plan* pl, int64_t m, const double* uvw, const void* vis,
 // Column transform of every plane: one pass for columns up to
 // kOnePassCols, else the four-step transform, which leaves the rows in the
 // transposed order described by the returned geometry.
+// With `strips` (marks of the column strips that hold records), strips
+// without marks are skipped: gridding left them zero, and so is their
+// transform.
 template <typename R>
-ws_status cols_impl(ws_plan* pl, int sign, Geo* gout) {
+ws_status cols_impl(ws_plan* pl, int sign, Geo* gout,
+                    const uint32_t* strips = nullptr) {
   const ws_params& p = pl->p;
   bool ok = true;
   Geo g = pl->g;
   if (p.nv <= kOnePassCols) {
     WS_TRY(launch(pl, "fft_cols", [&] {
       ok = launch_fft_cols<R>(pl->planes, p.nv, p.nu, p.nw,
-                              pl->work + pl->L.o_tw_v, sign, pl->stream);
+                              pl->work + pl->L.o_tw_v, sign, strips, g.T,
+                              pl->stream);
     }));
   } else {
     WS_TRY(launch(pl, "fft_cols4", [&] {
       ok = launch_fft_cols4<R>(pl->planes, p.nv, p.nu, p.nw,
-                               pl->work + pl->L.o_tw_v, sign, pl->stream);
+                               pl->work + pl->L.o_tw_v, sign, strips, g.T,
+                               pl->stream);
     }));
     int lg = 0;
     while ((1 << lg) < p.nv) ++lg;
@@ -447,11 +463,13 @@ ws_status fft_impl(ws_plan* pl, int sign) {
   return WS_OK;
 }
 
+// The stack holds what the gridding calls since the reset wrote, so the
+// column strips they never reached are skipped.
 template <typename R>
 ws_status image_impl(ws_plan* pl, void* image) {
   const ws_params& p = pl->p;
   Geo g;
-  WS_TRY(cols_impl<R>(pl, +1, &g));
+  WS_TRY(cols_impl<R>(pl, +1, &g, pl->w<uint32_t>(pl->L.o_strips)));
   if (g.perm_n1 == 0 && p.nu <= kFusedRows) {
     bool ok = true;
     WS_TRY(launch(pl, "row_screen_sum", [&] {
@@ -561,7 +579,8 @@ ws_status batch_image_impl(ws_batch* b, const int64_t* m,
     pl->state = kEmpty;
     uint32_t mi = 0;
     WS_TRY(bin_records<R>(pl, m[i], uvw[i], vis[i], weight ? weight[i] : nullptr,
-                          0, nullptr, &mi));
+                          0, nullptr, &mi, pl->w<uint32_t>(pl->L.o_strips),
+                          true));
     items += mi;
   }
   ws_plan* p0 = b->plans[0];

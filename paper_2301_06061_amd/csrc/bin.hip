@@ -232,7 +232,8 @@ __global__ __launch_bounds__(256) void k_tile_work(
     uint32_t* __restrict__ tile_slot, uint32_t* __restrict__ counters,
     uint32_t* __restrict__ split_list, uint32_t max_slots,
     uint2* __restrict__ extra, uint32_t max_extra,
-    uint32_t* __restrict__ busy, uint32_t* __restrict__ idle) {
+    uint32_t* __restrict__ busy, uint32_t* __restrict__ idle,
+    uint32_t* __restrict__ strips) {
   // counters[0]: scratch slots taken, [1]: split tiles, [2]: extra items,
   // [4]: tiles with records (listed in busy), [5]: tiles without (idle).
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -255,6 +256,13 @@ __global__ __launch_bounds__(256) void k_tile_work(
   if (!live) return;
   if (work > 0) busy[ib] = (uint32_t)t;
   else idle[ii] = (uint32_t)t;
+  if (work > 0 && strips != nullptr) {
+    // Column strip of this tile: plane k, tile column tx.
+    const int per_plane = g.tiles_u * g.tiles_v;
+    const int k = t / per_plane;
+    const int tx = (t - k * per_plane) % g.tiles_u;
+    strips[k * g.tiles_u + tx] = 1u;
+  }
   uint32_t nch = work == 0 ? 1u : (work + chunk - 1) / chunk;
   tile_slot[t] = 0;
   if (nch > 1 && !mode_degrid) {
@@ -330,11 +338,12 @@ void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t* tile_slot, uint32_t* counters,
                       uint32_t* split_list, uint32_t max_slots, uint2* extra,
                       uint32_t max_extra, uint32_t* busy, uint32_t* idle,
-                      hipStream_t st) {
+                      uint32_t* strips, hipStream_t st) {
   const int nb = (g.ntiles + 255) / 256;
   hipLaunchKernelGGL(k_tile_work, dim3(nb), dim3(256), 0, st, g, offsets,
                      mode_degrid, chunk, tile_chunks, tile_slot, counters,
-                     split_list, max_slots, extra, max_extra, busy, idle);
+                     split_list, max_slots, extra, max_extra, busy, idle,
+                     strips);
 }
 
 }  // namespace ws

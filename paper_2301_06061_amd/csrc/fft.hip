@@ -6,8 +6,8 @@
 // the last writes HBM directly, so a transform costs one read and one write
 // of its line.  Rows are transformed one per workgroup; columns in blocks of
 // BC adjacent columns per workgroup (BC * 8 or 16 bytes per row segment),
-// with the blocks of one XCD covering adjacent columns so that the partial
-// cache lines of a segment are shared in that XCD's L2.  The centring
+// with the blocks that share a cache line placed on one XCD so that the
+// partial lines are merged in that XCD's L2.  The centring
 // (DC at N/2 in both domains) is a (-1)^index sign on input and output,
 // valid for every N divisible by 4.  Twiddles e^{2 pi i t/N} come from
 // tables computed in FP64 once per plan.
@@ -277,23 +277,38 @@ __global__ __launch_bounds__(NT) void k_fft_rows_split(
   fft_line<R, LOGH, 1, NT>(lds, ld_diff, st_odd, twl, s);
 }
 
+// Logical column block of hardware block b.  Blocks are dispatched to the
+// eight XCDs in turn (b % 8); the G logical blocks that share one 128-byte
+// line of every row are given to one XCD (they then share its L2), and
+// successive groups go to successive XCDs, so every XCD holds an equal
+// share of every plane (planes can differ widely in how many of their
+// column strips are skipped).  Grids that are not a multiple of 8 G blocks
+// keep the identity order.
+template <typename R, int BC>
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  constexpr int W = BC * (int)sizeof(cplx<R>);
+  constexpr int G = W >= 128 ? 1 : 128 / W;
+  if (nb % (8 * G) != 0) return b;
+  const int x = b % 8, n = b / 8;
+  return ((n / G) * 8 + x) * G + n % G;
+}
+
 template <typename R, int LOGN, int BC, int NT>
-__global__ __launch_bounds__(NT) void k_fft_cols(cplx<R>* data, int ncols,
-                                                 int nplanes,
-                                                 const cplx<R>* __restrict__ tw,
-                                                 R s) {
+__global__ __launch_bounds__(NT) void k_fft_cols(
+    cplx<R>* data, int ncols, int nplanes, const cplx<R>* __restrict__ tw, R s,
+    const uint32_t* __restrict__ strips, int strip_w) {
   constexpr int N = 1 << LOGN;  // column length = number of rows
   __shared__ cplx<R> lds[lds_line<N>(BC)];
   __shared__ cplx<R> s_lo[kTwLo], s_hi[(N + kTwLo - 1) / kTwLo];
-  // XCD-aware order: the blocks one XCD runs (b, b+8, ...) take adjacent
-  // column blocks of the same plane.
   const int nb_plane = ncols / BC;
   const int nb = nb_plane * nplanes;
-  const int per_xcd = (nb + 7) / 8;
-  const int L = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const int L = xcd_block<R, BC>((int)blockIdx.x, nb);
   if (L >= nb) return;
   const int plane = L / nb_plane;
   const int col0 = (L - plane * nb_plane) * BC;
+  if (strips != nullptr &&
+      strips[plane * (ncols / strip_w) + col0 / strip_w] == 0u)
+    return;
   cplx<R>* base = data + (size_t)plane * N * ncols + col0;
   auto ld = [&](int e, int c, int, int) {
     return checker(base[(size_t)e * ncols + c], e);
@@ -317,22 +332,23 @@ __global__ __launch_bounds__(NT) void k_fft_cols(cplx<R>* data, int ncols,
 // that stack_row() undoes.
 
 template <typename R, int LOG1, int LOG2, int BC, int NT>
-__global__ __launch_bounds__(NT) void k_fft_colA(cplx<R>* data, int ncols,
-                                                 int nplanes,
-                                                 const cplx<R>* __restrict__ tw,
-                                                 R s) {
+__global__ __launch_bounds__(NT) void k_fft_colA(
+    cplx<R>* data, int ncols, int nplanes, const cplx<R>* __restrict__ tw, R s,
+    const uint32_t* __restrict__ strips, int strip_w) {
   constexpr int N1 = 1 << LOG1, N2 = 1 << LOG2, N = N1 * N2;
   __shared__ cplx<R> lds[lds_line<N1>(BC)];
   __shared__ cplx<R> s_lo[kTwLo], s_hi[(N1 + kTwLo - 1) / kTwLo];
   const int ncb = ncols / BC;
   const int nb = ncb * N2 * nplanes;
-  const int per_xcd = (nb + 7) / 8;
-  const int L = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const int L = xcd_block<R, BC>((int)blockIdx.x, nb);
   if (L >= nb) return;
   const int cb = L % ncb;
   const int rest = L / ncb;
   const int n2 = rest % N2;
   const int plane = rest / N2;
+  if (strips != nullptr &&
+      strips[plane * (ncols / strip_w) + cb * BC / strip_w] == 0u)
+    return;
   cplx<R>* base = data + (size_t)plane * N * ncols + (size_t)cb * BC;
   const Twiddles<R> twl = load_twiddles_sub(s_lo, s_hi, tw, N1, N);
   __syncthreads();
@@ -349,22 +365,23 @@ __global__ __launch_bounds__(NT) void k_fft_colA(cplx<R>* data, int ncols,
 }
 
 template <typename R, int LOG1, int LOG2, int BC, int NT>
-__global__ __launch_bounds__(NT) void k_fft_colB(cplx<R>* data, int ncols,
-                                                 int nplanes,
-                                                 const cplx<R>* __restrict__ tw,
-                                                 R s) {
+__global__ __launch_bounds__(NT) void k_fft_colB(
+    cplx<R>* data, int ncols, int nplanes, const cplx<R>* __restrict__ tw, R s,
+    const uint32_t* __restrict__ strips, int strip_w) {
   constexpr int N1 = 1 << LOG1, N2 = 1 << LOG2, N = N1 * N2;
   __shared__ cplx<R> lds[lds_line<N2>(BC)];
   __shared__ cplx<R> s_lo[kTwLo], s_hi[(N2 + kTwLo - 1) / kTwLo];
   const int ncb = ncols / BC;
   const int nb = ncb * N1 * nplanes;
-  const int per_xcd = (nb + 7) / 8;
-  const int L = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const int L = xcd_block<R, BC>((int)blockIdx.x, nb);
   if (L >= nb) return;
   const int cb = L % ncb;
   const int rest = L / ncb;
   const int k1 = rest % N1;
   const int plane = rest / N1;
+  if (strips != nullptr &&
+      strips[plane * (ncols / strip_w) + cb * BC / strip_w] == 0u)
+    return;
   cplx<R>* base = data + (size_t)plane * N * ncols + (size_t)k1 * N2 * ncols +
                   (size_t)cb * BC;
   const Twiddles<R> twl = load_twiddles_sub(s_lo, s_hi, tw, N2, N);
@@ -410,10 +427,11 @@ __device__ __forceinline__ double n_minus_one(const Geo& g, int p, int q) {
 // by plane (k = 0, 1, ... in order).  The phase w_k (n - 1) is formed and
 // reduced to [-1/2, 1/2] turn in FP64 on both paths.  The FP64 path seeds
 // an FP64 phasor with sincospi and advances it by an FP64 complex multiply
-// per plane; the FP32 path evaluates each plane's phasor directly with
-// FP32 sincospi of the reduced phase (error about 1e-7, the order of the
-// FP32 transform's own), which keeps two registers of state per pixel
-// instead of eight.
+// per plane; the FP32 path evaluates each plane's phasor directly from
+// the reduced phase with the hardware sine and cosine, whose argument is
+// in turns (measured maximum error 1.3e-7 over [-1/2, 1/2] turn, the order
+// of the FP32 transform's own), which keeps two registers of state per
+// pixel instead of eight and costs two instructions.
 template <typename R>
 struct Screen;
 
@@ -446,9 +464,7 @@ struct Screen<float> {
   __device__ __forceinline__ cplx<float> next(const Geo& g, int k) {
     const double a = (g.w0 + (double)k * g.dw) * nm1;
     const float f = (float)(a - rint(a));
-    float sn, cs;
-    sincospif(2.0f * f, &sn, &cs);
-    return {cs, sn};
+    return {__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f)};
   }
 };
 
@@ -664,7 +680,7 @@ bool rows_t(cplx<R>* data, int64_t nrows, const cplx<R>* tw, R s,
 
 template <typename R, int LOGN>
 bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
-            hipStream_t st) {
+            const uint32_t* strips, int strip_w, hipStream_t st) {
   if constexpr (LOGN > 12) {
     return false;
   } else {
@@ -677,15 +693,16 @@ bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
   constexpr int NT = (N * BC) / 8 < 64 ? 64 : ((N * BC) / 8 > 1024 ? 1024 : (N * BC) / 8);
   const int nb = (ncols / BC) * nplanes;
   const int grid = ((nb + 7) / 8) * 8;
+  if (strips != nullptr && strip_w % BC != 0) strips = nullptr;
   hipLaunchKernelGGL((k_fft_cols<R, LOGN, BC, NT>), dim3(grid), dim3(NT), 0,
-                     st, data, ncols, nplanes, tw, s);
+                     st, data, ncols, nplanes, tw, s, strips, strip_w);
   return true;
   }
 }
 
 template <typename R, int LOGN>
 bool cols4_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
-             hipStream_t st) {
+             const uint32_t* strips, int strip_w, hipStream_t st) {
   if constexpr (LOGN < 6) {
     return false;
   } else {
@@ -696,12 +713,13 @@ bool cols4_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
     const int ncb = ncols / BC;
     const int nba = ncb * (1 << LOG2) * nplanes;
     const int nbb = ncb * (1 << LOG1) * nplanes;
+    if (strips != nullptr && strip_w % BC != 0) strips = nullptr;
     hipLaunchKernelGGL((k_fft_colA<R, LOG1, LOG2, BC, NTA>),
                        dim3(((nba + 7) / 8) * 8), dim3(NTA), 0, st, data,
-                       ncols, nplanes, tw, s);
+                       ncols, nplanes, tw, s, strips, strip_w);
     hipLaunchKernelGGL((k_fft_colB<R, LOG1, LOG2, BC, NTB>),
                        dim3(((nbb + 7) / 8) * 8), dim3(NTB), 0, st, data,
-                       ncols, nplanes, tw, s);
+                       ncols, nplanes, tw, s, strips, strip_w);
     return true;
   }
 }
@@ -774,11 +792,13 @@ bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw, int sign,
 
 template <typename R>
 bool launch_fft_cols(void* data, int nrows, int ncols, int nplanes,
-                     const void* tw, int sign, hipStream_t st) {
+                     const void* tw, int sign, const uint32_t* strips,
+                     int strip_w, hipStream_t st) {
   const int lg = ilog2(nrows);
   bool ok = false;
   WS_LOGN_SWITCH(lg, (ok = cols_t<R, LG>((cplx<R>*)data, ncols, nplanes,
-                                         (const cplx<R>*)tw, (R)sign, st)));
+                                         (const cplx<R>*)tw, (R)sign, strips,
+                                         strip_w, st)));
   return ok;
 }
 
@@ -806,11 +826,13 @@ bool launch_screen_row_bcast(const void* img, int img_real, void* planes,
 
 template <typename R>
 bool launch_fft_cols4(void* data, int nrows, int ncols, int nplanes,
-                      const void* tw, int sign, hipStream_t st) {
+                      const void* tw, int sign, const uint32_t* strips,
+                      int strip_w, hipStream_t st) {
   const int lg = ilog2(nrows);
   bool ok = false;
   WS_LOGN_SWITCH(lg, (ok = cols4_t<R, LG>((cplx<R>*)data, ncols, nplanes,
-                                          (const cplx<R>*)tw, (R)sign, st)));
+                                          (const cplx<R>*)tw, (R)sign, strips,
+                                          strip_w, st)));
   return ok;
 }
 
@@ -864,7 +886,7 @@ void launch_twiddles(void* tw, int n, hipStream_t st) {
   template bool launch_fft_rows<R>(void*, int, int64_t, const void*, int,    \
                                    hipStream_t);                             \
   template bool launch_fft_cols<R>(void*, int, int, int, const void*, int,   \
-                                   hipStream_t);                             \
+                                   const uint32_t*, int, hipStream_t);       \
   template bool launch_row_screen_sum<R>(const void*, void*, const Geo&,     \
                                          const void*, hipStream_t);          \
   template bool launch_screen_row_bcast<R>(const void*, int, void*,          \
@@ -873,7 +895,7 @@ void launch_twiddles(void* tw, int n, hipStream_t st) {
   template void launch_wcorrect<R>(const void*, void*, const Geo&,           \
                                    hipStream_t);                             \
   template bool launch_fft_cols4<R>(void*, int, int, int, const void*, int,  \
-                                    hipStream_t);                            \
+                                    const uint32_t*, int, hipStream_t);      \
   template void launch_unpermute_rows<R>(const void*, void*, const Geo&,     \
                                          hipStream_t);                       \
   template void launch_screen_bcast<R>(const void*, int, void*, const Geo&,  \

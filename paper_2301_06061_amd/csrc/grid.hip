@@ -231,20 +231,31 @@ __device__ __forceinline__ uint32_t record_at(const GridItem<R>& x,
   return r;
 }
 
-// Loads list position f of the item; positions past the end re-read the
-// last record (so the loads need no branch) and give a zero value.
+// Loads list position f of the item for a share that ends at `end`;
+// positions past the end re-read the share's last record (so the loads
+// need no branch) and give a zero value.
 template <typename R>
 __device__ __forceinline__ RecBatch<R> load_batch(const GridJob<R>& j,
                                                   const GridItem<R>& x,
-                                                  uint32_t f) {
-  const bool in = f < x.f1;
-  const uint32_t r = record_at(x, in ? f : x.f1 - 1);
+                                                  uint32_t f, uint32_t end) {
+  const bool in = f < end;
+  const uint32_t r = record_at(x, in ? f : end - 1);
   RecBatch<R> b;
   b.cell = j.rec_cell[r];
   b.dxy = j.rec_dxy[r];
   b.val = j.rec_val[r];
   if (!in) b.val = {(R)0, (R)0};
   return b;
+}
+
+// Share of wavefront w (of nw) in the item's list positions [f0, f1):
+// consecutive runs of equal length, so that every wavefront has work even
+// in a tile with few records.
+__device__ __forceinline__ void wave_share(uint32_t f0, uint32_t f1, int w,
+                                           int nw, uint32_t& b, uint32_t& e) {
+  const uint32_t q = (f1 - f0 + (uint32_t)nw - 1) / (uint32_t)nw;
+  b = f0 + (uint32_t)w * q;
+  e = min(b + q, f1);
 }
 
 // Resolves queue entry `local` of job j.  The loads are unconditional
@@ -294,14 +305,48 @@ __device__ __forceinline__ GridItem<R> prepare_item(const GridJob<R>& j,
   }
   x.f0 = x.chunk * j.chunk;
   x.f1 = x.nch == 1 ? cum : min(cum, x.f0 + j.chunk);
-  if (x.f1 > x.f0)
-    x.first = load_batch(j, x, x.f0 + threadIdx.x);
+  if (x.f1 > x.f0) {
+    uint32_t b, e;
+    wave_share(x.f0, x.f1, threadIdx.x >> 6, blockDim.x >> 6, b, e);
+    x.first = load_batch(j, x, b + (threadIdx.x & 63), e);
+  }
   return x;
 }
 
-// Accumulates the item's records into the LDS tile.  Wavefront w takes
-// list positions [f0 + 64 w, f0 + 64 w + 64), then strides by the
-// workgroup; the next batch is in flight while the current one is added.
+// Adds one record (held in lane r of the batch registers) to the LDS tile:
+// lane t of the wavefront covers kernel tap t (and t + 64, ... for K > 7).
+template <typename R, int K>
+__device__ __forceinline__ void add_record(const Geo& g, const RecBatch<R>& c,
+                                           int r, int ox, int oy, int T,
+                                           int pitch, const int* ta,
+                                           const int* tb, const int* toff,
+                                           double* s_re, double* s_im) {
+  constexpr int KK = K * K;
+  constexpr int ROUNDS = (KK + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const uint32_t cc = bcast_u(c.cell, r);
+  const R dx = bcast(c.dxy.re, r), dy = bcast(c.dxy.im, r);
+  const R vr = bcast(c.val.re, r), vi = bcast(c.val.im, r);
+  const int ci = cell_i(cc) - ox, cj = cell_j(cc) - oy;
+  const int base = cj * pitch + ci;
+#pragma unroll
+  for (int q = 0; q < ROUNDS; ++q) {
+    if (KK % 64 == 0 || lane + 64 * q < KK) {
+      const int li = ci + ta[q], lj = cj + tb[q];
+      if ((unsigned)li < (unsigned)T && (unsigned)lj < (unsigned)T) {
+        const R ex = (R)ta[q] - dx, ey = (R)tb[q] - dy;
+        const R w = gauss2(g, ex * ex + ey * ey);
+        atomicAdd(s_re + base + toff[q], (double)(w * vr));
+        atomicAdd(s_im + base + toff[q], (double)(w * vi));
+      }
+    }
+  }
+}
+
+// Accumulates the item's records into the LDS tile.  Each wavefront takes
+// an equal run of the item's list positions, 64 at a time (one per lane),
+// with the next 64 in flight while the current ones are added two at a
+// time (two independent chains of instructions).
 template <typename R, int K>
 __device__ __forceinline__ void accumulate_item(const GridJob<R>& j,
                                                 const GridItem<R>& x,
@@ -312,8 +357,6 @@ __device__ __forceinline__ void accumulate_item(const GridJob<R>& j,
   const int T = j.g.T;
   const int pitch = j.pitch;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const uint32_t step = (uint32_t)blockDim.x;
   int k, oy, ox;
   tile_origin(j.g, x.tile, k, oy, ox);
   int ta[ROUNDS], tb[ROUNDS], toff[ROUNDS];
@@ -324,31 +367,23 @@ __device__ __forceinline__ void accumulate_item(const GridJob<R>& j,
     tb[q] = tt / K - H;
     toff[q] = tb[q] * pitch + ta[q];
   }
-  uint32_t b0 = x.f0 + (uint32_t)wave * 64u;
+  uint32_t b0, e;
+  wave_share(x.f0, x.f1, threadIdx.x >> 6, blockDim.x >> 6, b0, e);
   RecBatch<R> cur = x.first;
-  while (b0 < x.f1) {
-    const uint32_t b1 = b0 + step;
-    const RecBatch<R> nxt = load_batch(j, x, b1 + lane);
-    const int cnt = (x.f1 - b0) < 64u ? (int)(x.f1 - b0) : 64;
-    for (int r = 0; r < cnt; ++r) {
-      const uint32_t cc = bcast_u(cur.cell, r);
-      const R dx = bcast(cur.dxy.re, r), dy = bcast(cur.dxy.im, r);
-      const R vr = bcast(cur.val.re, r), vi = bcast(cur.val.im, r);
-      const int ci = cell_i(cc) - ox, cj = cell_j(cc) - oy;
-      const int base = cj * pitch + ci;
-#pragma unroll
-      for (int q = 0; q < ROUNDS; ++q) {
-        if (KK % 64 == 0 || lane + 64 * q < KK) {
-          const int li = ci + ta[q], lj = cj + tb[q];
-          if ((unsigned)li < (unsigned)T && (unsigned)lj < (unsigned)T) {
-            const R ex = (R)ta[q] - dx, ey = (R)tb[q] - dy;
-            const R w = gauss2(j.g, ex * ex + ey * ey);
-            atomicAdd(s_re + base + toff[q], (double)(w * vr));
-            atomicAdd(s_im + base + toff[q], (double)(w * vi));
-          }
-        }
-      }
+  while (b0 < e) {
+    const uint32_t b1 = b0 + 64u;
+    const RecBatch<R> nxt = load_batch(j, x, b1 + lane, e);
+    const int cnt = (e - b0) < 64u ? (int)(e - b0) : 64;
+    int r = 0;
+    for (; r + 1 < cnt; r += 2) {
+      add_record<R, K>(j.g, cur, r, ox, oy, T, pitch, ta, tb, toff, s_re,
+                       s_im);
+      add_record<R, K>(j.g, cur, r + 1, ox, oy, T, pitch, ta, tb, toff, s_re,
+                       s_im);
     }
+    if (r < cnt)
+      add_record<R, K>(j.g, cur, r, ox, oy, T, pitch, ta, tb, toff, s_re,
+                       s_im);
     cur = nxt;
     b0 = b1;
   }

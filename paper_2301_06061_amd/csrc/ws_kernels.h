@@ -29,7 +29,7 @@ void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t* tile_slot, uint32_t* counters,
                       uint32_t* split_list, uint32_t max_slots, uint2* extra,
                       uint32_t max_extra, uint32_t* busy, uint32_t* idle,
-                      hipStream_t st);
+                      uint32_t* strips, hipStream_t st);
 
 // gridding and degridding (grid.hip)
 int grid_lds_pitch(int T, int K);
@@ -92,9 +92,12 @@ bool fft_supported(int n, int elem_bytes);
 template <typename R>
 bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw,
                      int sign, hipStream_t st);
+// Column transforms; with `strips` non-null, the blocks of column strips
+// (strip_w columns of one plane) whose mark is zero are skipped.
 template <typename R>
 bool launch_fft_cols(void* data, int nrows, int ncols, int nplanes,
-                     const void* tw, int sign, hipStream_t st);
+                     const void* tw, int sign, const uint32_t* strips,
+                     int strip_w, hipStream_t st);
 template <typename R>
 bool launch_row_screen_sum(const void* planes, void* img, const Geo& g,
                            const void* tw_u, hipStream_t st);
@@ -103,7 +106,8 @@ bool launch_screen_row_bcast(const void* img, int img_real, void* planes,
                              const Geo& g, const void* tw_u, hipStream_t st);
 template <typename R>
 bool launch_fft_cols4(void* data, int nrows, int ncols, int nplanes,
-                      const void* tw, int sign, hipStream_t st);
+                      const void* tw, int sign, const uint32_t* strips,
+                      int strip_w, hipStream_t st);
 template <typename R>
 void launch_unpermute_rows(const void* src, void* dst, const Geo& g,
                            hipStream_t st);

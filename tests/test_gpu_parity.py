@@ -228,6 +228,37 @@ def test_grid_is_additive_over_calls(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_image_over_calls_and_reset_skips_only_empty_strips(precision):
+    """The image path transforms only the column strips that gridding calls
+    since the reset reached: two calls on opposite halves of the uv plane,
+    then a reset and a call on one quarter, each imaged against the
+    oracle."""
+    wl = _case(dict(n=256, nw=4, support=7, m=6000, law="gauss"), precision,
+               seed=31)
+    p = o.Params.of(wl)
+    plan = plan_for(wl, tile=32)
+    uvw, vis, wt = dev(wl)
+    left = wl.uvw[:, 0] < 0
+    il = torch.from_numpy(np.nonzero(left)[0]).to("cuda")
+    ir = torch.from_numpy(np.nonzero(~left)[0]).to("cuda")
+    plan.grid(uvw[il], vis[il], wt[il])
+    plan.grid(uvw[ir], vis[ir], wt[ir])
+    img = plan.new_image()
+    plan.image_accumulate(img)
+    assert_close(host(img), o.image(p, wl.uvw, wl.vis, wl.weight),
+                 precision == "fp64", "two calls")
+    quarter = (wl.uvw[:, 0] > 0) & (wl.uvw[:, 1] > 0)
+    iq = torch.from_numpy(np.nonzero(quarter)[0]).to("cuda")
+    plan.reset()
+    plan.grid(uvw[iq], vis[iq], wt[iq])
+    img = plan.new_image()
+    plan.image_accumulate(img)
+    assert_close(host(img), o.image(p, wl.uvw[quarter], wl.vis[quarter],
+                                    wl.weight[quarter]),
+                 precision == "fp64", "after reset")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("chunk", [64, 333, 0])
 def test_hot_bin_split_and_merge(precision, chunk):
     """Every visibility within a few cells of one point: tiles split into
