@@ -58,8 +58,8 @@ struct Layout {
   uint32_t max_extra;
   size_t planes_bytes;
   // workspace offsets
-  size_t o_tw_u, o_tw_v, o_counts, o_sums, o_keyrank, o_cell, o_dxy, o_val,
-      o_idx, o_chunks, o_slot, o_counters, o_split, o_extra, o_busy, o_idle,
+  size_t o_tw_u, o_tw_v, o_counts, o_sums, o_keyrank, o_rec, o_chunks,
+      o_slot, o_counters, o_split, o_extra, o_busy, o_idle,
       o_strips, o_partials, o_scratch, total;
 };
 
@@ -157,10 +157,9 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   L->o_counts = take((size_t)(L->nkeys + 1) * 4);
   L->o_sums = take((size_t)(scan_sums_len(nscan) + 1) * 4);
   L->o_keyrank = take((size_t)max_vis * 8);
-  L->o_cell = take((size_t)max_vis * 4);
-  L->o_dxy = take((size_t)max_vis * L->elem);
-  L->o_val = take((size_t)max_vis * L->elem);
-  L->o_idx = take((size_t)max_vis * 4);
+  L->o_rec = take((size_t)max_vis *
+                  (L->elem == 16 ? sizeof(Record<double>)
+                                 : sizeof(Record<float>)));
   L->o_chunks = take((size_t)(L->ntiles + 1) * 4);
   L->o_slot = take((size_t)L->ntiles * 4);
   L->o_counters = take(64);
@@ -320,9 +319,7 @@ ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
   }));
   WS_TRY(launch(pl, "bin_scatter", [&] {
     launch_bin_scatter<R>(g, uvw, vis, weight, m, keyrank, counts,
-                          pl->w<uint32_t>(L.o_cell), pl->work + L.o_dxy,
-                          pl->work + L.o_val,
-                          degrid ? pl->w<uint32_t>(L.o_idx) : nullptr, st);
+                          pl->work + L.o_rec, degrid, st);
   }));
   WS_TRY(launch(pl, "tile_work", [&] {
     launch_tile_work(g, counts, degrid, chunk, chunks, slot, counters, split,
@@ -351,9 +348,7 @@ GridJob<R> make_job(ws_plan* pl, int accumulate) {
   j.idle = pl->w<uint32_t>(L.o_idle);
   j.tile_chunks = pl->w<uint32_t>(L.o_chunks);
   j.tile_slot = pl->w<uint32_t>(L.o_slot);
-  j.rec_cell = pl->w<uint32_t>(L.o_cell);
-  j.rec_dxy = pl->w<cplx<R>>(L.o_dxy);
-  j.rec_val = pl->w<cplx<R>>(L.o_val);
+  j.rec = pl->w<Record<R>>(L.o_rec);
   j.chunk = L.chunk;
   j.planes = static_cast<cplx<R>*>(pl->planes);
   j.partials = pl->w<cplx<R>>(L.o_partials);
@@ -517,8 +512,7 @@ ws_status degrid_impl(ws_plan* pl, const void* image, int image_is_real,
                            pl->w<uint32_t>(L.o_counters),
                            pl->w<uint2>(L.o_extra),
                            pl->w<uint32_t>(L.o_busy), pl->planes,
-                           pl->w<uint32_t>(L.o_cell), pl->work + L.o_dxy,
-                           pl->work + L.o_val, pl->w<uint32_t>(L.o_idx),
+                           pl->work + L.o_rec,
                            L.chunk_degrid, vis_out, max_items, pl->cus,
                            pl->stream);
   }));

@@ -46,6 +46,17 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(
   uint32_t my_rank[kCountPerThread];
   unsigned long long my_drop = 0;
   const int64_t base = (int64_t)blockIdx.x * kCountPerBlock;
+  // All coordinates first (indices clamped into range), so that the loads
+  // overlap instead of each waiting behind the previous one's LDS atomics.
+  double cu[kCountPerThread], cv[kCountPerThread], cw[kCountPerThread];
+#pragma unroll
+  for (int e = 0; e < kCountPerThread; ++e) {
+    int64_t gi = base + e * kCountThreads + tid;
+    gi = gi < m ? gi : m - 1;
+    cu[e] = uvw[3 * gi];
+    cv[e] = uvw[3 * gi + 1];
+    cw[e] = uvw[3 * gi + 2];
+  }
 #pragma unroll
   for (int e = 0; e < kCountPerThread; ++e) {
     const int64_t gi = base + e * kCountThreads + tid;
@@ -53,7 +64,7 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(
     if (gi < m) {
       double x, y;
       int i0, j0, k;
-      const double u = uvw[3 * gi], v = uvw[3 * gi + 1], w = uvw[3 * gi + 2];
+      const double u = cu[e], v = cv[e], w = cw[e];
       if (place(g, u, v, w, x, y, i0, j0, k)) {
         my_drop += (unsigned long long)(g.K * g.K - taps_on_grid(g, i0, j0));
         const uint32_t key = bin_key(g, i0, j0, k);
@@ -75,9 +86,20 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(
   __syncthreads();
   // One global atomic per distinct key of the workgroup; the returned old
   // count becomes the workgroup's base rank for that key (kept in s_cnt).
-  for (int s = tid; s < kHashSize; s += kCountThreads) {
+  // All of a thread's atomics are issued before any result is used, so
+  // their round trips overlap.
+  constexpr int kSlotsPerThread = kHashSize / kCountThreads;
+  uint32_t old[kSlotsPerThread];
+#pragma unroll
+  for (int e = 0; e < kSlotsPerThread; ++e) {
+    const int s = tid + e * kCountThreads;
     const uint32_t key = s_key[s];
-    if (key != kNoKey) s_cnt[s] = atomicAdd(&counts[key], s_cnt[s]);
+    old[e] = key != kNoKey ? atomicAdd(&counts[key], s_cnt[s]) : 0u;
+  }
+#pragma unroll
+  for (int e = 0; e < kSlotsPerThread; ++e) {
+    const int s = tid + e * kCountThreads;
+    if (s_key[s] != kNoKey) s_cnt[s] = old[e];
   }
   __syncthreads();
 #pragma unroll
@@ -189,8 +211,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
     Geo g, const double* __restrict__ uvw, const cplx<R>* __restrict__ vis,
     const float* __restrict__ weight, int64_t m,
     const uint2* __restrict__ keyrank, const uint32_t* __restrict__ offsets,
-    uint32_t* __restrict__ rec_cell, cplx<R>* __restrict__ rec_dxy,
-    cplx<R>* __restrict__ rec_val, uint32_t* __restrict__ rec_idx) {
+    Record<R>* __restrict__ rec, int degrid) {
   const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= m) return;
   const uint2 kr = keyrank[gi];
@@ -199,17 +220,23 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
   int i0, j0, k;
   place(g, uvw[3 * gi], uvw[3 * gi + 1], uvw[3 * gi + 2], x, y, i0, j0, k);
   const uint32_t pos = offsets[kr.x] + kr.y;
-  rec_cell[pos] = pack_cell(i0, j0);
+  Record<R> r;
   // Fractional offsets from the nearest cell, subtracted in FP64 first.
-  rec_dxy[pos] = cplx<R>{(R)(x - (double)i0), (R)(y - (double)j0)};
+  r.dx = (R)(x - (double)i0);
+  r.dy = (R)(y - (double)j0);
   const R wt = weight != nullptr ? (R)weight[gi] : (R)1;
-  if (rec_idx == nullptr) {
+  if (!degrid) {
     const cplx<R> vv = vis[gi];
-    rec_val[pos] = cplx<R>{wt * vv.re, wt * vv.im};
+    r.vr = wt * vv.re;
+    r.vi = wt * vv.im;
   } else {
-    rec_val[pos] = cplx<R>{wt, (R)0};
-    rec_idx[pos] = (uint32_t)gi;
+    r.vr = wt;
+    r.vi = (R)0;
   }
+  r.cell = pack_cell(i0, j0);
+  r.idx = (uint32_t)gi;
+  r.pad0 = r.pad1 = 0u;
+  rec[pos] = r;
 }
 
 // Appends to a list with one atomic per wavefront: returns this lane's slot
@@ -313,25 +340,23 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
 template <typename R>
 void launch_bin_scatter(const Geo& g, const double* uvw, const void* vis,
                         const float* weight, int64_t m, const uint2* keyrank,
-                        const uint32_t* offsets, uint32_t* rec_cell,
-                        void* rec_dxy, void* rec_val, uint32_t* rec_idx,
-                        hipStream_t st) {
+                        const uint32_t* offsets, void* records,
+                        int degrid, hipStream_t st) {
   if (m == 0) return;
   const int64_t nb = (m + 255) / 256;
   hipLaunchKernelGGL(k_bin_scatter<R>, dim3((unsigned)nb), dim3(256), 0, st, g,
                      uvw, (const cplx<R>*)vis, weight, m, keyrank, offsets,
-                     rec_cell, (cplx<R>*)rec_dxy, (cplx<R>*)rec_val, rec_idx);
+                     (Record<R>*)records, degrid);
 }
 
 template void launch_bin_scatter<float>(const Geo&, const double*, const void*,
                                         const float*, int64_t, const uint2*,
-                                        const uint32_t*, uint32_t*, void*,
-                                        void*, uint32_t*, hipStream_t);
+                                        const uint32_t*, void*, int,
+                                        hipStream_t);
 template void launch_bin_scatter<double>(const Geo&, const double*,
                                          const void*, const float*, int64_t,
-                                         const uint2*, const uint32_t*,
-                                         uint32_t*, void*, void*, uint32_t*,
-                                         hipStream_t);
+                                         const uint2*, const uint32_t*, void*,
+                                         int, hipStream_t);
 
 void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t chunk, uint32_t* tile_chunks,

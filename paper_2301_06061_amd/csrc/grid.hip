@@ -240,11 +240,11 @@ __device__ __forceinline__ RecBatch<R> load_batch(const GridJob<R>& j,
                                                   uint32_t f, uint32_t end) {
   const bool in = f < end;
   const uint32_t r = record_at(x, in ? f : end - 1);
+  const Record<R> q = j.rec[r];
   RecBatch<R> b;
-  b.cell = j.rec_cell[r];
-  b.dxy = j.rec_dxy[r];
-  b.val = j.rec_val[r];
-  if (!in) b.val = {(R)0, (R)0};
+  b.cell = q.cell;
+  b.dxy = {q.dx, q.dy};
+  b.val = {in ? q.vr : (R)0, in ? q.vi : (R)0};
   return b;
 }
 
@@ -579,9 +579,8 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(
     Geo g, const uint32_t* __restrict__ offsets,
     uint32_t* __restrict__ counters, const uint2* __restrict__ extra,
     const uint32_t* __restrict__ busy,
-    const cplx<R>* __restrict__ planes, const uint32_t* __restrict__ rec_cell,
-    const cplx<R>* __restrict__ rec_dxy, const cplx<R>* __restrict__ rec_val,
-    const uint32_t* __restrict__ rec_idx, uint32_t chunk,
+    const cplx<R>* __restrict__ planes, const Record<R>* __restrict__ rec,
+    uint32_t chunk,
     cplx<R>* __restrict__ vis_out) {
   constexpr int H = (K - 1) / 2;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -612,8 +611,9 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(
     }
     lds_barrier();
     for (uint32_t r = start + threadIdx.x; r < end; r += blockDim.x) {
-      const uint32_t cc = rec_cell[r];
-      const cplx<R> dxy = rec_dxy[r];
+      const Record<R> q = rec[r];
+      const uint32_t cc = q.cell;
+      const cplx<R> dxy = {q.dx, q.dy};
       const int li = cell_i(cc) - ox + H;
       const int lj = cell_j(cc) - oy + H;
       R gx[K], gy[K];
@@ -640,8 +640,8 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(
         acc.re += gy[b] * racc.re;
         acc.im += gy[b] * racc.im;
       }
-      const R wt = rec_val[r].re;
-      vis_out[rec_idx[r]] = cplx<R>{cn * wt * acc.re, cn * wt * acc.im};
+      const R wt = q.vr;
+      vis_out[q.idx] = cplx<R>{cn * wt * acc.re, cn * wt * acc.im};
     }
   }
 }
@@ -680,17 +680,15 @@ void grid_batch_k(const GridJob<R>* jobs, int njobs, size_t lds,
 template <typename R, int K>
 void degrid_k(const Geo& g, const uint32_t* offsets, uint32_t* counters,
               const uint2* extra, const uint32_t* busy, const void* planes,
-              const uint32_t* rec_cell, const void* rec_dxy,
-              const void* rec_val, const uint32_t* rec_idx, uint32_t chunk,
+              const void* records, uint32_t chunk,
               void* vis_out, uint32_t max_items, int cus, hipStream_t st) {
   const int W = g.T + (K - 1);
   const size_t lds = (size_t)W * W * sizeof(cplx<R>);
   hipLaunchKernelGGL((k_degrid_tiles<R, K>),
                      dim3(persistent_groups(lds, cus, max_items)), dim3(256),
                      lds, st, g, offsets, counters, extra, busy,
-                     (const cplx<R>*)planes, rec_cell,
-                     (const cplx<R>*)rec_dxy, (const cplx<R>*)rec_val,
-                     rec_idx, chunk, (cplx<R>*)vis_out);
+                     (const cplx<R>*)planes, (const Record<R>*)records,
+                     chunk, (cplx<R>*)vis_out);
 }
 
 }  // namespace
@@ -759,15 +757,12 @@ template <typename R>
 void launch_degrid_tiles(const Geo& g, const uint32_t* offsets,
                          uint32_t* counters, const uint2* extra,
                          const uint32_t* busy, const void* planes,
-                         const uint32_t* rec_cell,
-                         const void* rec_dxy, const void* rec_val,
-                         const uint32_t* rec_idx, uint32_t chunk,
+                         const void* records, uint32_t chunk,
                          void* vis_out, uint32_t max_items, int cus,
                          hipStream_t st) {
   WS_K_SWITCH(g.K, (degrid_k<R, KK>(g, offsets, counters, extra, busy,
-                                    planes,
-                                    rec_cell, rec_dxy, rec_val, rec_idx,
-                                    chunk, vis_out, max_items, cus, st)));
+                                    planes, records, chunk, vis_out,
+                                    max_items, cus, st)));
 }
 
 #undef WS_K_SWITCH
@@ -793,9 +788,8 @@ size_t degrid_lds_bytes(int T, int K, int elem_bytes) {
                                      int, uint32_t, hipStream_t);          \
   template void launch_degrid_tiles<R>(                                    \
       const Geo&, const uint32_t*, uint32_t*, const uint2*,                \
-      const uint32_t*, const void*,                                        \
-      const uint32_t*, const void*, const void*, const uint32_t*,          \
-      uint32_t, void*, uint32_t, int, hipStream_t);
+      const uint32_t*, const void*, const void*, uint32_t, void*,          \
+      uint32_t, int, hipStream_t);
 WS_INST(float)
 WS_INST(double)
 #undef WS_INST

@@ -123,8 +123,10 @@ __host__ __device__ inline int strip(int local, int T, int h) {
 // regions; one corner: one region) are a single key range, except the
 // low-u edge, which is two.
 __host__ __device__ inline int region_code(int ry, int rx) {
-  const int tab[3][3] = {{0, 1, 2}, {7, 8, 3}, {6, 5, 4}};
-  return tab[ry][rx];
+  // Selects rather than a table, which the device compiler would place in
+  // memory and load per call.
+  const int mid = rx == 0 ? 7 : (rx == 1 ? 8 : 3);
+  return ry == 0 ? rx : (ry == 2 ? 6 - rx : mid);
 }
 
 // Bin key of a placed visibility: (plane, tile row, tile column, region).
@@ -141,6 +143,19 @@ __host__ __device__ inline uint32_t bin_key(const Geo& g, int i0, int j0,
       (uint32_t)tx;
   return tile * kRegions + (uint32_t)region_code(ry, rx);
 }
+
+// One binned visibility, stored whole (array of structures) so that the
+// scatter of a visibility into its bin is a single 32- or 48-byte write
+// and the gridder reads a batch of records with wide loads.
+//   dx, dy  offset of the exact position from the nearest cell
+//   vr, vi  weighted visibility (gridding) or weight and 0 (degridding)
+//   cell    packed nearest cell (pack_cell)
+//   idx     input index of the visibility (degridding)
+template <typename R>
+struct alignas(16) Record {
+  R dx, dy, vr, vi;
+  uint32_t cell, idx, pad0, pad1;
+};
 
 __host__ __device__ inline uint32_t pack_cell(int i0, int j0) {
   return (uint32_t)(i0 + kCellBias) | ((uint32_t)(j0 + kCellBias) << 16);

@@ -21,9 +21,8 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
 template <typename R>
 void launch_bin_scatter(const Geo& g, const double* uvw, const void* vis,
                         const float* weight, int64_t m, const uint2* keyrank,
-                        const uint32_t* offsets, uint32_t* rec_cell,
-                        void* rec_dxy, void* rec_val, uint32_t* rec_idx,
-                        hipStream_t st);
+                        const uint32_t* offsets, void* records,
+                        int degrid, hipStream_t st);
 void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t chunk, uint32_t* tile_chunks,
                       uint32_t* tile_slot, uint32_t* counters,
@@ -49,9 +48,7 @@ struct GridJob {
   const uint32_t* idle;       // tiles without ([5]), zeroed separately
   const uint32_t* tile_chunks;
   const uint32_t* tile_slot;
-  const uint32_t* rec_cell;
-  const cplx<R>* rec_dxy;
-  const cplx<R>* rec_val;
+  const Record<R>* rec;
   uint32_t chunk;
   cplx<R>* planes;
   cplx<R>* partials;
@@ -81,9 +78,7 @@ template <typename R>
 void launch_degrid_tiles(const Geo& g, const uint32_t* offsets,
                          uint32_t* counters, const uint2* extra,
                          const uint32_t* busy, const void* planes,
-                         const uint32_t* rec_cell,
-                         const void* rec_dxy, const void* rec_val,
-                         const uint32_t* rec_idx, uint32_t chunk,
+                         const void* records, uint32_t chunk,
                          void* vis_out, uint32_t max_items, int cus,
                          hipStream_t st);
 
