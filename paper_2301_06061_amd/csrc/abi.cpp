@@ -465,11 +465,13 @@ ws_status image_impl(ws_plan* pl, void* image) {
   const ws_params& p = pl->p;
   Geo g;
   WS_TRY(cols_impl<R>(pl, +1, &g, pl->w<uint32_t>(pl->L.o_strips)));
-  if (g.perm_n1 == 0 && p.nu <= kFusedRows) {
+  if (p.nu <= kFusedRows) {
     bool ok = true;
     WS_TRY(launch(pl, "row_screen_sum", [&] {
       ok = launch_row_screen_sum<R>(pl->planes, image, g,
-                                    pl->work + pl->L.o_tw_u, pl->stream);
+                                    pl->work + pl->L.o_tw_u,
+                                    pl->w<uint32_t>(pl->L.o_strips),
+                                    pl->stream);
     }));
     if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no fused row FFT for nu=%d",
                          p.nu);
@@ -488,7 +490,7 @@ ws_status degrid_impl(ws_plan* pl, const void* image, int image_is_real,
   const ws_params& p = pl->p;
   const Layout& L = pl->L;
   Geo g = pl->g;
-  if (p.nv <= kOnePassCols && p.nu <= kFusedRows) {
+  if (p.nu <= kFusedRows) {
     bool ok = true;
     WS_TRY(launch(pl, "screen_row_bcast", [&] {
       ok = launch_screen_row_bcast<R>(image, image_is_real, pl->planes,

@@ -26,6 +26,10 @@ namespace ws {
 
 namespace {
 
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
 template <typename R>
 __device__ __forceinline__ cplx<R> rot_i(cplx<R> a, R s) {
   // a * (s i)
@@ -173,9 +177,23 @@ struct Stage {
       if (NB % TPC == 0 || j < NB) {
         const int k = j & (NS - 1);
         if constexpr (NS > 1) {
+          // Twiddles W^(r k N / (NS RAD)), r = 1 .. RAD-1, as powers of the
+          // r = 1 value (one table lookup per butterfly; at most three
+          // products deep, a few units in the last place).
+          cplx<R> w[RAD];
+          w[1] = tw(k * (N / (NS * RAD)), s);
+          if constexpr (RAD > 2) {
+            w[2] = cmul(w[1], w[1]);
+            w[3] = cmul(w[2], w[1]);
+          }
+          if constexpr (RAD > 4) {
+            w[4] = cmul(w[2], w[2]);
+            w[5] = cmul(w[4], w[1]);
+            w[6] = cmul(w[4], w[2]);
+            w[7] = cmul(w[4], w[3]);
+          }
 #pragma unroll
-          for (int r = 1; r < RAD; ++r)
-            v[it][r] = cmul(v[it][r], tw(r * k * (N / (NS * RAD)), s));
+          for (int r = 1; r < RAD; ++r) v[it][r] = cmul(v[it][r], w[r]);
         }
         dft<R, RAD>(v[it], s);
         if constexpr (LAST) {
@@ -491,7 +509,7 @@ __global__ __launch_bounds__(256) void k_wcorrect(const cplx<R>* __restrict__ F,
 template <typename R, int LOGN, int NT>
 __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
     const cplx<R>* __restrict__ planes, cplx<R>* __restrict__ img, Geo g,
-    const cplx<R>* __restrict__ tw) {
+    const cplx<R>* __restrict__ tw, const uint32_t* __restrict__ strips) {
   constexpr int N = 1 << LOGN;
   using L = Stage<R, LOGN, 1, NT, (LOGN / 3) + ((LOGN % 3) ? 1 : 0) - 1>;
   constexpr int IT = L::IT, RAD = L::RAD, NB = L::NB;
@@ -519,20 +537,42 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
   // loads, so no register prefetch; FP64 runs one and prefetches.
   constexpr bool kPrefetch = sizeof(R) == 8;
   cplx<R> cur[IT0][RAD0], nxt[IT0][RAD0];
-  auto fetch = [&](int k, cplx<R> (&buf)[IT0][RAD0]) {
-    const cplx<R>* line = planes + ((size_t)k * g.nv + q) * N;
+  // Column-strip marks (non-null; used when T is 64, so that the 64
+  // samples one wavefront loads lie in one strip): samples of strips that
+  // hold no data are not read, since gridding left those columns zero and
+  // the column transform kept them so.  The marks of plane k + 1 are
+  // loaded (uniform loads, issued together) while plane k is transformed.
+  const bool skip = g.T == 64 && NB0 % 64 == 0;
+  auto marks = [&](int k, uint32_t (&on)[IT0][RAD0]) {
+    const uint32_t* sp = strips + (size_t)(k < g.nw ? k : 0) * g.tiles_u;
+#pragma unroll
+    for (int it = 0; it < IT0; ++it)
+#pragma unroll
+      for (int r = 0; r < RAD0; ++r) {
+        const uint32_t e = threadIdx.x + it * NT + r * NB0;
+        on[it][r] = skip ? sp[uniform_u32(e >> 6)] : 1u;
+      }
+  };
+  auto fetch = [&](int k, const uint32_t (&on)[IT0][RAD0],
+                   cplx<R> (&buf)[IT0][RAD0]) {
+    const cplx<R>* line = planes + ((size_t)k * g.nv + stack_row(g, q)) * N;
 #pragma unroll
     for (int it = 0; it < IT0; ++it)
 #pragma unroll
       for (int r = 0; r < RAD0; ++r) {
         const int j = threadIdx.x + it * NT;
-        if (NB0 % NT == 0 || j < NB0) buf[it][r] = line[j + r * NB0];
+        if (NB0 % NT == 0 || j < NB0)
+          buf[it][r] = on[it][r] != 0u ? line[j + r * NB0]
+                                       : cplx<R>{(R)0, (R)0};
       }
   };
-  if (kPrefetch) fetch(0, cur);
+  uint32_t on[IT0][RAD0], on_next[IT0][RAD0];
+  marks(0, on);
+  if (kPrefetch) fetch(0, on, cur);
   for (int k = 0; k < g.nw; ++k) {
-    if (kPrefetch && k + 1 < g.nw) fetch(k + 1, nxt);
-    if (!kPrefetch) fetch(k, cur);
+    marks(k + 1, on_next);
+    if (kPrefetch && k + 1 < g.nw) fetch(k + 1, on_next, nxt);
+    if (!kPrefetch) fetch(k, on, cur);
     auto ld = [&](int e, int, int it, int r) { return checker(cur[it][r], e); };
     auto st = [&](int e, int, int it, int r, cplx<R> v) {
       v = checker(v, e);
@@ -546,17 +586,28 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
 #pragma unroll
         for (int r = 0; r < RAD0; ++r) cur[it][r] = nxt[it][r];
     }
+#pragma unroll
+    for (int it = 0; it < IT0; ++it)
+#pragma unroll
+      for (int r = 0; r < RAD0; ++r) on[it][r] = on_next[it][r];
   }
+  // Add into the image row: all reads first, then all writes.
   cplx<R>* out = img + (size_t)q * N;
+  cplx<R> old[IT][RAD];
 #pragma unroll
   for (int it = 0; it < IT; ++it)
 #pragma unroll
     for (int r = 0; r < RAD; ++r) {
       const int j = threadIdx.x + it * NT;
-      if (NB % NT == 0 || j < NB) {
-        const int p = j + r * NB;
-        out[p] = cadd(out[p], acc[it][r]);
-      }
+      if (NB % NT == 0 || j < NB) old[it][r] = out[j + r * NB];
+    }
+#pragma unroll
+  for (int it = 0; it < IT; ++it)
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) {
+      const int j = threadIdx.x + it * NT;
+      if (NB % NT == 0 || j < NB)
+        out[j + r * NB] = cadd(old[it][r], acc[it][r]);
     }
 }
 
@@ -700,6 +751,24 @@ bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
   }
 }
 
+template <typename R, int LOG1, int LOG2, int BC>
+void cols4_bc(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
+              const uint32_t* strips, int strip_w, hipStream_t st) {
+  constexpr int NTA = ((1 << LOG1) * BC) / 8;
+  constexpr int NTB = ((1 << LOG2) * BC) / 8;
+  static_assert(NTA <= 1024 && NTB <= 1024, "step too long for one block");
+  const int ncb = ncols / BC;
+  const int nba = ncb * (1 << LOG2) * nplanes;
+  const int nbb = ncb * (1 << LOG1) * nplanes;
+  if (strips != nullptr && strip_w % BC != 0) strips = nullptr;
+  hipLaunchKernelGGL((k_fft_colA<R, LOG1, LOG2, BC, NTA>),
+                     dim3(((nba + 7) / 8) * 8), dim3(NTA), 0, st, data, ncols,
+                     nplanes, tw, s, strips, strip_w);
+  hipLaunchKernelGGL((k_fft_colB<R, LOG1, LOG2, BC, NTB>),
+                     dim3(((nbb + 7) / 8) * 8), dim3(NTB), 0, st, data, ncols,
+                     nplanes, tw, s, strips, strip_w);
+}
+
 template <typename R, int LOGN>
 bool cols4_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
              const uint32_t* strips, int strip_w, hipStream_t st) {
@@ -707,32 +776,31 @@ bool cols4_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
     return false;
   } else {
     constexpr int LOG1 = LOGN / 2, LOG2 = LOGN - LOG1;
-    constexpr int BC = 16;
-    constexpr int NTA = ((1 << LOG1) * BC) / 8;
-    constexpr int NTB = ((1 << LOG2) * BC) / 8;
-    const int ncb = ncols / BC;
-    const int nba = ncb * (1 << LOG2) * nplanes;
-    const int nbb = ncb * (1 << LOG1) * nplanes;
-    if (strips != nullptr && strip_w % BC != 0) strips = nullptr;
-    hipLaunchKernelGGL((k_fft_colA<R, LOG1, LOG2, BC, NTA>),
-                       dim3(((nba + 7) / 8) * 8), dim3(NTA), 0, st, data,
-                       ncols, nplanes, tw, s, strips, strip_w);
-    hipLaunchKernelGGL((k_fft_colB<R, LOG1, LOG2, BC, NTB>),
-                       dim3(((nbb + 7) / 8) * 8), dim3(NTB), 0, st, data,
-                       ncols, nplanes, tw, s, strips, strip_w);
+    // 512-byte row segments (64 FP32 or 32 FP64 columns) per workgroup
+    // when the grid is that wide (fewer if a step would exceed 1024
+    // threads); 16 columns otherwise.
+    constexpr int BCW = 512 / (int)sizeof(cplx<R>);
+    constexpr int NMAX = (1 << LOG2) > (1 << LOG1) ? (1 << LOG2) : (1 << LOG1);
+    constexpr int BC = (NMAX * BCW) / 8 > 1024 ? (8 * 1024) / NMAX : BCW;
+    if (ncols >= BC && ncols % BC == 0)
+      cols4_bc<R, LOG1, LOG2, BC>(data, ncols, nplanes, tw, s, strips,
+                                  strip_w, st);
+    else
+      cols4_bc<R, LOG1, LOG2, 16>(data, ncols, nplanes, tw, s, strips,
+                                  strip_w, st);
     return true;
   }
 }
 
 template <typename R, int LOGN>
 bool row_screen_t(const cplx<R>* planes, cplx<R>* img, const Geo& g,
-                  const cplx<R>* tw, hipStream_t st) {
+                  const cplx<R>* tw, const uint32_t* strips, hipStream_t st) {
   if constexpr (LOGN > 12) {
     return false;
   } else {
     constexpr int NT = row_threads(LOGN);
     hipLaunchKernelGGL((k_row_screen_sum<R, LOGN, NT>), dim3(g.nv), dim3(NT),
-                       0, st, planes, img, g, tw);
+                       0, st, planes, img, g, tw, strips);
     return true;
   }
 }
@@ -804,12 +872,14 @@ bool launch_fft_cols(void* data, int nrows, int ncols, int nplanes,
 
 template <typename R>
 bool launch_row_screen_sum(const void* planes, void* img, const Geo& g,
-                           const void* tw_u, hipStream_t st) {
+                           const void* tw_u, const uint32_t* strips,
+                           hipStream_t st) {
   const int lg = ilog2(g.nu);
   bool ok = false;
   WS_LOGN_SWITCH(lg, (ok = row_screen_t<R, LG>((const cplx<R>*)planes,
                                                (cplx<R>*)img, g,
-                                               (const cplx<R>*)tw_u, st)));
+                                               (const cplx<R>*)tw_u, strips,
+                                               st)));
   return ok;
 }
 
@@ -888,7 +958,8 @@ void launch_twiddles(void* tw, int n, hipStream_t st) {
   template bool launch_fft_cols<R>(void*, int, int, int, const void*, int,   \
                                    const uint32_t*, int, hipStream_t);       \
   template bool launch_row_screen_sum<R>(const void*, void*, const Geo&,     \
-                                         const void*, hipStream_t);          \
+                                         const void*, const uint32_t*,       \
+                                         hipStream_t);                       \
   template bool launch_screen_row_bcast<R>(const void*, int, void*,          \
                                            const Geo&, const void*,          \
                                            hipStream_t);                     \

@@ -95,7 +95,8 @@ bool launch_fft_cols(void* data, int nrows, int ncols, int nplanes,
                      int strip_w, hipStream_t st);
 template <typename R>
 bool launch_row_screen_sum(const void* planes, void* img, const Geo& g,
-                           const void* tw_u, hipStream_t st);
+                           const void* tw_u, const uint32_t* strips,
+                           hipStream_t st);
 template <typename R>
 bool launch_screen_row_bcast(const void* img, int img_real, void* planes,
                              const Geo& g, const void* tw_u, hipStream_t st);
