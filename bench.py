@@ -34,25 +34,60 @@ def log(*a):
 
 
 def algorithmic_bytes(name, wl, elem, m):
-    """Bytes a kernel must move per launch (reads + writes), by definition.
+    """Bytes a kernel must move per launch (reads + writes), by definition
+    of the step it performs (not what the kernel happens to skip).
 
-    grid_tiles: write every stack cell once + read each binned record once
-      (cell index 4 B, two fractional offsets and a complex value);
-    fft_cols: read + write the stack once;
+    fft_cols:       the 2-D transform of the stack: read + write the stack
+                    once (the row half is fused into row_screen_sum);
     row_screen_sum: read the stack once + read/write the image once;
-    bin_count: read uvw (24 B) + write key/rank (8 B) per visibility;
-    bin_scatter: read uvw, vis, weight, key/rank + write a record.
+    grid (step):    write every stack cell once + read each binned record
+                    once (zero_idle + grid_tiles + grid_merge together);
+    bin_count:      read uvw (24 B) + write key/rank (8 B) per visibility;
+    bin_scatter:    read uvw, vis, weight, key/rank + write a record.
     """
     cells = wl.nu * wl.nv * wl.nw
     img = wl.nu * wl.nv
-    rec = 4 + 2 * elem
+    rec = 32 if elem == 8 else 48
+    vis_b = elem
     return {
-        "grid_tiles": cells * elem + m * rec,
         "fft_cols": 2 * cells * elem,
         "row_screen_sum": cells * elem + 2 * img * elem,
+        "grid": cells * elem + m * rec,
         "bin_count": m * (24 + 8),
-        "bin_scatter": m * (24 + elem + 4 + 8 + rec),
+        "bin_scatter": m * (24 + vis_b + 4 + 8 + rec),
     }.get(name)
+
+
+def source_digest(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def pmc_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<kernel>_config2_fp32_pmc.txt), or None when there is none or
+    the kernel's source has changed since the counters were taken.  The
+    summary holds FETCH_SIZE and WRITE_SIZE (KiB per dispatch) and the
+    factors that scale them to bytes, measured on an elementwise kernel of
+    known size."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_config2_fp32_pmc.txt")
+    try:
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        src = os.path.join(ROOT, kv["source"])
+        if source_digest(src) != kv["source_sha256_16"]:
+            return None
+        return (float(kv["fetch_kib_per_launch"]) * 1024 *
+                float(kv["fetch_scale"]) +
+                float(kv["write_kib_per_launch"]) * 1024 *
+                float(kv["write_scale"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def time_path(plan, uvw, vis, wt, img, steps, warmup, torch):
@@ -279,24 +314,29 @@ def main(argv=None):
                                             (wl.m / (grid32 / 1e3) / 1e6) /
                                             res["fp64"]["grid_mvis_per_s"])
 
-    # Roofline of the dominant kernel (largest share of the step).
+    # Roofline of the dominant kernel (largest share of the step), from its
+    # average launch time measured with HIP events on the plan's stream.
     name, (tot, cnt) = max(kt32.items(), key=lambda x: x[1][0])
     avg_ms = tot / max(cnt, 1)
     ab = algorithmic_bytes(name, wl, 8, wl.m)
     roof = None
     if ab is not None:
         ach = ab / (avg_ms / 1e3) / 1e9
+        tr = pmc_traffic(name)
         roof = {"kernel": name, "bound": "hbm", "achieved": ach,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "frac": ach / HBM_PEAK_GBS, "traffic": tr,
                 "avg_ms": avg_ms, "algorithmic_bytes": ab}
     kernels = {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]}
                for k, v in kt32.items()}
+    # The gridding step as a whole (its kernels write the stack together).
+    gk = [k for k in ("zero_idle", "grid_tiles", "grid_merge") if k in kt32]
     gb = None
-    if "grid_tiles" in kt32:
-        g_ms = kt32["grid_tiles"][0] / kt32["grid_tiles"][1]
-        gab = algorithmic_bytes("grid_tiles", wl, 8, wl.m)
-        gb = {"avg_ms": g_ms, "achieved_gbs": gab / (g_ms / 1e3) / 1e9,
+    if gk:
+        g_ms = sum(kt32[k][0] for k in gk) / args.steps
+        gab = algorithmic_bytes("grid", wl, 8, wl.m)
+        gb = {"kernels": gk, "ms": g_ms,
+              "achieved_gbs": gab / (g_ms / 1e3) / 1e9,
               "frac": gab / (g_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 
     extra = {}
@@ -334,7 +374,7 @@ def main(argv=None):
         "grid_mvis_per_s": wl.m / (grid32 / 1e3) / 1e6,
         "ggpas": wl.m * wl.support ** 2 / (grid32 / 1e3) / 1e9,
         "roofline": roof,
-        "grid_tiles_roofline": gb,
+        "grid_step_roofline": gb,
         "kernels_fp32": kernels,
         "cpu_baseline": cpu,
     }

@@ -145,7 +145,12 @@ ws_status ws_wcorrect_accumulate(ws_plan* plan, void* image);
 /* Fused form of ws_fft_planes(+1) followed by ws_wcorrect_accumulate():
  * the last FFT stage, the screen and the plane sum run in one pass that
  * never writes the transformed planes back.  Same result to rounding.  It
- * consumes the stack: afterwards the plan is reset (empty). */
+ * images the stack as the gridding calls since the last reset left it:
+ * column strips (tile-wide column ranges of one plane) that none of those
+ * calls reached hold zeros and are not transformed or read (a caller that
+ * writes into the stack itself uses ws_fft_planes and
+ * ws_wcorrect_accumulate instead).  It consumes the stack: afterwards the
+ * plan is reset (empty).  Fails with WS_BAD_STATE after ws_fft_planes(). */
 ws_status ws_image_accumulate(ws_plan* plan, void* image);
 
 /* Degridding (Sec. 5 future work): the exact adjoint of gridding, FFT(+1)
