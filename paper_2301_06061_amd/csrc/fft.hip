@@ -339,6 +339,54 @@ __global__ __launch_bounds__(NT) void k_fft_cols(
   fft_line<R, LOGN, BC, NT>(lds, ld, st, twl, s);
 }
 
+// Column transform with twice the columns per workgroup that a whole
+// column of LDS allows: one radix-2 decimation-in-frequency step as the
+// samples arrive from HBM (rows e and e + N/2), the sums transformed in
+// LDS first (outputs 2e, written at once: every input has been read)
+// while the twiddled differences wait in registers, then the differences
+// (outputs 2e + 1).  The wider block doubles the row segment each access
+// moves (64 bytes instead of 32 for 4096-point FP32 columns).
+template <typename R, int LOGH, int BC, int NT>
+__global__ __launch_bounds__(NT) void k_fft_cols_split(
+    cplx<R>* data, int ncols, int nplanes, const cplx<R>* __restrict__ tw, R s,
+    const uint32_t* __restrict__ strips, int strip_w) {
+  constexpr int NH = 1 << LOGH;  // half the column length
+  constexpr int N = 2 * NH;
+  __shared__ cplx<R> lds[lds_line<NH>(BC)];
+  __shared__ cplx<R> s_lo[kTwLo], s_hi[(NH + kTwLo - 1) / kTwLo];
+  using F0 = Stage<R, LOGH, BC, NT, 0>;
+  using FL = Stage<R, LOGH, BC, NT, F0::NPASS - 1>;
+  const int nb_plane = ncols / BC;
+  const int nb = nb_plane * nplanes;
+  const int L = xcd_block<R, BC>((int)blockIdx.x, nb);
+  if (L >= nb) return;
+  const int plane = L / nb_plane;
+  const int col0 = (L - plane * nb_plane) * BC;
+  if (strips != nullptr &&
+      strips[plane * (ncols / strip_w) + col0 / strip_w] == 0u)
+    return;
+  cplx<R>* base = data + (size_t)plane * N * ncols + col0;
+  const Twiddles<R> twl = load_twiddles_sub(s_lo, s_hi, tw, NH, N);
+  __syncthreads();
+  cplx<R> diff[F0::IT][F0::RAD];
+  auto ld_sum = [&](int e, int c, int it, int r) {
+    const cplx<R> a = checker(base[(size_t)e * ncols + c], e);
+    const cplx<R> b = checker(base[(size_t)(e + NH) * ncols + c], e + NH);
+    diff[it][r] = cmul(csub(a, b), twiddle_full(tw, e, s));
+    return cadd(a, b);
+  };
+  // Output 2e has the centring sign +1, output 2e + 1 the sign -1.
+  auto st_even = [&](int e, int c, int, int, cplx<R> v) {
+    base[(size_t)(2 * e) * ncols + c] = v;
+  };
+  fft_line<R, LOGH, BC, NT>(lds, ld_sum, st_even, twl, s);
+  auto ld_diff = [&](int, int, int it, int r) { return diff[it][r]; };
+  auto st_odd = [&](int e, int c, int, int, cplx<R> v) {
+    base[(size_t)(2 * e + 1) * ncols + c] = cplx<R>{-v.re, -v.im};
+  };
+  fft_line<R, LOGH, BC, NT>(lds, ld_diff, st_odd, twl, s);
+}
+
 // ---- four-step column transform for long columns (N = N1 * N2) ---------
 //
 // Step A: for each n2, the length-N1 transform over rows n1*N2 + n2, times
@@ -744,6 +792,19 @@ bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
   constexpr int NT = (N * BC) / 8 < 64 ? 64 : ((N * BC) / 8 > 1024 ? 1024 : (N * BC) / 8);
   const int nb = (ncols / BC) * nplanes;
   const int grid = ((nb + 7) / 8) * 8;
+  if constexpr (BC * ELEM < 128 && LOGN >= 10) {
+    // Twice the columns per block with the split transform.
+    constexpr int BC2 = 2 * BC;
+    constexpr int NT2 = (N / 2 * BC2) / 8 > 1024 ? 1024 : (N / 2 * BC2) / 8;
+    if (ncols % BC2 == 0) {
+      const int nb2 = (ncols / BC2) * nplanes;
+      if (strips != nullptr && strip_w % BC2 != 0) strips = nullptr;
+      hipLaunchKernelGGL((k_fft_cols_split<R, LOGN - 1, BC2, NT2>),
+                         dim3(((nb2 + 7) / 8) * 8), dim3(NT2), 0, st, data,
+                         ncols, nplanes, tw, s, strips, strip_w);
+      return true;
+    }
+  }
   if (strips != nullptr && strip_w % BC != 0) strips = nullptr;
   hipLaunchKernelGGL((k_fft_cols<R, LOGN, BC, NT>), dim3(grid), dim3(NT), 0,
                      st, data, ncols, nplanes, tw, s, strips, strip_w);
