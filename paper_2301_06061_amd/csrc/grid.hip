@@ -584,13 +584,16 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(
     cplx<R>* __restrict__ vis_out) {
   constexpr int H = (K - 1) / 2;
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_item;
   cplx<R>* s_q = reinterpret_cast<cplx<R>*>(smem);
   const int T = g.T;
   const int W = T + 2 * H;
   const R cn = (R)g.cnorm;
-  Item it;
-  while (next_item(counters, counters, extra, busy, &s_item, it)) {
+  // One workgroup per item (the hardware overlaps the latencies of the
+  // workgroups resident on a CU); blocks past the item count exit.
+  {
+    const uint32_t item = blockIdx.x;
+    if (item >= item_total(counters)) return;
+    const Item it = resolve_item(item, counters, extra, busy);
     const int t = it.tile;
     const uint32_t c = it.chunk;
     int k, oy, ox;
@@ -598,50 +601,88 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(
     const uint32_t r0 = offsets[(uint32_t)t * kRegions];
     const uint32_t r1 = offsets[(uint32_t)t * kRegions + kRegions];
     const uint32_t start = r0 + c * chunk;
-    if (start >= r1) continue;
+    if (start >= r1) return;
     const uint32_t end = r1 - start > chunk ? start + chunk : r1;
     const cplx<R>* src = planes + (size_t)k * g.nv * g.nu;
-    for (int i = threadIdx.x; i < W * W; i += blockDim.x) {
-      const int lr = i / W, lc = i - lr * W;
-      const int gr = oy - H + lr, gc = ox - H + lc;
-      cplx<R> v = {(R)0, (R)0};
-      if ((unsigned)gr < (unsigned)g.nv && (unsigned)gc < (unsigned)g.nu)
-        v = src[(size_t)stack_row(g, gr) * g.nu + gc];
-      s_q[i] = v;
+    // Tile + halo into LDS, up to kTile loads in flight per thread before
+    // their LDS writes (one round trip for a 64 x 64 tile with K <= 15;
+    // addresses clamped into the plane, so the loads are unconditional;
+    // cells off the grid are zeroed afterwards).
+    constexpr int kTile = 24;
+    for (int i0 = threadIdx.x; i0 < W * W; i0 += kTile * (int)blockDim.x) {
+      cplx<R> v[kTile];
+#pragma unroll
+      for (int u = 0; u < kTile; ++u) {
+        const int i = i0 + u * (int)blockDim.x;
+        const int ii = i < W * W ? i : W * W - 1;
+        const int lr = ii / W, lc = ii - lr * W;
+        const int gr = oy - H + lr, gc = ox - H + lc;
+        const int grc = gr < 0 ? 0 : (gr >= g.nv ? g.nv - 1 : gr);
+        const int gcc = gc < 0 ? 0 : (gc >= g.nu ? g.nu - 1 : gc);
+        v[u] = src[(size_t)stack_row(g, grc) * g.nu + gcc];
+        if (gr != grc || gc != gcc) v[u] = cplx<R>{(R)0, (R)0};
+      }
+#pragma unroll
+      for (int u = 0; u < kTile; ++u) {
+        const int i = i0 + u * (int)blockDim.x;
+        if (i < W * W) s_q[i] = v[u];
+      }
     }
     lds_barrier();
-    for (uint32_t r = start + threadIdx.x; r < end; r += blockDim.x) {
-      const Record<R> q = rec[r];
-      const uint32_t cc = q.cell;
-      const cplx<R> dxy = {q.dx, q.dy};
-      const int li = cell_i(cc) - ox + H;
-      const int lj = cell_j(cc) - oy + H;
-      R gx[K], gy[K];
+    // Records kRec at a time per thread, the next kRec in flight while the
+    // current ones are evaluated (positions past the end re-read the last
+    // record and are not written).
+    constexpr int kRec = sizeof(R) == 4 ? 4 : 2;
+    const uint32_t step = blockDim.x;
+    auto load = [&](uint32_t r0, Record<R> (&q)[kRec]) {
 #pragma unroll
-      for (int a = 0; a < K; ++a) {
-        gx[a] = gauss1(g, (R)(a - H) - dxy.re);
-        gy[a] = gauss1(g, (R)(a - H) - dxy.im);
+      for (int u = 0; u < kRec; ++u) {
+        const uint32_t r = r0 + (uint32_t)u * step;
+        q[u] = rec[r < end ? r : end - 1];
       }
-      cplx<R> acc = {(R)0, (R)0};
+    };
+    Record<R> cur[kRec];
+    uint32_t rb = start + threadIdx.x;
+    load(rb, cur);
+    while (rb < end) {
+      Record<R> nxt[kRec];
+      const uint32_t rn = rb + (uint32_t)kRec * step;
+      load(rn, nxt);
 #pragma unroll
-      for (int b = 0; b < K; ++b) {
-        const int row = lj + b - H;
-        if ((unsigned)row >= (unsigned)W) continue;
-        cplx<R> racc = {(R)0, (R)0};
+      for (int u = 0; u < kRec; ++u) {
+        const Record<R>& q = cur[u];
+        const int li = cell_i(q.cell) - ox + H;
+        const int lj = cell_j(q.cell) - oy + H;
+        R gx[K], gy[K];
 #pragma unroll
         for (int a = 0; a < K; ++a) {
-          const int col = li + a - H;
-          if ((unsigned)col < (unsigned)W) {
-            const cplx<R> q = s_q[row * W + col];
-            racc.re += gx[a] * q.re;
-            racc.im += gx[a] * q.im;
-          }
+          gx[a] = gauss1(g, (R)(a - H) - q.dx);
+          gy[a] = gauss1(g, (R)(a - H) - q.dy);
         }
-        acc.re += gy[b] * racc.re;
-        acc.im += gy[b] * racc.im;
+        cplx<R> acc = {(R)0, (R)0};
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+          const int row = lj + b - H;
+          if ((unsigned)row >= (unsigned)W) continue;
+          cplx<R> racc = {(R)0, (R)0};
+#pragma unroll
+          for (int a = 0; a < K; ++a) {
+            const int col = li + a - H;
+            if ((unsigned)col < (unsigned)W) {
+              const cplx<R> v = s_q[row * W + col];
+              racc.re += gx[a] * v.re;
+              racc.im += gx[a] * v.im;
+            }
+          }
+          acc.re += gy[b] * racc.re;
+          acc.im += gy[b] * racc.im;
+        }
+        if (rb + (uint32_t)u * step < end)
+          vis_out[q.idx] = cplx<R>{cn * q.vr * acc.re, cn * q.vr * acc.im};
       }
-      const R wt = q.vr;
-      vis_out[q.idx] = cplx<R>{cn * wt * acc.re, cn * wt * acc.im};
+#pragma unroll
+      for (int u = 0; u < kRec; ++u) cur[u] = nxt[u];
+      rb = rn;
     }
   }
 }
@@ -685,7 +726,7 @@ void degrid_k(const Geo& g, const uint32_t* offsets, uint32_t* counters,
   const int W = g.T + (K - 1);
   const size_t lds = (size_t)W * W * sizeof(cplx<R>);
   hipLaunchKernelGGL((k_degrid_tiles<R, K>),
-                     dim3(persistent_groups(lds, cus, max_items)), dim3(256),
+                     dim3(max_items > 0 ? max_items : 1), dim3(256),
                      lds, st, g, offsets, counters, extra, busy,
                      (const cplx<R>*)planes, (const Record<R>*)records,
                      chunk, (cplx<R>*)vis_out);
