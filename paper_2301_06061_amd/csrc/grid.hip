@@ -27,9 +27,10 @@
 // tile with records, then groups of tiles without records, which only get
 // zeros.
 //
-// Degridding: persistent workgroups take (tile, chunk) items; each loads
-// the transformed plane's tile plus an h-cell halo into LDS once, and each
-// lane evaluates one visibility's K x K weighted sum from LDS.
+// Degridding: one workgroup per (tile, chunk) item (the hardware overlaps
+// the latencies of the workgroups resident on a CU); each loads the
+// transformed plane's tile plus an h-cell halo into LDS in one round trip,
+// and each lane evaluates one visibility's K x K weighted sum from LDS.
 #include "ws_kernels.h"
 
 namespace ws {
@@ -94,22 +95,6 @@ __device__ __forceinline__ Item resolve_item(uint32_t item,
     it.chunk = 0;
   }
   return it;
-}
-
-// Pop the next item of a plan's own queue (counters[3]); used by the
-// degridder.  Contains the barriers that order LDS reuse between items.
-__device__ __forceinline__ bool next_item(const uint32_t* counters_ro,
-                                          uint32_t* counters,
-                                          const uint2* extra,
-                                          const uint32_t* busy,
-                                          uint32_t* s_item, Item& it) {
-  lds_barrier();
-  if (threadIdx.x == 0) *s_item = atomicAdd(&counters[3], 1u);
-  lds_barrier();
-  const uint32_t item = *s_item;
-  if (item >= item_total(counters_ro)) return false;
-  it = resolve_item(item, counters_ro, extra, busy);
-  return true;
 }
 
 __device__ __forceinline__ void tile_origin(const Geo& g, int t, int& k,
