@@ -153,6 +153,19 @@ ws_status ws_wcorrect_accumulate(ws_plan* plan, void* image);
  * plan is reset (empty).  Fails with WS_BAD_STATE after ws_fft_planes(). */
 ws_status ws_image_accumulate(ws_plan* plan, void* image);
 
+/* Gridding (Eq. 3) and imaging (Eq. 2) in one call, with the stack as
+ * scratch: the same image as ws_grid_visibilities() followed by
+ * ws_image_accumulate(), to rounding.  Because no caller observes the
+ * stack in between, tiles that receive no visibility are not zeroed when
+ * the imaging pass can take them as zero by itself (tile edge 64, nu in
+ * [512, 4096], nv <= 4096); otherwise the call does exactly the two steps.
+ * Arguments as for those two calls; the plan must be empty (after init or
+ * ws_plan_reset(), else WS_BAD_STATE) and is empty afterwards, with the
+ * stack's contents unspecified. */
+ws_status ws_grid_image(ws_plan* plan, int64_t m, const double* uvw,
+                        const void* vis, const float* weight, void* image,
+                        int64_t* n_dropped_taps);
+
 /* Degridding (Sec. 5 future work): the exact adjoint of gridding, FFT(+1)
  * and w-correction.  vis_out[m] = w_m sum_taps c g g Q_k(m)[j][i] with
  * Q_k = FFT(-1)(conj(screen_k) * X).  image: device [nv][nu], complex in the

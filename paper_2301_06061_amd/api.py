@@ -133,6 +133,25 @@ class WStackPlan:
         self._bind()
         _abi.call("ws_image_accumulate", self._h, _ptr(image))
 
+    def grid_image(self, uvw, vis, weight=None, image=None, dropped=None):
+        """Grid and image in one call (the stack must be empty, e.g. after
+        ``reset()``); adds into ``image`` (a new zero image if None) and
+        returns it.  The stack is scratch: afterwards its contents are
+        unspecified and the plan is empty."""
+        m = int(uvw.shape[0])
+        if image is None:
+            image = self.new_image()
+        self._check(uvw, torch.float64, (m, 3), "uvw")
+        self._check(vis, self.cdtype, (m,), "vis")
+        self._check(weight, torch.float32, (m,), "weight")
+        self._check(image, self.cdtype, (self.params.nv, self.params.nu),
+                    "image")
+        self._check(dropped, torch.int64, (1,), "dropped")
+        self._bind()
+        _abi.call("ws_grid_image", self._h, m, _ptr(uvw), _ptr(vis),
+                  _ptr(weight), _ptr(image), _ptr(dropped))
+        return image
+
     def new_image(self):
         return torch.zeros((self.params.nv, self.params.nu), dtype=self.cdtype,
                            device=self.device)

@@ -368,15 +368,18 @@ ws_status merge_impl(ws_plan* pl, int acc) {
   });
 }
 
+// With `lazy` (a first call whose stack only the fused imaging path will
+// read), tiles without records are not zeroed.
 template <typename R>
 ws_status grid_impl(ws_plan* pl, int64_t m, const double* uvw, const void* vis,
-                    const float* weight, int64_t* n_dropped) {
+                    const float* weight, int64_t* n_dropped,
+                    bool lazy = false) {
   uint32_t max_items = 0;
   const int acc = pl->state == kGridded ? 1 : 0;
   WS_TRY(bin_records<R>(pl, m, uvw, vis, weight, 0, n_dropped, &max_items,
                         pl->w<uint32_t>(pl->L.o_strips), !acc));
   const GridJob<R> j = make_job<R>(pl, acc);
-  if (!acc) {
+  if (!acc && !lazy) {
     // First call since the reset: tiles without records get their zeros.
     WS_TRY(launch(pl, "zero_idle", [&] {
       launch_zero_idle<R>(pl->g, j.counters, j.idle, pl->planes, pl->stream);
@@ -398,7 +401,8 @@ ws_status grid_impl(ws_plan* pl, int64_t m, const double* uvw, const void* vis,
 // transform.
 template <typename R>
 ws_status cols_impl(ws_plan* pl, int sign, Geo* gout,
-                    const uint32_t* strips = nullptr) {
+                    const uint32_t* strips = nullptr,
+                    const uint32_t* tiles = nullptr) {
   const ws_params& p = pl->p;
   bool ok = true;
   Geo g = pl->g;
@@ -406,7 +410,7 @@ ws_status cols_impl(ws_plan* pl, int sign, Geo* gout,
     WS_TRY(launch(pl, "fft_cols", [&] {
       ok = launch_fft_cols<R>(pl->planes, p.nv, p.nu, p.nw,
                               pl->work + pl->L.o_tw_v, sign, strips, g.T,
-                              pl->stream);
+                              tiles, pl->stream);
     }));
   } else {
     WS_TRY(launch(pl, "fft_cols4", [&] {
@@ -460,11 +464,14 @@ ws_status fft_impl(ws_plan* pl, int sign) {
 
 // The stack holds what the gridding calls since the reset wrote, so the
 // column strips they never reached are skipped.
+// With `lazy`, tiles without records were never written (their cells are
+// taken as zero from the per-tile record counts).
 template <typename R>
-ws_status image_impl(ws_plan* pl, void* image) {
+ws_status image_impl(ws_plan* pl, void* image, bool lazy = false) {
   const ws_params& p = pl->p;
   Geo g;
-  WS_TRY(cols_impl<R>(pl, +1, &g, pl->w<uint32_t>(pl->L.o_strips)));
+  WS_TRY(cols_impl<R>(pl, +1, &g, pl->w<uint32_t>(pl->L.o_strips),
+                      lazy ? pl->w<uint32_t>(pl->L.o_chunks) : nullptr));
   if (p.nu <= kFusedRows) {
     bool ok = true;
     WS_TRY(launch(pl, "row_screen_sum", [&] {
@@ -765,6 +772,37 @@ ws_status ws_image_accumulate(ws_plan* plan, void* image) {
   ws_status st = plan->p.precision == WS_FP64
                      ? image_impl<double>(plan, image)
                      : image_impl<float>(plan, image);
+  plan->state = kEmpty;
+  return st;
+}
+
+ws_status ws_grid_image(ws_plan* plan, int64_t m, const double* uvw,
+                        const void* vis, const float* weight, void* image,
+                        int64_t* n_dropped_taps) {
+  WS_TRY(check_plan(plan));
+  WS_TRY(check_vis_args(plan, m, uvw, weight));
+  if (m > 0 && vis == nullptr) return fail(WS_INVALID_ARG, "vis is NULL");
+  if (image == nullptr) return fail(WS_INVALID_ARG, "image is NULL");
+  if (!aligned(vis, plan->L.elem) || !aligned(image, plan->L.elem) ||
+      !aligned(n_dropped_taps, 8))
+    return fail(WS_INVALID_ARG, "misaligned vis, image or n_dropped_taps");
+  if (plan->state != kEmpty)
+    return fail(WS_BAD_STATE,
+                "the stack is not empty; call ws_plan_reset first");
+  const ws_params& p = plan->p;
+  // Tiles without records stay unwritten only where every later read
+  // knows them: one-pass columns with tile-wide blocks and the fused rows
+  // reading by strip marks (tile edge 64, rows of 512 or more).
+  const bool lazy = plan->g.T == 64 && p.nv <= kOnePassCols &&
+                    p.nu >= 512 && p.nu <= kFusedRows;
+  const bool f64 = p.precision == WS_FP64;
+  ws_status st = f64 ? grid_impl<double>(plan, m, uvw, vis, weight,
+                                         n_dropped_taps, lazy)
+                     : grid_impl<float>(plan, m, uvw, vis, weight,
+                                        n_dropped_taps, lazy);
+  if (st == WS_OK)
+    st = f64 ? image_impl<double>(plan, image, lazy)
+             : image_impl<float>(plan, image, lazy);
   plan->state = kEmpty;
   return st;
 }

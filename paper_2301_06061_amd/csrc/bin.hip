@@ -310,7 +310,9 @@ __global__ __launch_bounds__(256) void k_tile_work(
       nch = 1;  // cannot happen with the sizes the plan reserves
     }
   }
-  tile_chunks[t] = nch;
+  // 0 marks a tile without records (its stack cells may be left unwritten
+  // by a fused grid-and-image call).
+  tile_chunks[t] = work == 0 ? 0u : nch;
 }
 
 }  // namespace

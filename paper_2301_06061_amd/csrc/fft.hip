@@ -297,6 +297,31 @@ __global__ __launch_bounds__(NT) void k_fft_rows_split(
   fft_line<R, LOGH, 1, NT>(lds, ld_diff, st_odd, twl, s);
 }
 
+// Which rows of a column block hold data, from the per-tile record
+// counts of gridding (0 = a tile without records, whose cells a fused
+// grid-and-image call leaves unwritten and the transform takes as zero).
+// Without a table every row holds data.  A wavefront of a BC-column block
+// loads 64 / BC consecutive rows; when they lie in one tile row (T >=
+// 64 / BC) the lookup is a uniform load.
+template <int BC>
+struct TileRows {
+  const uint32_t* t;  // tile counts of this plane and column strip, or null
+  int tw, T;
+  __device__ __forceinline__ TileRows(const uint32_t* tiles, int plane,
+                                      int nrows, int ncols, int col0, int T_)
+      : t(nullptr), tw(0), T(T_) {
+    if (tiles != nullptr) {
+      tw = ncols / T_;
+      t = tiles + (size_t)plane * (nrows / T_) * tw + col0 / T_;
+    }
+  }
+  __device__ __forceinline__ bool has(int e) const {
+    if (t == nullptr) return true;
+    const uint32_t row = (uint32_t)e / (uint32_t)T;
+    return t[(size_t)(T * BC >= 64 ? uniform_u32(row) : row) * tw] != 0u;
+  }
+};
+
 // Logical column block of hardware block b.  Blocks are dispatched to the
 // eight XCDs in turn (b % 8); the G logical blocks that share one 128-byte
 // line of every row are given to one XCD (they then share its L2), and
@@ -316,7 +341,8 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 template <typename R, int LOGN, int BC, int NT>
 __global__ __launch_bounds__(NT) void k_fft_cols(
     cplx<R>* data, int ncols, int nplanes, const cplx<R>* __restrict__ tw, R s,
-    const uint32_t* __restrict__ strips, int strip_w) {
+    const uint32_t* __restrict__ strips, int strip_w,
+    const uint32_t* __restrict__ tiles) {
   constexpr int N = 1 << LOGN;  // column length = number of rows
   __shared__ cplx<R> lds[lds_line<N>(BC)];
   __shared__ cplx<R> s_lo[kTwLo], s_hi[(N + kTwLo - 1) / kTwLo];
@@ -330,8 +356,10 @@ __global__ __launch_bounds__(NT) void k_fft_cols(
       strips[plane * (ncols / strip_w) + col0 / strip_w] == 0u)
     return;
   cplx<R>* base = data + (size_t)plane * N * ncols + col0;
+  const TileRows<BC> tr(tiles, plane, N, ncols, col0, strip_w);
   auto ld = [&](int e, int c, int, int) {
-    return checker(base[(size_t)e * ncols + c], e);
+    return tr.has(e) ? checker(base[(size_t)e * ncols + c], e)
+                     : cplx<R>{(R)0, (R)0};
   };
   auto st = [&](int e, int c, int, int, cplx<R> v) {
     base[(size_t)e * ncols + c] = checker(v, e);
@@ -351,7 +379,8 @@ __global__ __launch_bounds__(NT) void k_fft_cols(
 template <typename R, int LOGH, int BC, int NT>
 __global__ __launch_bounds__(NT) void k_fft_cols_split(
     cplx<R>* data, int ncols, int nplanes, const cplx<R>* __restrict__ tw, R s,
-    const uint32_t* __restrict__ strips, int strip_w) {
+    const uint32_t* __restrict__ strips, int strip_w,
+    const uint32_t* __restrict__ tiles) {
   constexpr int NH = 1 << LOGH;  // half the column length
   constexpr int N = 2 * NH;
   __shared__ cplx<R> lds[lds_line<NH>(BC)];
@@ -371,9 +400,13 @@ __global__ __launch_bounds__(NT) void k_fft_cols_split(
   const Twiddles<R> twl = load_twiddles_sub(s_lo, s_hi, tw, NH, N);
   __syncthreads();
   cplx<R> diff[F0::IT][F0::RAD];
+  const TileRows<BC> tr(tiles, plane, N, ncols, col0, strip_w);
   auto ld_sum = [&](int e, int c, int it, int r) {
-    const cplx<R> a = checker(base[(size_t)e * ncols + c], e);
-    const cplx<R> b = checker(base[(size_t)(e + NH) * ncols + c], e + NH);
+    const cplx<R> a = tr.has(e) ? checker(base[(size_t)e * ncols + c], e)
+                                : cplx<R>{(R)0, (R)0};
+    const cplx<R> b =
+        tr.has(e + NH) ? checker(base[(size_t)(e + NH) * ncols + c], e + NH)
+                       : cplx<R>{(R)0, (R)0};
     diff[it][r] = cmul(csub(a, b), twiddle_full(tw, e, s));
     return cadd(a, b);
   };
@@ -781,7 +814,8 @@ bool rows_t(cplx<R>* data, int64_t nrows, const cplx<R>* tw, R s,
 
 template <typename R, int LOGN>
 bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
-            const uint32_t* strips, int strip_w, hipStream_t st) {
+            const uint32_t* strips, int strip_w, const uint32_t* tiles,
+            hipStream_t st) {
   if constexpr (LOGN > 12) {
     return false;
   } else {
@@ -800,16 +834,16 @@ bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
     constexpr int NT2 = (N / 2 * BC2) / 8 > 1024 ? 1024 : (N / 2 * BC2) / 8;
     if (ncols % BC2 == 0) {
       const int nb2 = (ncols / BC2) * nplanes;
-      if (strips != nullptr && strip_w % BC2 != 0) strips = nullptr;
+      if (strip_w % BC2 != 0) strips = tiles = nullptr;
       hipLaunchKernelGGL((k_fft_cols_split<R, LOGN - 1, BC2, NT2>),
                          dim3(((nb2 + 7) / 8) * 8), dim3(NT2), 0, st, data,
-                         ncols, nplanes, tw, s, strips, strip_w);
+                         ncols, nplanes, tw, s, strips, strip_w, tiles);
       return true;
     }
   }
-  if (strips != nullptr && strip_w % BC != 0) strips = nullptr;
+  if (strip_w % BC != 0) strips = tiles = nullptr;
   hipLaunchKernelGGL((k_fft_cols<R, LOGN, BC, NT>), dim3(grid), dim3(NT), 0,
-                     st, data, ncols, nplanes, tw, s, strips, strip_w);
+                     st, data, ncols, nplanes, tw, s, strips, strip_w, tiles);
   return true;
   }
 }
@@ -924,12 +958,12 @@ bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw, int sign,
 template <typename R>
 bool launch_fft_cols(void* data, int nrows, int ncols, int nplanes,
                      const void* tw, int sign, const uint32_t* strips,
-                     int strip_w, hipStream_t st) {
+                     int strip_w, const uint32_t* tiles, hipStream_t st) {
   const int lg = ilog2(nrows);
   bool ok = false;
   WS_LOGN_SWITCH(lg, (ok = cols_t<R, LG>((cplx<R>*)data, ncols, nplanes,
                                          (const cplx<R>*)tw, (R)sign, strips,
-                                         strip_w, st)));
+                                         strip_w, tiles, st)));
   return ok;
 }
 
@@ -1019,7 +1053,8 @@ void launch_twiddles(void* tw, int n, hipStream_t st) {
   template bool launch_fft_rows<R>(void*, int, int64_t, const void*, int,    \
                                    hipStream_t);                             \
   template bool launch_fft_cols<R>(void*, int, int, int, const void*, int,   \
-                                   const uint32_t*, int, hipStream_t);       \
+                                   const uint32_t*, int, const uint32_t*,    \
+                                   hipStream_t);                             \
   template bool launch_row_screen_sum<R>(const void*, void*, const Geo&,     \
                                          const void*, const uint32_t*,       \
                                          hipStream_t);                       \

@@ -88,11 +88,13 @@ template <typename R>
 bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw,
                      int sign, hipStream_t st);
 // Column transforms; with `strips` non-null, the blocks of column strips
-// (strip_w columns of one plane) whose mark is zero are skipped.
+// (strip_w columns of one plane) whose mark is zero are skipped; with
+// `tiles` non-null (per-tile record counts, tile edge strip_w), rows of
+// tiles without records are taken as zero and not read.
 template <typename R>
 bool launch_fft_cols(void* data, int nrows, int ncols, int nplanes,
                      const void* tw, int sign, const uint32_t* strips,
-                     int strip_w, hipStream_t st);
+                     int strip_w, const uint32_t* tiles, hipStream_t st);
 template <typename R>
 bool launch_row_screen_sum(const void* planes, void* img, const Geo& g,
                            const void* tw_u, const uint32_t* strips,

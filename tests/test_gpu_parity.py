@@ -259,6 +259,48 @@ def test_image_over_calls_and_reset_skips_only_empty_strips(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(512, 512, 4), (1024, 512, 3),
+                                   (256, 256, 2)])
+@pytest.mark.parametrize("law", ["core", "gauss"])
+def test_grid_image_matches_oracle(precision, shape, law):
+    """The one-call grid + image: the form that never zeroes the tiles
+    without visibilities (tile edge 64, nu >= 512) and the plain form
+    (nu = 256)."""
+    nu, nv, nw = shape
+    wl = synth.random_case(41, n=nu, nv=nv, nw=nw, support=7, m=20000,
+                           law=law, precision=1 if precision == "fp64" else 0)
+    plan = plan_for(wl, tile=64)
+    uvw, vis, wt = dev(wl)
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = plan.grid_image(uvw, vis, wt, dropped=dropped)
+    p = o.Params.of(wl)
+    assert_close(host(img), o.image(p, wl.uvw, wl.vis, wl.weight),
+                 precision == "fp64", "grid_image")
+    assert int(dropped.item()) == o.grid(p, wl.uvw, wl.vis, wl.weight)[1]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_grid_image_reuses_a_dirty_stack(precision):
+    """Same plan, same geometry, two data sets: the second call's idle
+    tiles still hold the first call's sums and must not be read."""
+    wl1 = synth.random_case(51, n=512, nw=4, support=7, m=30000, law="core",
+                            precision=1 if precision == "fp64" else 0)
+    wl2 = synth.random_case(52, n=512, nw=4, support=7, m=500, law="gauss",
+                            precision=1 if precision == "fp64" else 0)
+    wl2.w_min, wl2.w_max = wl1.w_min, wl1.w_max
+    wl2.uvw[:, 2] = np.clip(wl2.uvw[:, 2], wl1.w_min, wl1.w_max)
+    plan = plan_for(wl1, tile=64)
+    for wl in (wl1, wl2, wl1):
+        uvw, vis, wt = dev(wl)
+        img = plan.grid_image(uvw, vis, wt)
+        ref = o.image(o.Params.of(wl), wl.uvw, wl.vis, wl.weight)
+        assert_close(host(img), ref, precision == "fp64", "reuse")
+    with pytest.raises(ws.WStackError):
+        plan.grid(uvw, vis, wt)
+        plan.grid_image(uvw, vis, wt)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("chunk", [64, 333, 0])
 def test_hot_bin_split_and_merge(precision, chunk):
     """Every visibility within a few cells of one point: tiles split into
