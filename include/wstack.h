@@ -185,6 +185,15 @@ ws_status ws_set_stream(ws_plan* plan, void* hip_stream);
 /* Wait for all work the plan enqueued; reports asynchronous HIP errors. */
 ws_status ws_sync(ws_plan* plan);
 
+/* Work counts of the last call that binned visibilities on this plan
+ * (ws_grid_visibilities, ws_grid_image, ws_degrid, or the plan's part of a
+ * batch): out[0] the tile edge in cells, out[1] tiles (of all planes) that
+ * received records, out[2] tiles that received none, out[3] tiles split
+ * into several work items, out[4] the further items of split tiles.  Waits
+ * for the plan's stream.  Diagnostics of the binning (Sec. 3.4); before any
+ * such call the counts are unspecified. */
+ws_status ws_tile_stats(ws_plan* plan, int64_t out[5]);
+
 /* Per-kernel timing: when enabled, every kernel launch of the plan is
  * bracketed by HIP events on the plan's stream and its duration is added
  * to a per-kernel total.  ws_kernel_times() waits for the plan's stream,

@@ -52,6 +52,7 @@ _SIGS = {
     "ws_wcorrect_accumulate": (C.c_int32, [_P, _P]),
     "ws_image_accumulate": (C.c_int32, [_P, _P]),
     "ws_grid_image": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P, _P]),
+    "ws_tile_stats": (C.c_int32, [_P, _P]),
     "ws_degrid": (C.c_int32, [_P, _P, C.c_int32, C.c_int64, _P, _P, _P]),
     "ws_plan_reset": (C.c_int32, [_P]),
     "ws_set_stream": (C.c_int32, [_P, _P]),

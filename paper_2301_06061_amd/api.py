@@ -157,13 +157,15 @@ class WStackPlan:
                            device=self.device)
 
     def dirty_image(self, uvw, vis, weight=None, fused=True, dropped=None):
-        """Reset, grid, transform, screen and sum: a fresh dirty image."""
+        """Reset, grid, transform, screen and sum: a fresh dirty image
+        (``fused``: one ws_grid_image call; else grid, FFT and the separate
+        screen + sum)."""
         self.reset()
         img = self.new_image()
-        self.grid(uvw, vis, weight, dropped)
         if fused:
-            self.image_accumulate(img)
+            self.grid_image(uvw, vis, weight, img, dropped)
         else:
+            self.grid(uvw, vis, weight, dropped)
             self.fft(+1)
             self.wcorrect(img)
             self.reset()
@@ -191,6 +193,13 @@ class WStackPlan:
     def sync(self):
         self._bind()
         _abi.call("ws_sync", self._h)
+
+    def tile_stats(self) -> dict:
+        """Work counts of the last binning call (waits for the stream)."""
+        out = (C.c_int64 * 5)()
+        _abi.call("ws_tile_stats", self._h, out)
+        return {"tile": out[0], "busy": out[1], "idle": out[2],
+                "split": out[3], "extra_items": out[4]}
 
     def set_profiling(self, enable: bool):
         _abi.call("ws_set_profiling", self._h, int(bool(enable)))

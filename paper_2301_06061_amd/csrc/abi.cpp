@@ -847,6 +847,25 @@ ws_status ws_sync(ws_plan* plan) {
   return WS_OK;
 }
 
+ws_status ws_tile_stats(ws_plan* plan, int64_t out[5]) {
+  WS_TRY(check_plan(plan));
+  if (out == nullptr) return fail(WS_INVALID_ARG, "out is NULL");
+  uint32_t c[8];
+  hipError_t e = hipStreamSynchronize(plan->stream);
+  if (e == hipSuccess)
+    e = hipMemcpy(c, plan->w<uint32_t>(plan->L.o_counters), sizeof(c),
+                  hipMemcpyDeviceToHost);
+  if (e != hipSuccess)
+    return fail(WS_HIP_ERROR, "reading the tile counts: %s",
+                hipGetErrorString(e));
+  out[0] = plan->g.T;
+  out[1] = c[4];
+  out[2] = c[5];
+  out[3] = c[1];
+  out[4] = c[2];
+  return WS_OK;
+}
+
 ws_status ws_set_profiling(ws_plan* plan, int32_t enable) {
   if (plan == nullptr) return fail(WS_INVALID_ARG, "plan is NULL");
   plan->profile = enable != 0;

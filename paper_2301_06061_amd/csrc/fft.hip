@@ -300,26 +300,49 @@ __global__ __launch_bounds__(NT) void k_fft_rows_split(
 // Which rows of a column block hold data, from the per-tile record
 // counts of gridding (0 = a tile without records, whose cells a fused
 // grid-and-image call leaves unwritten and the transform takes as zero).
-// Without a table every row holds data.  A wavefront of a BC-column block
-// loads 64 / BC consecutive rows; when they lie in one tile row (T >=
-// 64 / BC) the lookup is a uniform load.
-template <int BC>
+// The counts of the block's tile column (at most 64 tile rows) become one
+// 64-bit mask per wavefront in the prologue, so every element then costs a
+// shift and a select: no load, no branch, and the data loads of a
+// wavefront still issue back to back.  Without a table every row holds
+// data.
 struct TileRows {
-  const uint32_t* t;  // tile counts of this plane and column strip, or null
-  int tw, T;
+  unsigned long long mask;
+  int log_t;
+  // Issues the load of this lane's tile count (without a table, of any
+  // valid word `any`, then ignored: the load stays unconditional and
+  // nothing waits for it here); finish() turns the counts into the mask,
+  // so other loads can be issued in between.
   __device__ __forceinline__ TileRows(const uint32_t* tiles, int plane,
-                                      int nrows, int ncols, int col0, int T_)
-      : t(nullptr), tw(0), T(T_) {
-    if (tiles != nullptr) {
-      tw = ncols / T_;
-      t = tiles + (size_t)plane * (nrows / T_) * tw + col0 / T_;
-    }
+                                      int nrows, int ncols, int col0,
+                                      int log_t_, const void* any)
+      : mask(~0ull), log_t(log_t_), rows(nrows >> log_t_),
+        table(tiles != nullptr) {
+    const int tw = ncols >> log_t;
+    const int lane = (int)(threadIdx.x & 63);
+    const uint32_t* src =
+        table ? tiles + (size_t)plane * rows * tw + (col0 >> log_t) +
+                    (size_t)min(lane, rows - 1) * tw
+              : (const uint32_t*)any;
+    count = *src;
   }
-  __device__ __forceinline__ bool has(int e) const {
-    if (t == nullptr) return true;
-    const uint32_t row = (uint32_t)e / (uint32_t)T;
-    return t[(size_t)(T * BC >= 64 ? uniform_u32(row) : row) * tw] != 0u;
+  __device__ __forceinline__ void finish() {
+    const unsigned long long m =
+        __ballot((int)(threadIdx.x & 63) < rows && count != 0u);
+    mask = table ? m : ~0ull;
   }
+  // Value v, loaded unconditionally from row e, or zero where the row was
+  // never written (a select, so whatever the unwritten cells hold, NaN
+  // patterns included, is dropped).
+  template <typename R>
+  __device__ __forceinline__ cplx<R> keep(int e, cplx<R> v) const {
+    const bool h = ((mask >> (e >> log_t)) & 1ull) != 0ull;
+    return cplx<R>{h ? v.re : (R)0, h ? v.im : (R)0};
+  }
+
+ private:
+  uint32_t count;
+  int rows;
+  bool table;
 };
 
 // Logical column block of hardware block b.  Blocks are dispatched to the
@@ -341,7 +364,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 template <typename R, int LOGN, int BC, int NT>
 __global__ __launch_bounds__(NT) void k_fft_cols(
     cplx<R>* data, int ncols, int nplanes, const cplx<R>* __restrict__ tw, R s,
-    const uint32_t* __restrict__ strips, int strip_w,
+    const uint32_t* __restrict__ strips, int log_strip,
     const uint32_t* __restrict__ tiles) {
   constexpr int N = 1 << LOGN;  // column length = number of rows
   __shared__ cplx<R> lds[lds_line<N>(BC)];
@@ -353,13 +376,13 @@ __global__ __launch_bounds__(NT) void k_fft_cols(
   const int plane = L / nb_plane;
   const int col0 = (L - plane * nb_plane) * BC;
   if (strips != nullptr &&
-      strips[plane * (ncols / strip_w) + col0 / strip_w] == 0u)
+      strips[plane * (ncols >> log_strip) + (col0 >> log_strip)] == 0u)
     return;
   cplx<R>* base = data + (size_t)plane * N * ncols + col0;
-  const TileRows<BC> tr(tiles, plane, N, ncols, col0, strip_w);
+  TileRows tr(tiles, plane, N, ncols, col0, log_strip, base);
+  tr.finish();
   auto ld = [&](int e, int c, int, int) {
-    return tr.has(e) ? checker(base[(size_t)e * ncols + c], e)
-                     : cplx<R>{(R)0, (R)0};
+    return tr.keep(e, checker(base[(size_t)e * ncols + c], e));
   };
   auto st = [&](int e, int c, int, int, cplx<R> v) {
     base[(size_t)e * ncols + c] = checker(v, e);
@@ -379,14 +402,14 @@ __global__ __launch_bounds__(NT) void k_fft_cols(
 template <typename R, int LOGH, int BC, int NT>
 __global__ __launch_bounds__(NT) void k_fft_cols_split(
     cplx<R>* data, int ncols, int nplanes, const cplx<R>* __restrict__ tw, R s,
-    const uint32_t* __restrict__ strips, int strip_w,
+    const uint32_t* __restrict__ strips, int log_strip,
     const uint32_t* __restrict__ tiles) {
   constexpr int NH = 1 << LOGH;  // half the column length
   constexpr int N = 2 * NH;
   __shared__ cplx<R> lds[lds_line<NH>(BC)];
   __shared__ cplx<R> s_lo[kTwLo], s_hi[(NH + kTwLo - 1) / kTwLo];
+  __shared__ cplx<R> f_lo[kTwLo], f_hi[N / kTwLo];
   using F0 = Stage<R, LOGH, BC, NT, 0>;
-  using FL = Stage<R, LOGH, BC, NT, F0::NPASS - 1>;
   const int nb_plane = ncols / BC;
   const int nb = nb_plane * nplanes;
   const int L = xcd_block<R, BC>((int)blockIdx.x, nb);
@@ -394,20 +417,40 @@ __global__ __launch_bounds__(NT) void k_fft_cols_split(
   const int plane = L / nb_plane;
   const int col0 = (L - plane * nb_plane) * BC;
   if (strips != nullptr &&
-      strips[plane * (ncols / strip_w) + col0 / strip_w] == 0u)
+      strips[plane * (ncols >> log_strip) + (col0 >> log_strip)] == 0u)
     return;
   cplx<R>* base = data + (size_t)plane * N * ncols + col0;
-  const Twiddles<R> twl = load_twiddles_sub(s_lo, s_hi, tw, NH, N);
+  // The loads of the prologue go first (the hardware returns loads in
+  // order): one entry of the four twiddle tables per thread (W_NH^m and
+  // W_NH^(64 m) for the half-length stages, W_N^m and W_N^(64 m) for the
+  // difference terms), and the tile counts.
+  static_assert(NT >= 4 * kTwLo && N / kTwLo <= kTwLo, "one entry a thread");
+  const int tq = min((int)threadIdx.x / kTwLo, 3), tm = threadIdx.x % kTwLo;
+  const int tidx = tq == 0   ? 2 * tm
+                   : tq == 1 ? tm
+                   : tq == 2 ? 2 * kTwLo * min(tm, NH / kTwLo - 1)
+                             : kTwLo * min(tm, N / kTwLo - 1);
+  const cplx<R> tval = tw[tidx];
+  TileRows tr(tiles, plane, N, ncols, col0, log_strip, base);
+  if (threadIdx.x < 4 * kTwLo) {
+    if (tq == 0) s_lo[tm] = tval;
+    else if (tq == 1) f_lo[tm] = tval;
+    else if (tq == 2) { if (tm < NH / kTwLo) s_hi[tm] = tval; }
+    else if (tm < N / kTwLo) f_hi[tm] = tval;
+  }
+  tr.finish();
+  const Twiddles<R> twl{s_lo, s_hi}, twf{f_lo, f_hi};
   __syncthreads();
   cplx<R> diff[F0::IT][F0::RAD];
-  const TileRows<BC> tr(tiles, plane, N, ncols, col0, strip_w);
+  // Each pair of samples is loaded where the first stage needs it.  With
+  // one 1024-thread workgroup per CU, loads interleaved with the arithmetic
+  // keep HBM busy while the butterflies run; requesting them all before any
+  // arithmetic measured about 10% slower.
   auto ld_sum = [&](int e, int c, int it, int r) {
-    const cplx<R> a = tr.has(e) ? checker(base[(size_t)e * ncols + c], e)
-                                : cplx<R>{(R)0, (R)0};
-    const cplx<R> b =
-        tr.has(e + NH) ? checker(base[(size_t)(e + NH) * ncols + c], e + NH)
-                       : cplx<R>{(R)0, (R)0};
-    diff[it][r] = cmul(csub(a, b), twiddle_full(tw, e, s));
+    const cplx<R> a = tr.keep(e, checker(base[(size_t)e * ncols + c], e));
+    const cplx<R> b = tr.keep(
+        e + NH, checker(base[(size_t)(e + NH) * ncols + c], e + NH));
+    diff[it][r] = cmul(csub(a, b), twf(e, s));
     return cadd(a, b);
   };
   // Output 2e has the centring sign +1, output 2e + 1 the sign -1.
@@ -812,6 +855,12 @@ bool rows_t(cplx<R>* data, int64_t nrows, const cplx<R>* tw, R s,
   }
 }
 
+int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
 template <typename R, int LOGN>
 bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
             const uint32_t* strips, int strip_w, const uint32_t* tiles,
@@ -821,6 +870,15 @@ bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
   } else {
   constexpr int N = 1 << LOGN;
   constexpr int ELEM = sizeof(cplx<R>);
+  // Strips and tile rows are powers of two; a tile table covers at most
+  // 64 tile rows (one bit each in a wavefront mask).
+  const bool pow2 = strip_w > 0 && (strip_w & (strip_w - 1)) == 0;
+  if (!pow2) {
+    if (tiles != nullptr) return false;
+    strips = nullptr;
+  }
+  const int log_strip = pow2 ? ilog2(strip_w) : 0;
+  if (tiles != nullptr && (N >> log_strip) > 64) return false;
   // Widest column block (<= 16) whose padded N x BC tile fits 150 KiB of
   // LDS (the twiddle tables take the rest).
   constexpr int BCMAX = (150 * 1024) / (lds_line<N>(1) * ELEM);
@@ -834,16 +892,22 @@ bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
     constexpr int NT2 = (N / 2 * BC2) / 8 > 1024 ? 1024 : (N / 2 * BC2) / 8;
     if (ncols % BC2 == 0) {
       const int nb2 = (ncols / BC2) * nplanes;
-      if (strip_w % BC2 != 0) strips = tiles = nullptr;
+      if (strip_w % BC2 != 0) {
+        if (tiles != nullptr) return false;  // the table cannot be honoured
+        strips = nullptr;
+      }
       hipLaunchKernelGGL((k_fft_cols_split<R, LOGN - 1, BC2, NT2>),
                          dim3(((nb2 + 7) / 8) * 8), dim3(NT2), 0, st, data,
-                         ncols, nplanes, tw, s, strips, strip_w, tiles);
+                         ncols, nplanes, tw, s, strips, log_strip, tiles);
       return true;
     }
   }
-  if (strip_w % BC != 0) strips = tiles = nullptr;
+  if (strip_w % BC != 0) {
+    if (tiles != nullptr) return false;
+    strips = nullptr;
+  }
   hipLaunchKernelGGL((k_fft_cols<R, LOGN, BC, NT>), dim3(grid), dim3(NT), 0,
-                     st, data, ncols, nplanes, tw, s, strips, strip_w, tiles);
+                     st, data, ncols, nplanes, tw, s, strips, log_strip, tiles);
   return true;
   }
 }
@@ -913,12 +977,6 @@ bool screen_bcast_t(const void* img, int img_real, cplx<R>* planes,
                        dim3(NT), 0, st, img, img_real, planes, g, tw);
     return true;
   }
-}
-
-int ilog2(int n) {
-  int l = 0;
-  while ((1 << l) < n) ++l;
-  return l;
 }
 
 #define WS_LOGN_SWITCH(LOGN_VAR, CALL)                                     \

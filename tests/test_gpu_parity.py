@@ -376,3 +376,23 @@ def test_config1_full_image(precision):
     assert_close(img, ref, precision == "fp64", "config1")
     if precision == "fp32":
         print(f"config1 FP32 rel-L2 {rel_l2(img, ref):.3e}")
+
+
+@pytest.mark.parametrize("tile", [16, 32, 64])
+def test_tile_stats_cover_the_tiles_the_oracle_writes(tile):
+    """Busy + idle tiles = every tile of the stack, and every tile that
+    holds a nonzero cell of the oracle's gridded stack was counted busy."""
+    wl = synth.random_case(23, n=256, nw=5, support=7, m=6000, law="core",
+                           precision=1)
+    plan = plan_for(wl, tile=tile)
+    uvw, vis, wt = dev(wl)
+    plan.reset()
+    plan.grid(uvw, vis, wt)
+    st = plan.tile_stats()
+    assert st["tile"] == tile
+    tu, tv = wl.nu // tile, wl.nv // tile
+    assert st["busy"] + st["idle"] == wl.nw * tu * tv
+    planes, _ = o.grid(o.Params.of(wl), wl.uvw, wl.vis, wl.weight)
+    nz = np.abs(planes).reshape(wl.nw, tv, tile, tu, tile).max(axis=(2, 4))
+    assert st["busy"] >= int((nz > 0).sum()) > 0
+    assert 0 <= st["split"] <= st["busy"]
