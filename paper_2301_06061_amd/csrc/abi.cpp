@@ -59,7 +59,7 @@ struct Layout {
   size_t planes_bytes;
   // workspace offsets
   size_t o_tw_u, o_tw_v, o_counts, o_sums, o_keyrank, o_rec, o_chunks,
-      o_slot, o_counters, o_split, o_extra, o_busy, o_idle,
+      o_slot, o_counters, o_split, o_extra, o_busy, o_idle, o_copies,
       o_strips, o_partials, o_scratch, total;
 };
 
@@ -155,6 +155,7 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   L->o_tw_u = take((size_t)p->nu * L->elem);
   L->o_tw_v = take((size_t)p->nv * L->elem);
   L->o_counts = take((size_t)(L->nkeys + 1) * 4);
+  L->o_copies = take((size_t)kCountCopies * L->nkeys * 4);
   L->o_sums = take((size_t)(scan_sums_len(nscan) + 1) * 4);
   L->o_keyrank = take((size_t)max_vis * 8);
   L->o_rec = take((size_t)max_vis *
@@ -304,21 +305,25 @@ ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
   uint32_t* counters = pl->w<uint32_t>(L.o_counters);
   uint32_t* split = pl->w<uint32_t>(L.o_split);
   const uint32_t chunk = degrid ? L.chunk_degrid : L.chunk;
+  uint32_t* copies = pl->w<uint32_t>(L.o_copies);
+  const uint32_t nkeys = (uint32_t)L.nkeys;
   WS_TRY(launch(pl, "zero_counts", [&] {
-    launch_zero_u32(counts, L.nkeys + 1, st);
+    launch_zero_u32(copies, kCountCopies * L.nkeys, st);
     launch_zero_u32(counters, 16, st);
     if (strips != nullptr && clear_strips)
       launch_zero_u32(strips, (int64_t)g.nw * g.tiles_u, st);
   }));
   WS_TRY(launch(pl, "bin_count", [&] {
-    launch_bin_count(g, uvw, m, counts, keyrank,
+    launch_bin_count(g, uvw, m, copies, nkeys, keyrank,
                      reinterpret_cast<unsigned long long*>(n_dropped), st);
   }));
   WS_TRY(launch(pl, "scan_keys", [&] {
+    launch_fold_copies(copies, nkeys, counts, st);
     launch_exclusive_scan(counts, counts, L.nkeys, sums, st);
+    launch_copy_offsets(copies, nkeys, counts, st);
   }));
   WS_TRY(launch(pl, "bin_scatter", [&] {
-    launch_bin_scatter<R>(g, uvw, vis, weight, m, keyrank, counts,
+    launch_bin_scatter<R>(g, uvw, vis, weight, m, keyrank, copies, nkeys,
                           pl->work + L.o_rec, degrid, st);
   }));
   WS_TRY(launch(pl, "tile_work", [&] {

@@ -28,8 +28,10 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t key) {
 
 __global__ __launch_bounds__(kCountThreads) void k_bin_count(
     Geo g, const double* __restrict__ uvw, int64_t m,
-    uint32_t* __restrict__ counts, uint2* __restrict__ keyrank,
-    unsigned long long* __restrict__ dropped) {
+    uint32_t* __restrict__ copies, uint32_t nkeys,
+    uint2* __restrict__ keyrank, unsigned long long* __restrict__ dropped) {
+  uint32_t* __restrict__ counts =
+      copies + (size_t)(blockIdx.x % kCountCopies) * nkeys;
   __shared__ uint32_t s_key[kHashSize];
   __shared__ uint32_t s_cnt[kHashSize];
   __shared__ unsigned long long s_drop;
@@ -114,6 +116,39 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(
   }
   if (tid == 0 && dropped != nullptr && s_drop != 0)
     atomicAdd(dropped, s_drop);
+}
+
+// Per-key totals of the count copies.
+__global__ __launch_bounds__(256) void k_fold_copies(
+    const uint32_t* __restrict__ copies, uint32_t nkeys,
+    uint32_t* __restrict__ totals) {
+  const uint32_t key = blockIdx.x * 256u + threadIdx.x;
+  if (key >= nkeys) return;
+  uint32_t c[kCountCopies];
+#pragma unroll
+  for (int x = 0; x < kCountCopies; ++x) c[x] = copies[(size_t)x * nkeys + key];
+  uint32_t t = 0;
+#pragma unroll
+  for (int x = 0; x < kCountCopies; ++x) t += c[x];
+  totals[key] = t;
+}
+
+// Copy x of key k becomes the offset of its first record: the key's offset
+// plus the counts of the copies before x.
+__global__ __launch_bounds__(256) void k_copy_offsets(
+    uint32_t* __restrict__ copies, uint32_t nkeys,
+    const uint32_t* __restrict__ offsets) {
+  const uint32_t key = blockIdx.x * 256u + threadIdx.x;
+  if (key >= nkeys) return;
+  uint32_t c[kCountCopies];
+#pragma unroll
+  for (int x = 0; x < kCountCopies; ++x) c[x] = copies[(size_t)x * nkeys + key];
+  uint32_t o = offsets[key];
+#pragma unroll
+  for (int x = 0; x < kCountCopies; ++x) {
+    copies[(size_t)x * nkeys + key] = o;
+    o += c[x];
+  }
 }
 
 // ---- exclusive scan of uint32 counts (reduce, scan of block sums, apply) --
@@ -211,7 +246,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
     Geo g, const double* __restrict__ uvw, const cplx<R>* __restrict__ vis,
     const float* __restrict__ weight, int64_t m,
     const uint2* __restrict__ keyrank, const uint32_t* __restrict__ offsets,
-    Record<R>* __restrict__ rec, int degrid) {
+    uint32_t nkeys, Record<R>* __restrict__ rec, int degrid) {
   const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= m) return;
   const uint2 kr = keyrank[gi];
@@ -219,7 +254,9 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
   double x, y;
   int i0, j0, k;
   place(g, uvw[3 * gi], uvw[3 * gi + 1], uvw[3 * gi + 2], x, y, i0, j0, k);
-  const uint32_t pos = offsets[kr.x] + kr.y;
+  // The copy the counting workgroup of this visibility added into.
+  const int64_t copy = (gi / kCountPerBlock) % kCountCopies;
+  const uint32_t pos = offsets[copy * nkeys + kr.x] + kr.y;
   Record<R> r;
   // Fractional offsets from the nearest cell, subtracted in FP64 first.
   r.dx = (R)(x - (double)i0);
@@ -318,12 +355,24 @@ __global__ __launch_bounds__(256) void k_tile_work(
 }  // namespace
 
 void launch_bin_count(const Geo& g, const double* uvw, int64_t m,
-                      uint32_t* counts, uint2* keyrank,
+                      uint32_t* copies, uint32_t nkeys, uint2* keyrank,
                       unsigned long long* dropped, hipStream_t st) {
   if (m == 0) return;
   const int64_t nb = (m + kCountPerBlock - 1) / kCountPerBlock;
   hipLaunchKernelGGL(k_bin_count, dim3((unsigned)nb), dim3(kCountThreads), 0,
-                     st, g, uvw, m, counts, keyrank, dropped);
+                     st, g, uvw, m, copies, nkeys, keyrank, dropped);
+}
+
+void launch_fold_copies(const uint32_t* copies, uint32_t nkeys,
+                        uint32_t* totals, hipStream_t st) {
+  hipLaunchKernelGGL(k_fold_copies, dim3((nkeys + 255) / 256), dim3(256), 0,
+                     st, copies, nkeys, totals);
+}
+
+void launch_copy_offsets(uint32_t* copies, uint32_t nkeys,
+                         const uint32_t* offsets, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_offsets, dim3((nkeys + 255) / 256), dim3(256), 0,
+                     st, copies, nkeys, offsets);
 }
 
 int64_t scan_sums_len(int64_t n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
@@ -342,23 +391,23 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
 template <typename R>
 void launch_bin_scatter(const Geo& g, const double* uvw, const void* vis,
                         const float* weight, int64_t m, const uint2* keyrank,
-                        const uint32_t* offsets, void* records,
-                        int degrid, hipStream_t st) {
+                        const uint32_t* offsets, uint32_t nkeys,
+                        void* records, int degrid, hipStream_t st) {
   if (m == 0) return;
   const int64_t nb = (m + 255) / 256;
   hipLaunchKernelGGL(k_bin_scatter<R>, dim3((unsigned)nb), dim3(256), 0, st, g,
                      uvw, (const cplx<R>*)vis, weight, m, keyrank, offsets,
-                     (Record<R>*)records, degrid);
+                     nkeys, (Record<R>*)records, degrid);
 }
 
 template void launch_bin_scatter<float>(const Geo&, const double*, const void*,
                                         const float*, int64_t, const uint2*,
-                                        const uint32_t*, void*, int,
+                                        const uint32_t*, uint32_t, void*, int,
                                         hipStream_t);
 template void launch_bin_scatter<double>(const Geo&, const double*,
                                          const void*, const float*, int64_t,
-                                         const uint2*, const uint32_t*, void*,
-                                         int, hipStream_t);
+                                         const uint2*, const uint32_t*,
+                                         uint32_t, void*, int, hipStream_t);
 
 void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t chunk, uint32_t* tile_chunks,

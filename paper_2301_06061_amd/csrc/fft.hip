@@ -330,12 +330,18 @@ struct TileRows {
         __ballot((int)(threadIdx.x & 63) < rows && count != 0u);
     mask = table ? m : ~0ull;
   }
-  // Value v, loaded unconditionally from row e, or zero where the row was
-  // never written (a select, so whatever the unwritten cells hold, NaN
-  // patterns included, is dropped).
+  __device__ __forceinline__ bool has(int e) const {
+    return ((mask >> (e >> log_t)) & 1ull) != 0ull;
+  }
+  // Sample of row e: loaded from p where the row holds data; elsewhere the
+  // load goes to `spare` (one line that every such lane shares, so it costs
+  // no HBM traffic) and the value is replaced by zero.  The load itself is
+  // unconditional, so a wavefront issues its loads back to back.
   template <typename R>
-  __device__ __forceinline__ cplx<R> keep(int e, cplx<R> v) const {
-    const bool h = ((mask >> (e >> log_t)) & 1ull) != 0ull;
+  __device__ __forceinline__ cplx<R> load(int e, const cplx<R>* p,
+                                          const cplx<R>* spare) const {
+    const bool h = has(e);
+    const cplx<R> v = *(h ? p : spare);
     return cplx<R>{h ? v.re : (R)0, h ? v.im : (R)0};
   }
 
@@ -382,7 +388,7 @@ __global__ __launch_bounds__(NT) void k_fft_cols(
   TileRows tr(tiles, plane, N, ncols, col0, log_strip, base);
   tr.finish();
   auto ld = [&](int e, int c, int, int) {
-    return tr.keep(e, checker(base[(size_t)e * ncols + c], e));
+    return checker(tr.load(e, base + (size_t)e * ncols + c, tw), e);
   };
   auto st = [&](int e, int c, int, int, cplx<R> v) {
     base[(size_t)e * ncols + c] = checker(v, e);
@@ -442,14 +448,33 @@ __global__ __launch_bounds__(NT) void k_fft_cols_split(
   const Twiddles<R> twl{s_lo, s_hi}, twf{f_lo, f_hi};
   __syncthreads();
   cplx<R> diff[F0::IT][F0::RAD];
-  // Each pair of samples is loaded where the first stage needs it.  With
-  // one 1024-thread workgroup per CU, loads interleaved with the arithmetic
-  // keep HBM busy while the butterflies run; requesting them all before any
-  // arithmetic measured about 10% slower.
-  auto ld_sum = [&](int e, int c, int it, int r) {
-    const cplx<R> a = tr.keep(e, checker(base[(size_t)e * ncols + c], e));
-    const cplx<R> b = tr.keep(
-        e + NH, checker(base[(size_t)(e + NH) * ncols + c], e + NH));
+  // The first stage takes the thread's sample pairs in order n = it * RAD +
+  // r; the pair n + AHEAD is requested when pair n is combined, so each
+  // wavefront keeps 2 AHEAD + 2 loads in flight without holding the whole
+  // strip in registers (with one workgroup per CU there is no other
+  // workgroup to hide the latency).  FP32 (512 threads, 256 registers)
+  // runs 4 pairs ahead; FP64 at 1024 threads has no registers to spare and
+  // loads each pair where it is used (measured fastest for each; requesting
+  // every pair before any arithmetic measured slower for both).
+  constexpr int AHEAD = sizeof(R) == 4 ? 4 : 0;
+  constexpr int NE = F0::IT * F0::RAD;
+  const int c0 = (int)threadIdx.x % BC, jt = (int)threadIdx.x / BC;
+  cplx<R> qa[NE], qb[NE];
+  auto issue = [&](int n) {
+    const int j = jt + (n / F0::RAD) * F0::TPC;
+    if (F0::NB % F0::TPC == 0 || j < F0::NB) {
+      const int e = j + (n % F0::RAD) * F0::NB;
+      qa[n] = tr.load(e, base + (size_t)e * ncols + c0, tw);
+      qb[n] = tr.load(e + NH, base + (size_t)(e + NH) * ncols + c0, tw);
+    }
+  };
+#pragma unroll
+  for (int n = 0; n < AHEAD && n < NE; ++n) issue(n);
+  auto ld_sum = [&](int e, int, int it, int r) {
+    const int n = it * F0::RAD + r;
+    if (n + AHEAD < NE) issue(n + AHEAD);
+    const cplx<R> a = checker(qa[n], e);
+    const cplx<R> b = checker(qb[n], e + NH);
     diff[it][r] = cmul(csub(a, b), twf(e, s));
     return cadd(a, b);
   };
@@ -889,7 +914,11 @@ bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
   if constexpr (BC * ELEM < 128 && LOGN >= 10) {
     // Twice the columns per block with the split transform.
     constexpr int BC2 = 2 * BC;
-    constexpr int NT2 = (N / 2 * BC2) / 8 > 1024 ? 1024 : (N / 2 * BC2) / 8;
+    // FP32: 512 threads (256 registers each: a deeper queue of loads per
+    // wavefront beats more wavefronts; measured 25% faster than 1024 at
+    // 4096-point columns); FP64: 1024.
+    constexpr int CAP = sizeof(R) == 4 ? 512 : 1024;
+    constexpr int NT2 = (N / 2 * BC2) / 8 > CAP ? CAP : (N / 2 * BC2) / 8;
     if (ncols % BC2 == 0) {
       const int nb2 = (ncols / BC2) * nplanes;
       if (strip_w % BC2 != 0) {

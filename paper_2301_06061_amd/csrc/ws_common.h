@@ -35,6 +35,14 @@ __device__ __forceinline__ cplx<R> csub(cplx<R> a, cplx<R> b) {
 // neighbouring tile needs form a few contiguous key ranges.
 constexpr int kRegions = 9;
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+// Key counts are kept in kCountCopies copies: workgroup b of the counting
+// kernel adds into copy b % kCountCopies, so the atomics on one key (the
+// densely sampled centre of the uv plane puts many visibilities on a few
+// keys) spread over that many addresses; the workgroups of one copy run on
+// one XCD when blocks are dealt to the XCDs in turn.  The copies are then
+// turned into per-copy offsets; any assignment of workgroups to copies
+// gives the same records.
+constexpr int kCountCopies = 8;
 // Integer cell indices are packed into 16 bits each with this offset.
 constexpr int kCellBias = 64;
 

@@ -12,17 +12,24 @@
 namespace ws {
 
 // binning (bin.hip)
+// Counts go to kCountCopies copies of nkeys words each (zeroed by the
+// caller); fold them into totals, scan the totals, then turn the copies
+// into per-copy offsets, which the scatter reads.
 void launch_bin_count(const Geo& g, const double* uvw, int64_t m,
-                      uint32_t* counts, uint2* keyrank,
+                      uint32_t* copies, uint32_t nkeys, uint2* keyrank,
                       unsigned long long* dropped, hipStream_t st);
+void launch_fold_copies(const uint32_t* copies, uint32_t nkeys,
+                        uint32_t* totals, hipStream_t st);
+void launch_copy_offsets(uint32_t* copies, uint32_t nkeys,
+                         const uint32_t* offsets, hipStream_t st);
 int64_t scan_sums_len(int64_t n);
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
                            uint32_t* sums, hipStream_t st);
 template <typename R>
 void launch_bin_scatter(const Geo& g, const double* uvw, const void* vis,
                         const float* weight, int64_t m, const uint2* keyrank,
-                        const uint32_t* offsets, void* records,
-                        int degrid, hipStream_t st);
+                        const uint32_t* offsets, uint32_t nkeys,
+                        void* records, int degrid, hipStream_t st);
 void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t chunk, uint32_t* tile_chunks,
                       uint32_t* tile_slot, uint32_t* counters,
