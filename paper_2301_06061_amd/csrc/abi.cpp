@@ -59,7 +59,7 @@ struct Layout {
   size_t planes_bytes;
   // workspace offsets
   size_t o_tw_u, o_tw_v, o_counts, o_sums, o_keyrank, o_rec, o_chunks,
-      o_slot, o_counters, o_split, o_extra, o_busy, o_idle, o_copies,
+      o_slot, o_counters, o_split, o_extra, o_busy, o_idle, o_copies, o_desc,
       o_strips, o_partials, o_scratch, total;
 };
 
@@ -167,6 +167,7 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   L->o_split = take((size_t)(L->max_slots / 2 + 1) * 4);
   L->o_extra = take((size_t)L->max_extra * 8);
   L->o_busy = take((size_t)L->ntiles * 4);
+  L->o_desc = take((size_t)(L->ntiles + L->max_extra + 1) * kDescWords * 4);
   L->o_idle = take((size_t)L->ntiles * 4);
   // Column strips (T columns of one plane) that some gridding call since
   // the reset wrote records into.
@@ -337,6 +338,15 @@ ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
   int64_t extra = (reads + chunk - 1) / chunk + 1;
   if (extra > L.max_extra) extra = L.max_extra;
   *max_items = (uint32_t)(L.ntiles + extra);
+  if (!degrid) {
+    // Extra items are capped by max_extra, so every item has a slot.
+    WS_TRY(launch(pl, "item_desc", [&] {
+      launch_item_desc(g, counts, counters, pl->w<uint2>(L.o_extra),
+                       pl->w<uint32_t>(L.o_busy), chunks, chunk,
+                       pl->w<uint32_t>(L.o_desc),
+                       (uint32_t)(L.ntiles + L.max_extra), st);
+    }));
+  }
   return WS_OK;
 }
 
@@ -354,6 +364,7 @@ GridJob<R> make_job(ws_plan* pl, int accumulate) {
   j.tile_chunks = pl->w<uint32_t>(L.o_chunks);
   j.tile_slot = pl->w<uint32_t>(L.o_slot);
   j.rec = pl->w<Record<R>>(L.o_rec);
+  j.desc = pl->w<uint32_t>(L.o_desc);
   j.chunk = L.chunk;
   j.planes = static_cast<cplx<R>*>(pl->planes);
   j.partials = pl->w<cplx<R>>(L.o_partials);
@@ -954,8 +965,8 @@ ws_status ws_batch_create(int32_t n, ws_plan* const* plans, void* work,
   b->lds = 0;
   std::vector<unsigned char> host(batch_jobs_bytes(n), 0);
   for (int i = 0; i < n; ++i) {
-    const size_t lds = (size_t)2 * plans[i]->L.T *
-                       grid_lds_pitch(plans[i]->L.T, b->K) * sizeof(double);
+    const size_t lds = grid_lds_bytes(plans[i]->L.T, b->K,
+                                      b->precision == WS_FP64 ? 8 : 4);
     if (lds > b->lds) b->lds = lds;
     if (b->precision == WS_FP64) {
       const GridJob<double> j = make_job<double>(plans[i], 0);

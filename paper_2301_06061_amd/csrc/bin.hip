@@ -18,12 +18,13 @@ namespace ws {
 namespace {
 
 constexpr int kCountThreads = 256;
-constexpr int kCountPerBlock = 2048;    // visibilities per workgroup
-constexpr int kHashSize = 4096;         // >= 2 x kCountPerBlock
+constexpr int kCountPerBlock = 4096;    // visibilities per workgroup
+constexpr int kHashSize = 8192;         // >= 2 x kCountPerBlock
+static_assert(kHashSize == 1 << 13, "hash_slot takes 13 bits");
 constexpr int kCountPerThread = kCountPerBlock / kCountThreads;
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t key) {
-  return (key * 2654435761u) >> (32 - 12);  // 12 = log2(kHashSize)
+  return (key * 2654435761u) >> (32 - 13);  // 13 = log2(kHashSize)
 }
 
 __global__ __launch_bounds__(kCountThreads) void k_bin_count(

@@ -115,11 +115,11 @@ __device__ __forceinline__ void store16(cplx<double>* p,
   *p = v[0];
 }
 
-// Store (or add) a T x T tile of FP64 LDS accumulators, held as separate
-// real and imaginary rows, into a row-major complex destination of the
-// path precision, 16 bytes per store; the LDS cells read are cleared.
-template <typename R>
-__device__ __forceinline__ void store_tile_clear(double* s_re, double* s_im,
+// Store (or add) a T x T tile of LDS accumulators (type A), held as
+// separate real and imaginary rows, into a row-major complex destination of
+// the path precision, 16 bytes per store; the LDS cells read are cleared.
+template <typename R, typename A>
+__device__ __forceinline__ void store_tile_clear(A* s_re, A* s_im,
                                                  int pitch, int T,
                                                  double scale, cplx<R>* dst,
                                                  size_t dst_pitch,
@@ -133,8 +133,8 @@ __device__ __forceinline__ void store_tile_clear(double* s_re, double* s_im,
     for (int e = 0; e < V; ++e) {
       const int a = lj * pitch + li + e;
       v[e] = {(R)(scale * s_re[a]), (R)(scale * s_im[a])};
-      s_re[a] = 0.0;
-      s_im[a] = 0.0;
+      s_re[a] = (A)0;
+      s_im[a] = (A)0;
     }
     cplx<R>* p = dst + (size_t)lj * dst_pitch + li;
     if (accumulate) {
@@ -243,53 +243,93 @@ __device__ __forceinline__ void wave_share(uint32_t f0, uint32_t f1, int w,
   e = min(b + q, f1);
 }
 
-// Resolves queue entry `local` of job j.  The loads are unconditional
-// (indices valid whatever the data), so the compiler issues them back to
-// back; the only branch is on a uniform value.
-template <typename R>
-__device__ __forceinline__ GridItem<R> prepare_item(const GridJob<R>& j,
-                                                    uint32_t local,
-                                                    uint32_t nextra,
-                                                    uint32_t total) {
-  GridItem<R> x;
-  x.valid = local < total;
-  x.tile = 0;
-  x.chunk = 0;
-  x.nch = 1;
-  x.f0 = x.f1 = 0;
-  x.off0 = 0;
-#pragma unroll
-  for (int s = 0; s < kSegments; ++s) x.cum[s] = x.step[s] = 0;
-  x.first.cell = 0;
-  x.first.dxy = x.first.val = {(R)0, (R)0};
-  if (!x.valid) return x;
-  const bool is_extra = local < nextra;
-  const uint2 tc = j.extra[is_extra ? local : 0u];
-  const uint32_t bt = j.busy[is_extra ? 0u : local - nextra];
-  x.tile = (int)uniform(is_extra ? tc.x : bt);
-  x.chunk = uniform(is_extra ? tc.y : 0u);
-  const uint32_t nch = j.tile_chunks[x.tile];
-  uint32_t lo[kSegments], hi[kSegments], a[kSegments], b[kSegments];
-  tile_segments(j.g, x.tile, lo, hi);
-#pragma unroll
-  for (int s = 0; s < kSegments; ++s) {
-    a[s] = j.offsets[lo[s]];
-    b[s] = j.offsets[hi[s]];
-  }
-  x.nch = uniform(nch);
+// Work item descriptors: everything the gridder needs to start an item,
+// written by k_item_desc after the tile work pass, so that the gridder
+// starts an item with one load instead of a chain of dependent loads (queue
+// entry -> tile -> its key ranges).  Words: tile, chunks of the tile, chunk,
+// f0, f1, off0, cum[1 .. kSegments-1], step[1 .. kSegments-1].
+static_assert(6 + 2 * (kSegments - 1) == kDescWords, "descriptor layout");
+
+__global__ __launch_bounds__(256) void k_item_desc(
+    Geo g, const uint32_t* __restrict__ offsets,
+    const uint32_t* __restrict__ counters, const uint2* __restrict__ extra,
+    const uint32_t* __restrict__ busy,
+    const uint32_t* __restrict__ tile_chunks, uint32_t chunk,
+    uint32_t* __restrict__ desc, uint32_t max_items) {
+  const uint32_t n = blockIdx.x * 256u + threadIdx.x;
+  if (n >= max_items) return;
+  const uint32_t nextra = counters[2];
+  if (n >= nextra + counters[4]) return;
+  const bool is_extra = n < nextra;
+  const uint32_t tile = is_extra ? extra[n].x : busy[n - nextra];
+  const uint32_t ch = is_extra ? extra[n].y : 0u;
+  const uint32_t nch = tile_chunks[tile];
+  uint32_t lo[kSegments], hi[kSegments];
+  tile_segments(g, (int)tile, lo, hi);
+  uint32_t w[kDescWords];
   uint32_t cum = 0, prev = 0;
 #pragma unroll
   for (int s = 0; s < kSegments; ++s) {
-    const uint32_t as = uniform(a[s]), bs = uniform(b[s]);
+    const uint32_t as = offsets[lo[s]], bs = offsets[hi[s]];
     const uint32_t off = as - cum;
-    x.cum[s] = cum;
-    x.step[s] = off - prev;
-    if (s == 0) x.off0 = off;
+    if (s == 0) {
+      w[5] = off;
+    } else {
+      w[5 + s] = cum;
+      w[5 + kSegments - 1 + s] = off - prev;
+    }
     prev = off;
     cum += bs - as;
   }
-  x.f0 = x.chunk * j.chunk;
-  x.f1 = x.nch == 1 ? cum : min(cum, x.f0 + j.chunk);
+  const uint32_t f0 = ch * chunk;
+  w[0] = tile;
+  w[1] = nch;
+  w[2] = ch;
+  w[3] = f0;
+  w[4] = nch == 1 ? cum : min(cum, f0 + chunk);
+  uint4* d = reinterpret_cast<uint4*>(desc + (size_t)n * kDescWords);
+#pragma unroll
+  for (int q = 0; q < kDescWords / 4; ++q)
+    d[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+}
+
+// A descriptor as loaded (uniform values; left in whatever registers the
+// loads produce until the item starts, so nothing waits for them early).
+struct DescRegs {
+  uint32_t w[kDescWords];
+};
+
+__device__ __forceinline__ DescRegs load_desc(const uint32_t* __restrict__ desc,
+                                              uint32_t n, bool valid) {
+  DescRegs d;
+  const uint32_t* p = desc + (size_t)(valid ? n : 0u) * kDescWords;
+#pragma unroll
+  for (int i = 0; i < kDescWords; ++i) d.w[i] = p[i];
+  return d;
+}
+
+// The item of a loaded descriptor, with this thread's share of its first
+// batch of records requested.
+template <typename R>
+__device__ __forceinline__ GridItem<R> item_from(const GridJob<R>& j,
+                                                 const DescRegs& d,
+                                                 bool valid) {
+  GridItem<R> x;
+  x.valid = valid;
+  x.tile = (int)uniform(valid ? d.w[0] : 0u);
+  x.nch = uniform(valid ? d.w[1] : 1u);
+  x.chunk = uniform(valid ? d.w[2] : 0u);
+  x.f0 = uniform(valid ? d.w[3] : 0u);
+  x.f1 = uniform(valid ? d.w[4] : 0u);
+  x.off0 = uniform(valid ? d.w[5] : 0u);
+  x.cum[0] = x.step[0] = 0;
+#pragma unroll
+  for (int s = 1; s < kSegments; ++s) {
+    x.cum[s] = uniform(valid ? d.w[5 + s] : 0u);
+    x.step[s] = uniform(valid ? d.w[5 + kSegments - 1 + s] : 0u);
+  }
+  x.first.cell = 0;
+  x.first.dxy = x.first.val = {(R)0, (R)0};
   if (x.f1 > x.f0) {
     uint32_t b, e;
     wave_share(x.f0, x.f1, threadIdx.x >> 6, blockDim.x >> 6, b, e);
@@ -298,77 +338,126 @@ __device__ __forceinline__ GridItem<R> prepare_item(const GridJob<R>& j,
   return x;
 }
 
-// Adds one record (held in lane r of the batch registers) to the LDS tile:
-// lane t of the wavefront covers kernel tap t (and t + 64, ... for K > 7).
+// Lanes of the accumulation: lane = slot * K + row, slot < RPW.  A group
+// of RPW records is added at once, each by K lanes, one kernel row per
+// lane (K = 7: 9 records on 63 lanes); a batch of the wavefront's record
+// loads (one record per lane) holds NG groups.
+template <int K>
+struct RowLanes {
+  static constexpr int RPW = 64 / K;   // records per group
+  static constexpr int NG = 64 / RPW;  // groups per batch
+  static constexpr int BS = RPW * NG;  // records per batch (<= 64)
+};
+
+// Kernel weights of one row of taps, exp(-(a - H - dx)^2 / (2 sigma^2)) for
+// a = 0 .. K-1, times the row weight gy.  FP32: one hardware exp2 per tap.
+// FP64: the ratio of neighbouring taps, q(a) = w(a+1) / w(a), itself
+// changes by the constant factor d = exp(-1 / sigma^2), so a row costs two
+// exps and two products a tap (relative rounding a few ulps of FP64).
 template <typename R, int K>
-__device__ __forceinline__ void add_record(const Geo& g, const RecBatch<R>& c,
-                                           int r, int ox, int oy, int T,
-                                           int pitch, const int* ta,
-                                           const int* tb, const int* toff,
-                                           double* s_re, double* s_im) {
-  constexpr int KK = K * K;
-  constexpr int ROUNDS = (KK + 63) / 64;
-  const int lane = threadIdx.x & 63;
-  const uint32_t cc = bcast_u(c.cell, r);
-  const R dx = bcast(c.dxy.re, r), dy = bcast(c.dxy.im, r);
-  const R vr = bcast(c.val.re, r), vi = bcast(c.val.im, r);
-  const int ci = cell_i(cc) - ox, cj = cell_j(cc) - oy;
-  const int base = cj * pitch + ci;
+struct RowWeights;
+template <int K>
+struct RowWeights<float, K> {
+  float dx;
+  float kappa;
+  __device__ __forceinline__ RowWeights(const Geo& g, float dx_, double)
+      : dx(dx_), kappa(g.kappa) {}
+  __device__ __forceinline__ float at(int a) {
+    const float ex = (float)(a - (K - 1) / 2) - dx;
+    return __builtin_amdgcn_exp2f(-kappa * (ex * ex));
+  }
+};
+template <int K>
+struct RowWeights<double, K> {
+  double w, q, d;
+  __device__ __forceinline__ RowWeights(const Geo& g, double dx, double d_) {
+    const double e0 = (double)(-(K - 1) / 2) - dx;
+    w = exp(-g.inv2s2 * (e0 * e0));
+    q = exp(-g.inv2s2 * (2.0 * e0 + 1.0));
+    d = d_;
+  }
+  __device__ __forceinline__ double at(int) {
+    const double v = w;
+    w *= q;
+    q *= d;
+    return v;
+  }
+};
+
+// Adds kernel row `row` of one record to the LDS tile (taps outside the
+// tile belong to a neighbouring tile and are skipped).
+template <typename R, int K>
+__device__ __forceinline__ void add_row(const Geo& g, uint32_t cc, R dx, R dy,
+                                        R vr, R vi, int row, int ox, int oy,
+                                        int T, int pitch, double d,
+                                        GridAcc<R>* s_re, GridAcc<R>* s_im) {
+  constexpr int H = (K - 1) / 2;
+  const int ci = cell_i(cc) - ox - H;  // tile column of tap 0
+  const int lj = cell_j(cc) - oy + row - H;
+  if ((unsigned)lj >= (unsigned)T) return;
+  const R ey = (R)(row - H) - dy;
+  const R gy = gauss2(g, ey * ey);
+  const R wr = gy * vr, wi = gy * vi;
+  GridAcc<R>* pre = s_re + lj * pitch + ci;
+  GridAcc<R>* pim = s_im + lj * pitch + ci;
+  RowWeights<R, K> rw(g, dx, d);
 #pragma unroll
-  for (int q = 0; q < ROUNDS; ++q) {
-    if (KK % 64 == 0 || lane + 64 * q < KK) {
-      const int li = ci + ta[q], lj = cj + tb[q];
-      if ((unsigned)li < (unsigned)T && (unsigned)lj < (unsigned)T) {
-        const R ex = (R)ta[q] - dx, ey = (R)tb[q] - dy;
-        const R w = gauss2(g, ex * ex + ey * ey);
-        atomicAdd(s_re + base + toff[q], (double)(w * vr));
-        atomicAdd(s_im + base + toff[q], (double)(w * vi));
-      }
+  for (int a = 0; a < K; ++a) {
+    const R gx = rw.at(a);
+    if ((unsigned)(ci + a) < (unsigned)T) {
+      atomicAdd(pre + a, (GridAcc<R>)(gx * wr));
+      atomicAdd(pim + a, (GridAcc<R>)(gx * wi));
     }
   }
 }
 
+template <typename R>
+__device__ __forceinline__ R lane_value(R x, int src) {
+  return __shfl(x, src, 64);
+}
+__device__ __forceinline__ uint32_t lane_value_u(uint32_t x, int src) {
+  return (uint32_t)__shfl((int)x, src, 64);
+}
+
 // Accumulates the item's records into the LDS tile.  Each wavefront takes
-// an equal run of the item's list positions, 64 at a time (one per lane),
-// with the next 64 in flight while the current ones are added two at a
-// time (two independent chains of instructions).
+// an equal run of the item's list positions, BS at a time (one record per
+// lane), with the next BS in flight while the current ones are added a
+// group of RPW records at a time (lane values moved by lane permutes).
 template <typename R, int K>
 __device__ __forceinline__ void accumulate_item(const GridJob<R>& j,
                                                 const GridItem<R>& x,
-                                                double* s_re, double* s_im) {
-  constexpr int H = (K - 1) / 2;
-  constexpr int KK = K * K;
-  constexpr int ROUNDS = (KK + 63) / 64;
+                                                GridAcc<R>* s_re,
+                                                GridAcc<R>* s_im) {
+  using RL = RowLanes<K>;
   const int T = j.g.T;
   const int pitch = j.pitch;
   const int lane = threadIdx.x & 63;
+  const int slot = lane / K;
+  const int row = lane - slot * K;
+  const bool act = slot < RL::RPW;
+  const int src0 = act ? slot : 0;
+  // FP64 weights: the factor between neighbouring tap ratios.
+  const double d = sizeof(R) == 8 ? exp(-2.0 * j.g.inv2s2) : 0.0;
   int k, oy, ox;
   tile_origin(j.g, x.tile, k, oy, ox);
-  int ta[ROUNDS], tb[ROUNDS], toff[ROUNDS];
-#pragma unroll
-  for (int q = 0; q < ROUNDS; ++q) {
-    const int tt = lane + 64 * q;
-    ta[q] = tt % K - H;
-    tb[q] = tt / K - H;
-    toff[q] = tb[q] * pitch + ta[q];
-  }
   uint32_t b0, e;
   wave_share(x.f0, x.f1, threadIdx.x >> 6, blockDim.x >> 6, b0, e);
   RecBatch<R> cur = x.first;
   while (b0 < e) {
-    const uint32_t b1 = b0 + 64u;
+    const uint32_t b1 = b0 + (uint32_t)RL::BS;
     const RecBatch<R> nxt = load_batch(j, x, b1 + lane, e);
-    const int cnt = (e - b0) < 64u ? (int)(e - b0) : 64;
-    int r = 0;
-    for (; r + 1 < cnt; r += 2) {
-      add_record<R, K>(j.g, cur, r, ox, oy, T, pitch, ta, tb, toff, s_re,
-                       s_im);
-      add_record<R, K>(j.g, cur, r + 1, ox, oy, T, pitch, ta, tb, toff, s_re,
-                       s_im);
+    const int cnt = (e - b0) < (uint32_t)RL::BS ? (int)(e - b0) : RL::BS;
+#pragma unroll
+    for (int gq = 0; gq < RL::NG; ++gq) {
+      if (gq * RL::RPW >= cnt) break;
+      const int src = gq * RL::RPW + src0;
+      const uint32_t cc = lane_value_u(cur.cell, src);
+      const R dx = lane_value(cur.dxy.re, src), dy = lane_value(cur.dxy.im, src);
+      const R vr = lane_value(cur.val.re, src), vi = lane_value(cur.val.im, src);
+      if (act && src < cnt)
+        add_row<R, K>(j.g, cc, dx, dy, vr, vi, row, ox, oy, T, pitch, d, s_re,
+                      s_im);
     }
-    if (r < cnt)
-      add_record<R, K>(j.g, cur, r, ox, oy, T, pitch, ta, tb, toff, s_re,
-                       s_im);
     cur = nxt;
     b0 = b1;
   }
@@ -380,8 +469,9 @@ __device__ __forceinline__ void accumulate_item(const GridJob<R>& j,
 // to a tile left empty) gets zeros on a first call and nothing otherwise.
 template <typename R>
 __device__ __forceinline__ void store_item(const GridJob<R>& j,
-                                           const GridItem<R>& x, double* s_re,
-                                           double* s_im) {
+                                           const GridItem<R>& x,
+                                           GridAcc<R>* s_re,
+                                           GridAcc<R>* s_im) {
   const int T = j.g.T;
   int k, oy, ox;
   tile_origin(j.g, x.tile, k, oy, ox);
@@ -398,66 +488,81 @@ __device__ __forceinline__ void store_item(const GridJob<R>& j,
   }
 }
 
-__device__ __forceinline__ void clear_lds(double* s, uint32_t words) {
-  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) s[i] = 0.0;
+template <typename A>
+__device__ __forceinline__ void clear_lds(A* s, uint32_t words) {
+  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) s[i] = (A)0;
 }
 
-// Persistent loop over the items of a queue: thread 0 pops queue numbers
-// into *s_next; `resolve(n, job)` turns a number into an item and its job.
-// The next item is resolved (all its loads issued) after this item's
-// accumulation and before its global stores, which then drain while the
-// next item starts; the barriers order LDS only.
-template <typename R, int K, class Job, class Resolve>
-__device__ __forceinline__ void item_loop(double* s_lds, uint32_t* queue,
-                                          uint32_t* s_next, Job job0,
-                                          Resolve resolve) {
-  if (threadIdx.x == 0) *s_next = atomicAdd(queue, 1u);
+// Persistent loop over the items of a queue.  Thread 0 pops queue numbers
+// into s_next; `locate(n, job)` turns number n into its job and the index
+// of the item in that job (returns false past the end).  Queue numbers are
+// popped two items ahead: the descriptor of the item after the current one
+// is loaded while the current one accumulates, and that item's first
+// records are requested before the current tile's global stores, which
+// then drain while it starts.  The barriers order LDS only.
+template <typename R, int K, class Locate>
+__device__ __forceinline__ void item_loop(GridAcc<R>* s_lds, uint32_t* queue,
+                                          uint32_t* s_next,
+                                          const GridJob<R>* job0,
+                                          Locate locate) {
+  if (threadIdx.x == 0) {
+    s_next[0] = atomicAdd(queue, 1u);
+    s_next[1] = atomicAdd(queue, 1u);
+  }
   lds_barrier();
-  Job job = job0;
-  GridItem<R> x = resolve(uniform(*s_next), job);
+  const GridJob<R>* job = job0;
+  uint32_t li = 0;
+  bool v = locate(uniform(s_next[0]), job, li);
+  GridItem<R> x = item_from(*job, load_desc(job->desc, li, v), v);
+  const GridJob<R>* jn = job0;
+  bool vn = locate(uniform(s_next[1]), jn, li);
+  DescRegs dn = load_desc(jn->desc, li, vn);
   while (x.valid) {
-    lds_barrier();  // every thread has read *s_next; LDS is clear
-    if (threadIdx.x == 0) *s_next = atomicAdd(queue, 1u);
+    lds_barrier();  // every thread has read s_next; LDS is clear
+    if (threadIdx.x == 0) s_next[0] = atomicAdd(queue, 1u);
     const GridJob<R>& j = *job;
-    double* s_re = s_lds;
-    double* s_im = s_lds + j.g.T * j.pitch;
+    GridAcc<R>* s_re = s_lds;
+    GridAcc<R>* s_im = s_lds + j.g.T * j.pitch;
     if (x.f1 > x.f0) accumulate_item<R, K>(j, x, s_re, s_im);
-    lds_barrier();  // LDS sums complete; *s_next visible
-    Job nj = job;
-    const GridItem<R> nx = resolve(uniform(*s_next), nj);
+    lds_barrier();  // LDS sums complete; s_next visible
+    const GridItem<R> nx = item_from(*jn, dn, vn);
+    const GridJob<R>* jnn = job0;
+    const bool vnn = locate(uniform(s_next[0]), jnn, li);
+    dn = load_desc(jnn->desc, li, vnn);
     store_item(j, x, s_re, s_im);
     x = nx;
-    job = nj;
+    job = jn;
+    jn = jnn;
+    vn = vnn;
   }
 }
 
 template <typename R, int K>
 __global__ __launch_bounds__(kGridThreads) void k_grid_tiles(GridJob<R> j) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_next;
-  double* s_lds = reinterpret_cast<double*>(smem);
-  const uint32_t nextra = j.counters[2];
+  __shared__ uint32_t s_next[2];
+  GridAcc<R>* s_lds = reinterpret_cast<GridAcc<R>*>(smem);
   const uint32_t total = item_total(j.counters);
   clear_lds(s_lds, 2u * (uint32_t)(j.g.T * j.pitch));
-  const GridJob<R>* jp = &j;
-  item_loop<R, K>(s_lds, &j.counters[3], &s_next, jp,
-                  [&](uint32_t n, const GridJob<R>*&) {
-                    return prepare_item(j, n, nextra, total);
+  item_loop<R, K>(s_lds, &j.counters[3], s_next, &j,
+                  [&](uint32_t n, const GridJob<R>*&, uint32_t& li) {
+                    li = n;
+                    return n < total;
                   });
 }
 
 // Batched gridding: one persistent launch drains a single queue holding the
 // work items of every job (plan), job after job; the LDS tile is sized for
-// the largest tile of the batch (lds_words FP64 words in all).  Jobs are
+// the largest tile of the batch (lds_words accumulators in all).  Jobs are
 // read in place (uniform loads), never copied.
 template <typename R, int K>
 __global__ __launch_bounds__(kGridThreads) void k_grid_batch(
     const GridJob<R>* __restrict__ jobs, int njobs,
     uint32_t* __restrict__ queue, uint32_t lds_words) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ uint32_t s_next;
+  __shared__ uint32_t s_next[2];
   __shared__ uint32_t s_base[kMaxBatch + 1];
-  double* s_lds = reinterpret_cast<double*>(smem);
+  GridAcc<R>* s_lds = reinterpret_cast<GridAcc<R>*>(smem);
   if (threadIdx.x == 0) {
     uint32_t b = 0;
     for (int p = 0; p < njobs; ++p) {
@@ -468,18 +573,15 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_batch(
   }
   clear_lds(s_lds, lds_words);
   lds_barrier();
-  item_loop<R, K>(s_lds, queue, &s_next, jobs,
-                  [&](uint32_t n, const GridJob<R>*& jp) {
+  item_loop<R, K>(s_lds, queue, s_next, jobs,
+                  [&](uint32_t n, const GridJob<R>*& jp, uint32_t& li) {
                     int p = 0;
                     const bool live = n < s_base[njobs];
                     if (live)
                       while (n >= s_base[p + 1]) ++p;
                     jp = jobs + p;
-                    const GridJob<R>& jj = *jp;
-                    const uint32_t total =
-                        live ? item_total(jj.counters) : 0u;
-                    return prepare_item(jj, live ? n - s_base[p] : 0u,
-                                        jj.counters[2], total);
+                    li = live ? n - s_base[p] : 0u;
+                    return live;
                   });
 }
 
@@ -687,7 +789,7 @@ uint32_t persistent_groups(size_t lds_bytes, int cus, uint32_t max_items) {
 template <typename R, int K>
 void grid_k(const GridJob<R>& j, uint32_t max_items, int cus,
             hipStream_t st) {
-  const size_t lds = (size_t)2 * j.g.T * j.pitch * sizeof(double);
+  const size_t lds = grid_lds_bytes(j.g.T, K, (int)sizeof(R));
   hipLaunchKernelGGL((k_grid_tiles<R, K>),
                      dim3(persistent_groups(lds, cus, max_items)),
                      dim3(kGridThreads), lds, st, j);
@@ -700,7 +802,7 @@ void grid_batch_k(const GridJob<R>* jobs, int njobs, size_t lds,
   hipLaunchKernelGGL((k_grid_batch<R, K>),
                      dim3(persistent_groups(lds, cus, max_items)),
                      dim3(kGridThreads), lds, st, jobs, njobs, queue,
-                     (uint32_t)(lds / sizeof(double)));
+                     (uint32_t)(lds / sizeof(GridAcc<R>)));
 }
 
 template <typename R, int K>
@@ -718,6 +820,11 @@ void degrid_k(const Geo& g, const uint32_t* offsets, uint32_t* counters,
 }
 
 }  // namespace
+
+size_t grid_lds_bytes(int T, int K, int real_bytes) {
+  return (size_t)2 * T * grid_lds_pitch(T, K) *
+         (real_bytes == 8 ? sizeof(GridAcc<double>) : sizeof(GridAcc<float>));
+}
 
 int grid_lds_pitch(int T, int K) {
   // Row pitch in FP64 accumulators: T + K is odd, so the K rows of one
@@ -750,6 +857,17 @@ void launch_grid_batch(const GridJob<R>* jobs, int njobs, int K, size_t lds,
                        hipStream_t st) {
   WS_K_SWITCH(K, (grid_batch_k<R, KK>(jobs, njobs, lds, queue, max_items,
                                       cus, st)));
+}
+
+void launch_item_desc(const Geo& g, const uint32_t* offsets,
+                      const uint32_t* counters, const uint2* extra,
+                      const uint32_t* busy, const uint32_t* tile_chunks,
+                      uint32_t chunk, uint32_t* desc, uint32_t max_items,
+                      hipStream_t st) {
+  if (max_items == 0) return;
+  hipLaunchKernelGGL(k_item_desc, dim3((max_items + 255) / 256), dim3(256),
+                     0, st, g, offsets, counters, extra, busy, tile_chunks,
+                     chunk, desc, max_items);
 }
 
 template <typename R>

@@ -38,7 +38,21 @@ void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t* strips, hipStream_t st);
 
 // gridding and degridding (grid.hip)
+// LDS accumulator of the gridder: FP64 for both paths.  On gfx950 the
+// LDS add of FP64 values (ds_add_f64) is far faster than that of FP32
+// (the FP32 gridder measured 1.04 ms with FP64 sums and 5.1 ms with FP32
+// sums on 1e7 visibilities), and FP64 sums keep the per-cell error of the
+// FP32 path at the rounding of its inputs.
+template <typename R>
+struct GridAccOf {
+  using type = double;
+};
+template <typename R>
+using GridAcc = typename GridAccOf<R>::type;
 int grid_lds_pitch(int T, int K);
+// LDS bytes of one gridding tile (real and imaginary accumulators);
+// real_bytes = 4 (FP32 path) or 8 (FP64).
+size_t grid_lds_bytes(int T, int K, int real_bytes);
 size_t degrid_lds_bytes(int T, int K, int elem_bytes);
 // Everything one gridding launch needs for one plan (passed by value, or
 // as an array in device memory for a batch).
@@ -56,12 +70,21 @@ struct GridJob {
   const uint32_t* tile_chunks;
   const uint32_t* tile_slot;
   const Record<R>* rec;
+  const uint32_t* desc;       // item descriptors (kDescWords words each)
   uint32_t chunk;
   cplx<R>* planes;
   cplx<R>* partials;
   int accumulate;
 };
 
+// Descriptors of the gridding work items (after launch_tile_work), one
+// per item in queue order; desc holds max_items * kDescWords words.
+constexpr int kDescWords = 24;
+void launch_item_desc(const Geo& g, const uint32_t* offsets,
+                      const uint32_t* counters, const uint2* extra,
+                      const uint32_t* busy, const uint32_t* tile_chunks,
+                      uint32_t chunk, uint32_t* desc, uint32_t max_items,
+                      hipStream_t st);
 template <typename R>
 void launch_grid_tiles(const GridJob<R>& j, uint32_t max_items, int cus,
                        hipStream_t st);
