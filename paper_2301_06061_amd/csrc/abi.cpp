@@ -548,6 +548,14 @@ bool aligned(const void* p, size_t a) {
   return (reinterpret_cast<uintptr_t>(p) % a) == 0;
 }
 
+// Tiles without records may stay unwritten only where every later read
+// knows them: one-pass columns with tile-wide blocks and the fused rows
+// reading by strip marks (tile edge 64, rows of 512 or more).
+bool lazy_ok(const ws_plan* pl) {
+  return pl->g.T == 64 && pl->p.nv <= kOnePassCols && pl->p.nu >= 512 &&
+         pl->p.nu <= kFusedRows;
+}
+
 ws_status check_plan(ws_plan* pl) {
   if (pl == nullptr) return fail(WS_INVALID_ARG, "plan is NULL");
   if (hipSetDevice(pl->device) != hipSuccess)
@@ -605,12 +613,18 @@ ws_status batch_image_impl(ws_batch* b, const int64_t* m,
   ws_plan* p0 = b->plans[0];
   uint32_t* queue = reinterpret_cast<uint32_t*>(b->work + batch_jobs_bytes(b->n));
   WS_TRY(launch(p0, "zero_counts", [&] { launch_zero_u32(queue, 1, b->stream); }));
-  uint64_t tiles = 0;
-  for (int i = 0; i < b->n; ++i) tiles += (uint64_t)b->plans[i]->g.ntiles;
-  WS_TRY(launch(p0, "zero_idle", [&] {
-    launch_zero_idle_batch<R>(reinterpret_cast<const GridJob<R>*>(b->work),
-                              b->n, tiles, b->stream);
-  }));
+  // As in ws_grid_image: when every plan's imaging reads by tile counts
+  // and strip marks, tiles without records are never written.
+  bool lazy = true;
+  for (int i = 0; i < b->n; ++i) lazy = lazy && lazy_ok(b->plans[i]);
+  if (!lazy) {
+    uint64_t tiles = 0;
+    for (int i = 0; i < b->n; ++i) tiles += (uint64_t)b->plans[i]->g.ntiles;
+    WS_TRY(launch(p0, "zero_idle", [&] {
+      launch_zero_idle_batch<R>(reinterpret_cast<const GridJob<R>*>(b->work),
+                                b->n, tiles, b->stream);
+    }));
+  }
   WS_TRY(launch(p0, "grid_batch", [&] {
     launch_grid_batch<R>(reinterpret_cast<const GridJob<R>*>(b->work), b->n,
                          b->K, b->lds, queue, items, p0->cus, b->stream);
@@ -619,7 +633,7 @@ ws_status batch_image_impl(ws_batch* b, const int64_t* m,
     ws_plan* pl = b->plans[i];
     WS_TRY(merge_impl<R>(pl, 0));
     pl->state = kGridded;
-    ws_status st = image_impl<R>(pl, images[i]);
+    ws_status st = image_impl<R>(pl, images[i], lazy);
     pl->state = kEmpty;
     WS_TRY(st);
   }
@@ -805,13 +819,8 @@ ws_status ws_grid_image(ws_plan* plan, int64_t m, const double* uvw,
   if (plan->state != kEmpty)
     return fail(WS_BAD_STATE,
                 "the stack is not empty; call ws_plan_reset first");
-  const ws_params& p = plan->p;
-  // Tiles without records stay unwritten only where every later read
-  // knows them: one-pass columns with tile-wide blocks and the fused rows
-  // reading by strip marks (tile edge 64, rows of 512 or more).
-  const bool lazy = plan->g.T == 64 && p.nv <= kOnePassCols &&
-                    p.nu >= 512 && p.nu <= kFusedRows;
-  const bool f64 = p.precision == WS_FP64;
+  const bool lazy = lazy_ok(plan);
+  const bool f64 = plan->p.precision == WS_FP64;
   ws_status st = f64 ? grid_impl<double>(plan, m, uvw, vis, weight,
                                          n_dropped_taps, lazy)
                      : grid_impl<float>(plan, m, uvw, vis, weight,

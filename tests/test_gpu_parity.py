@@ -396,3 +396,37 @@ def test_tile_stats_cover_the_tiles_the_oracle_writes(tile):
     nz = np.abs(planes).reshape(wl.nw, tv, tile, tu, tile).max(axis=(2, 4))
     assert st["busy"] >= int((nz > 0).sum()) > 0
     assert 0 <= st["split"] <= st["busy"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_grid_image_full_length_columns_edge_tile_rows(precision):
+    """One-call path on 4096-row columns (64 tile rows of 64: every bit of
+    the column transform's tile mask), with visibilities in the first and
+    last tile rows and most tiles without records."""
+    wl = synth.random_case(47, n=512, nv=4096, nw=2, support=7, m=3000,
+                           law="gauss",
+                           precision=1 if precision == "fp64" else 0)
+    rng = np.random.default_rng(5)
+    dv = 1.0 / wl.fov_m
+    uvw = wl.uvw.copy()
+    # Cells j = 4 .. 60 (tile row 0) and 4035 .. 4091 (tile row 63), the
+    # kernel footprint still on the grid.
+    lo = rng.integers(4, 61, 150) + rng.uniform(-0.4, 0.4, 150)
+    hi = rng.integers(4035, 4092, 150) + rng.uniform(-0.4, 0.4, 150)
+    uvw[:150, 1] = (lo - wl.nv / 2) * dv
+    uvw[150:300, 1] = (hi - wl.nv / 2) * dv
+    wl = synth.Workload(wl.nu, wl.nv, wl.nw, wl.fov_l, wl.fov_m, wl.w_min,
+                        wl.w_max, wl.support, wl.sigma, wl.precision,
+                        np.ascontiguousarray(uvw), wl.vis, wl.weight,
+                        name="edge-rows")
+    plan = plan_for(wl, tile=64)
+    d_uvw, vis, wt = dev(wl)
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    plan.reset()
+    img = plan.grid_image(d_uvw, vis, wt, dropped=dropped)
+    st = plan.tile_stats()
+    assert st["idle"] > st["busy"] > 0
+    p = o.Params.of(wl)
+    assert_close(host(img), o.image(p, wl.uvw, wl.vis, wl.weight),
+                 precision == "fp64", "grid_image edge rows")
+    assert int(dropped.item()) == o.grid(p, wl.uvw, wl.vis, wl.weight)[1]
