@@ -87,6 +87,7 @@ __device__ __forceinline__ void dft(cplx<R>* v, R s) {
 // for lo < 64 and e^{2 pi i 64 hi/N}, both rounded from FP64 values.
 template <typename R>
 struct Twiddles {
+  static constexpr bool kTable = false;
   const cplx<R>* t_lo;
   const cplx<R>* t_hi;
   __device__ __forceinline__ cplx<R> operator()(int idx, R s) const {
@@ -136,6 +137,66 @@ constexpr int lds_line(int bc) {
   return (N + (N + 31) / 32) * bc;
 }
 
+// Pass structure of a length-2^LOGN transform: radix 8, the remainder
+// (radix 2 or 4) last; NS = product of the earlier radices.
+constexpr int stage_npass(int logn) { return logn / 3 + (logn % 3 ? 1 : 0); }
+constexpr int stage_rad(int logn, int P) {
+  return P < logn / 3 ? 8 : (logn % 3 == 1 ? 2 : 4);
+}
+constexpr int stage_ns(int logn, int P) { return 1 << (3 * P); }
+// Offset of stage P's entries in a stage twiddle table (stages 1 ..).
+constexpr int stage_tw_off(int logn, int P) {
+  int o = 0;
+  for (int q = 1; q < P; ++q)
+    o += (stage_rad(logn, q) - 1) * stage_ns(logn, q);
+  return o;
+}
+constexpr int stage_tw_total(int logn) {
+  return stage_tw_off(logn, stage_npass(logn));
+}
+
+// Twiddles of every stage held whole in LDS: stage P keeps
+// W^(r k N / (NS RAD)) for r = 1 .. RAD-1, k < NS at
+// tab[stage_tw_off(P) + (r - 1) NS + k] (lanes read consecutive k), the
+// transform sign applied when the table is filled.  One LDS read per
+// twiddle instead of a lookup and the powers of W^k: fewer vector
+// instructions for kernels that transform many lines per table fill.
+template <typename R>
+struct TableTwiddles {
+  static constexpr bool kTable = true;
+  const cplx<R>* tab;
+};
+
+// Fills the stage table of a length-2^LOGN transform from the line's
+// global table tw (W_N^i, i < N), conjugated for s = -1.  With
+// `centred_in`, the last stage's entries also carry (-1)^r: a (-1)^e input
+// centring gives every butterfly of the earlier stages one common sign,
+// which the radix-8 Stockham order carries to input r of the last stage
+// as (-1)^r, so the input needs no sign flips of its own.
+template <typename R, int LOGN>
+__device__ __forceinline__ void fill_stage_twiddles(cplx<R>* tab,
+                                                    const cplx<R>* tw, R s,
+                                                    bool centred_in) {
+  constexpr int N = 1 << LOGN;
+  constexpr int NPASS = stage_npass(LOGN);
+  for (int i = threadIdx.x; i < stage_tw_total(LOGN); i += blockDim.x) {
+    int idx = 0;
+    bool neg = false;
+#pragma unroll
+    for (int P = 1; P < NPASS; ++P) {
+      const int off = stage_tw_off(LOGN, P), ns = stage_ns(LOGN, P);
+      const int rad = stage_rad(LOGN, P);
+      if (i >= off && i < off + (rad - 1) * ns) {
+        const int r = (i - off) / ns + 1, k = (i - off) % ns;
+        idx = (r * k * (N / (ns * rad))) & (N - 1);
+        neg = centred_in && P == NPASS - 1 && (r & 1);
+      }
+    }
+    const cplx<R> w = tw[idx];
+    tab[i] = neg ? cplx<R>{-w.re, -s * w.im} : cplx<R>{w.re, s * w.im};
+  }
+}
+
 // Stage P of a length-2^LOGN Stockham FFT over BC interleaved columns
 // (element e of column c at lds[e * BC + c]).  Stage 0 reads through
 // ld(e, c); the last stage hands each output to st(e, c, it, r, value).
@@ -153,10 +214,10 @@ struct Stage {
   static constexpr bool FIRST = P == 0;
   static constexpr bool LAST = P == NPASS - 1;
 
-  template <class Load, class Store>
+  template <class Load, class Store, class TW>
   __device__ __forceinline__ static void run(cplx<R>* lds, const Load& ld,
-                                             const Store& st,
-                                             const Twiddles<R>& tw, R s) {
+                                             const Store& st, const TW& tw,
+                                             R s) {
     const int c = threadIdx.x % BC;
     const int jt = threadIdx.x / BC;
     cplx<R> v[IT][RAD];
@@ -178,7 +239,12 @@ struct Stage {
       const int j = jt + it * TPC;
       if (NB % TPC == 0 || j < NB) {
         const int k = j & (NS - 1);
-        if constexpr (NS > 1) {
+        if constexpr (NS > 1 && TW::kTable) {
+          constexpr int OFF = stage_tw_off(LOGN, P);
+#pragma unroll
+          for (int r = 1; r < RAD; ++r)
+            v[it][r] = cmul(v[it][r], tw.tab[OFF + (r - 1) * NS + k]);
+        } else if constexpr (NS > 1) {
           // Twiddles W^(r k N / (NS RAD)), r = 1 .. RAD-1, as powers of the
           // r = 1 value (one table lookup per butterfly; at most three
           // products deep, a few units in the last place).
@@ -216,10 +282,10 @@ struct Stage {
   }
 };
 
-template <typename R, int LOGN, int BC, int NT, class Load, class Store>
+template <typename R, int LOGN, int BC, int NT, class Load, class Store,
+          class TW>
 __device__ __forceinline__ void fft_line(cplx<R>* lds, const Load& ld,
-                                         const Store& st,
-                                         const Twiddles<R>& tw, R s) {
+                                         const Store& st, const TW& tw, R s) {
   Stage<R, LOGN, BC, NT, 0>::run(lds, ld, st, tw, s);
 }
 
@@ -607,16 +673,19 @@ struct Screen;
 template <>
 struct Screen<double> {
   cplx<double> ph, step;
-  __device__ __forceinline__ void init(const Geo& g, int p, int q, bool conj) {
+  // `odd`: the phasor also carries the output centring sign -1.
+  __device__ __forceinline__ void init(const Geo& g, int p, int q, bool conj,
+                                       bool odd = false) {
     const double nm1 = n_minus_one(g, p, q);
-    ph = turns_phasor(g.w0 * nm1);
+    ph = turns_phasor(g.w0 * nm1 + (odd ? 0.5 : 0.0));
     step = turns_phasor(g.dw * nm1);
     if (conj) {
       ph.im = -ph.im;
       step.im = -step.im;
     }
   }
-  __device__ __forceinline__ cplx<double> next(const Geo&, int) {
+  __device__ __forceinline__ cplx<double> next(const Geo&, int,
+                                               double = 0.0) {
     const cplx<double> w = ph;
     ph = cmul(ph, step);
     return w;
@@ -626,12 +695,16 @@ struct Screen<double> {
 template <>
 struct Screen<float> {
   double nm1;  // negated for the conjugate screen
-  __device__ __forceinline__ void init(const Geo& g, int p, int q, bool conj) {
+  __device__ __forceinline__ void init(const Geo& g, int p, int q, bool conj,
+                                       bool = false) {
     nm1 = n_minus_one(g, p, q);
     if (conj) nm1 = -nm1;
   }
-  __device__ __forceinline__ cplx<float> next(const Geo& g, int k) {
-    const double a = (g.w0 + (double)k * g.dw) * nm1;
+  // `half` = 1/2 adds the output centring sign -1 as half a turn, inside
+  // the FP64 phase (a fused multiply-add, so it costs nothing).
+  __device__ __forceinline__ cplx<float> next(const Geo& g, int k,
+                                              double half = 0.0) {
+    const double a = fma(g.w0 + (double)k * g.dw, nm1, half);
     const float f = (float)(a - rint(a));
     return {__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f)};
   }
@@ -665,10 +738,17 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
   using L = Stage<R, LOGN, 1, NT, (LOGN / 3) + ((LOGN % 3) ? 1 : 0) - 1>;
   constexpr int IT = L::IT, RAD = L::RAD, NB = L::NB;
   __shared__ cplx<R> lds[lds_line<N>(1)];
-  __shared__ cplx<R> s_lo[kTwLo], s_hi[(N + kTwLo - 1) / kTwLo];
+  __shared__ cplx<R> s_tab[stage_tw_total(LOGN)];
   const int q = blockIdx.x;
-  const Twiddles<R> twl = load_twiddles(s_lo, s_hi, tw, N);
+  // Stage twiddles in LDS, the input centring folded into the last stage;
+  // the output centring (-1)^p is half a turn in the screen phase (p has
+  // the parity of the thread index: NT and NB are even).
+  fill_stage_twiddles<R, LOGN>(s_tab, tw, (R)1, true);
   __syncthreads();
+  const TableTwiddles<R> twl{s_tab};
+  static_assert(NT % 2 == 0 && NB % 2 == 0, "output parity per thread");
+  const bool odd = (threadIdx.x & 1) != 0;
+  const double half = odd ? 0.5 : 0.0;
   cplx<R> acc[IT][RAD];
   Screen<R> sc[IT][RAD];
 #pragma unroll
@@ -678,7 +758,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
       const int p = threadIdx.x + it * NT + r * NB;
       acc[it][r] = {(R)0, (R)0};
       if (NB % NT == 0 || threadIdx.x + it * NT < NB)
-        sc[it][r].init(g, p, q, false);
+        sc[it][r].init(g, p, q, false, odd);
     }
   // Row q of plane k + 1 can be loaded into registers while plane k is
   // being transformed, so the HBM reads overlap the LDS stages.
@@ -724,10 +804,9 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
     marks(k + 1, on_next);
     if (kPrefetch && k + 1 < g.nw) fetch(k + 1, on_next, nxt);
     if (!kPrefetch) fetch(k, on, cur);
-    auto ld = [&](int e, int, int it, int r) { return checker(cur[it][r], e); };
-    auto st = [&](int e, int, int it, int r, cplx<R> v) {
-      v = checker(v, e);
-      const auto w = sc[it][r].next(g, k);
+    auto ld = [&](int, int, int it, int r) { return cur[it][r]; };
+    auto st = [&](int, int, int it, int r, cplx<R> v) {
+      const auto w = sc[it][r].next(g, k, half);
       acc[it][r] = cadd(acc[it][r], cmul(v, cplx<R>{(R)w.re, (R)w.im}));
     };
     fft_line<R, LOGN, 1, NT>(lds, ld, st, twl, (R)1);
