@@ -851,10 +851,14 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_screen_row_bcast
   using F0 = Stage<R, LOGN, 1, NT, 0>;
   constexpr int IT = F0::IT, RAD = F0::RAD, NB = F0::NB;
   __shared__ cplx<R> lds[lds_line<N>(1)];
-  __shared__ cplx<R> s_lo[kTwLo], s_hi[(N + kTwLo - 1) / kTwLo];
+  __shared__ cplx<R> s_tab[stage_tw_total(LOGN)];
   const int q = blockIdx.x;
-  const Twiddles<R> twl = load_twiddles(s_lo, s_hi, tw, N);
+  // Stage twiddles in LDS (conjugate: sign -1), the input centring folded
+  // into the last stage; the output centring stays on the stores (the
+  // column transform that follows centres the other axis).
+  fill_stage_twiddles<R, LOGN>(s_tab, tw, (R)-1, true);
   __syncthreads();
+  const TableTwiddles<R> twl{s_tab};
   cplx<R> x[IT][RAD];
   Screen<R> sc[IT][RAD];
 #pragma unroll
@@ -875,10 +879,9 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_screen_row_bcast
     }
   for (int k = 0; k < g.nw; ++k) {
     cplx<R>* line = planes + ((size_t)k * g.nv + q) * N;
-    auto ld = [&](int e, int, int it, int r) {
+    auto ld = [&](int, int, int it, int r) {
       const auto w = sc[it][r].next(g, k);
-      const cplx<R> v = cmul(x[it][r], cplx<R>{(R)w.re, (R)w.im});
-      return checker(v, e);
+      return cmul(x[it][r], cplx<R>{(R)w.re, (R)w.im});
     };
     auto st = [&](int e, int, int, int, cplx<R> v) { line[e] = checker(v, e); };
     fft_line<R, LOGN, 1, NT>(lds, ld, st, twl, (R)-1);
