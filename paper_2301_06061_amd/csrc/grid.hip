@@ -629,7 +629,10 @@ __global__ __launch_bounds__(1024) void k_grid_merge(
     const uint32_t* __restrict__ tile_slot,
     const cplx<R>* __restrict__ partials, cplx<R>* __restrict__ planes,
     int accumulate) {
-  // One workgroup per split tile sums its partial tiles in chunk order.
+  // Several workgroups per split tile (blockIdx.y), each summing the
+  // partials of its share of the cells in chunk order, eight loads in
+  // flight per thread: the hottest tiles have tens of chunks, and the
+  // chain of dependent sums per cell is what the merge waits on.
   if (blockIdx.x >= counters[1]) return;
   const int t = (int)split_list[blockIdx.x];
   const uint32_t nch = tile_chunks[t];
@@ -640,17 +643,17 @@ __global__ __launch_bounds__(1024) void k_grid_merge(
   cplx<R>* dst = planes + ((size_t)k * g.nv + oy) * g.nu + ox;
   const R cn = (R)g.cnorm;
   const size_t tt = (size_t)T * T;
-  for (int i = threadIdx.x; i < T * T; i += blockDim.x) {
+  for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < T * T;
+       i += gridDim.y * blockDim.x) {
     const cplx<R>* src = partials + (size_t)slot * tt + i;
     cplx<R> acc = {(R)0, (R)0};
     uint32_t c = 0;
-    for (; c + 4 <= nch; c += 4) {
-      const cplx<R> a0 = src[(c + 0) * tt], a1 = src[(c + 1) * tt];
-      const cplx<R> a2 = src[(c + 2) * tt], a3 = src[(c + 3) * tt];
-      acc = cadd(acc, a0);
-      acc = cadd(acc, a1);
-      acc = cadd(acc, a2);
-      acc = cadd(acc, a3);
+    for (; c + 8 <= nch; c += 8) {
+      cplx<R> a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = src[(c + u) * tt];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = cadd(acc, a[u]);
     }
     for (; c < nch; ++c) acc = cadd(acc, src[c * tt]);
     const int li = i % T, lj = i / T;
@@ -892,7 +895,9 @@ void launch_grid_merge(const Geo& g, const uint32_t* counters,
                        const uint32_t* tile_slot, const void* partials,
                        void* planes, int accumulate, uint32_t max_split,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_grid_merge<R>, dim3(max_split), dim3(1024), 0, st, g,
+  constexpr unsigned kMergeParts = 4;
+  hipLaunchKernelGGL(k_grid_merge<R>, dim3(max_split, kMergeParts), dim3(1024),
+                     0, st, g,
                      counters, split_list, tile_chunks, tile_slot,
                      (const cplx<R>*)partials, (cplx<R>*)planes, accumulate);
 }
