@@ -82,7 +82,7 @@ typedef int32_t ws_status;
  *   tile     gridding tile edge in cells (power of two, 16..64, > K - 1);
  *            0 = automatic
  *   chunk    most visibilities one gridding work item accumulates before a
- *            split tile is merged; 0 = automatic */
+ *            split tile is merged; 0 = automatic (4096) */
 typedef struct ws_params {
   int32_t nu, nv, nw;
   double fov_l, fov_m;

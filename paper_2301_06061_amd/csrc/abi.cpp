@@ -126,7 +126,7 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   if (L->T <= p->support - 1)
     return fail(WS_UNSUPPORTED_SIZE, "grid %d too small for support %d", nmin,
                 p->support);
-  L->chunk = p->chunk != 0 ? (uint32_t)p->chunk : 2048u;
+  L->chunk = p->chunk != 0 ? (uint32_t)p->chunk : 4096u;
   L->chunk_degrid = p->chunk != 0 ? (uint32_t)p->chunk : 4096u;
   L->elem = p->precision == WS_FP64 ? 16 : 8;
   const int64_t tu = p->nu / L->T, tv = p->nv / L->T;
