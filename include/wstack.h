@@ -229,7 +229,9 @@ ws_status ws_batch_create(int32_t n, ws_plan* const* plans, void* work,
 /* One dirty image per plan: images[i] += image of the m[i] visibilities
  * uvw[i], vis[i], weight[i] (weight may be NULL, or any weight[i] NULL).
  * The arrays are host arrays of n entries holding device pointers.  The
- * plans are reset before and after. */
+ * plans are reset before and after, and their stacks are scratch: when
+ * every plan meets the conditions of ws_grid_image for leaving tiles
+ * without visibilities unwritten, the batch leaves them unwritten too. */
 ws_status ws_batch_image(ws_batch* batch, const int64_t* m,
                          const double* const* uvw, const void* const* vis,
                          const float* const* weight, void* const* images);
