@@ -129,3 +129,38 @@ def test_config4_scaled_channels():
             assert _err(imgs[i].cpu().numpy(), ref, False) <= 1e-5, i
             checked += 1
     b.close()
+
+
+def test_batch_graph_replays_lazy_channels():
+    """Graph replays of a batch whose plans all leave tiles without records
+    unwritten (tile edge 64, rows of 512 or more): each replay starts from
+    the stacks the previous one left, with new visibility values."""
+    wls = []
+    for i, (n, nv, nw, m) in enumerate([(512, 512, 2, 4000),
+                                        (1024, 512, 3, 6000),
+                                        (512, 1024, 1, 2000)]):
+        wl = synth.random_case(30 + i, n=n, nv=nv, nw=nw, support=7, m=m,
+                               law="core", precision=0)
+        if nw == 1:
+            wl.w_max = wl.w_min
+        wls.append(wl)
+    uvw, vis, wt = _dev(wls)
+    b = BatchedImager(wls, uvw, vis, wt, precision="fp32")
+    eager = [t.clone() for t in b.run()]
+    for i, wl in enumerate(wls):
+        ref = o.image(o.Params.of(wl), wl.uvw, wl.vis, wl.weight)
+        assert _err(eager[i].cpu().numpy(), ref, False) <= 1e-5, i
+    b.capture()
+    for rep in range(3):
+        scale = float(rep + 2)
+        for i in range(len(wls)):
+            vis[i].copy_(torch.from_numpy(wls[i].vis).to(DEV) * scale)
+        torch.cuda.synchronize()
+        got = b.replay()
+        torch.cuda.synchronize()
+        for i in range(len(wls)):
+            ref = eager[i] * scale
+            err = float(torch.linalg.vector_norm(got[i] - ref) /
+                        max(float(torch.linalg.vector_norm(ref)), 1e-30))
+            assert err <= 1e-6, (rep, i, err)
+    b.close()
