@@ -154,7 +154,9 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   const int64_t nscan = L->nkeys > L->ntiles ? L->nkeys : L->ntiles;
   L->o_tw_u = take((size_t)p->nu * L->elem);
   L->o_tw_v = take((size_t)p->nv * L->elem);
+  // Key counts, scanned in place into key offsets (+ the total).
   L->o_counts = take((size_t)(L->nkeys + 1) * 4);
+  // kCountCopies copies of the key counts, turned into per-copy offsets.
   L->o_copies = take((size_t)kCountCopies * L->nkeys * 4);
   L->o_sums = take((size_t)(scan_sums_len(nscan) + 1) * 4);
   L->o_keyrank = take((size_t)max_vis * 8);
@@ -167,6 +169,7 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   L->o_split = take((size_t)(L->max_slots / 2 + 1) * 4);
   L->o_extra = take((size_t)L->max_extra * 8);
   L->o_busy = take((size_t)L->ntiles * 4);
+  // One descriptor per gridding work item (every tile, every extra chunk).
   L->o_desc = take((size_t)(L->ntiles + L->max_extra + 1) * kDescWords * 4);
   L->o_idle = take((size_t)L->ntiles * 4);
   // Column strips (T columns of one plane) that some gridding call since

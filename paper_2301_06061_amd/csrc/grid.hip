@@ -157,23 +157,6 @@ __device__ __forceinline__ void zero_tile(int T, cplx<R>* dst,
   }
 }
 
-template <typename R>
-__device__ __forceinline__ R bcast(R x, int lane);
-template <>
-__device__ __forceinline__ float bcast<float>(float x, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
-}
-template <>
-__device__ __forceinline__ double bcast<double>(double x, int lane) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) |
-                              (long long)(unsigned)lo);
-}
-__device__ __forceinline__ uint32_t bcast_u(uint32_t x, int lane) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
-}
 __device__ __forceinline__ uint32_t uniform(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
 }
