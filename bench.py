@@ -2,19 +2,26 @@
 
 One step = the whole hot path on one batch of synthetic visibilities held in
 HBM, in one call (ws_grid_image): binning + gridding onto N_w w-planes, then
-the per-plane 2-D FFT, w-screen and plane sum into the dirty image.  Default workload: 1e7 visibilities with a dense core
-(r = R U^2, w = wmax r/R + N(0, 0.1 wmax)), 4096^2 grid, 32 w-planes, 7x7
-Gaussian kernel, 5 deg field, FP32 path; the FP64 path is timed on the same
-inputs for comparison.
+the per-plane 2-D FFT, w-screen and plane sum into the dirty image.  Default
+workload: 1e7 visibilities with a dense core (r = R U^2, w = wmax r/R +
+N(0, 0.1 wmax)), 4096^2 grid, 32 w-planes, 7x7 Gaussian kernel, 5 deg field,
+FP32 path; the FP64 path is timed on the same inputs for comparison.
+
+Further legs (on by default, each skippable): the large single image
+(1e8 visibilities, 16384^2 x 32, K = 9, FP32 and FP64), 64 batched channels
+(autotuned, replayed from a HIP graph), the differentiable operator
+(degrid forward + grid backward, 1e7 visibilities, 4096^2 x 32), and the
+headline step with its host-to-device input copies (pinned memory) and the
+image copy back inside the timing.
 
 Prints one JSON line (the last line on stdout).  value = visibilities imaged
-per second (Mvis/s) over the timed steps.
+per second (Mvis/s) over the timed steps of the headline workload.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -32,30 +39,54 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(name, wl, elem, m):
-    """Bytes a kernel must move per launch (reads + writes), by definition
-    of the step it performs (not what the kernel happens to skip).
+def record_bytes(elem):
+    """Bytes of one binned record (FP32 path: elem 8; FP64: 16)."""
+    return 32 if elem == 8 else 48
 
-    fft_cols:       the 2-D transform of the stack: read + write the stack
-                    once (the row half is fused into row_screen_sum);
-    row_screen_sum: read the stack once + read/write the image once;
-    grid (step):    write every stack cell once + read each binned record
-                    once (zero_idle + grid_tiles + grid_merge together; the
-                    one-call path writes only the tiles with records);
-    bin_count:      read uvw (24 B) + write key/rank (8 B) per visibility;
-    bin_scatter:    read uvw, vis, weight, key/rank + write a record.
+
+def algorithmic_bytes(name, wl, elem, m, st=None):
+    """Bytes a kernel must move per launch (reads + writes).
+
+    Without tile statistics ``st``, the definition of the step on a full
+    stack: the 2-D transform reads and writes the stack once, the screen
+    pass reads it once and the image twice, gridding writes every cell once
+    and reads every record once.  With ``st`` (ws_tile_stats of the timed
+    one-call path), the bytes that path has to move given the work the
+    binning found: only tiles that received records are written by the
+    gridder and read by the column transform, only marked column strips
+    (tile-wide columns of one plane) are written by the column transform
+    and read by the row pass, and every record is read once per tile its
+    footprint reaches.
+      fft_cols:       busy tiles read + marked strips written;
+      row_screen_sum: marked strips read + image read and written;
+      grid (step):    busy tiles written + records read + split-tile
+                      partials written and read back by the merge;
+      bin_count:      uvw read (24 B) + key/rank written (8 B) per vis;
+      bin_scatter:    uvw, vis, weight, key/rank and the key offset read,
+                      one record written per visibility.
     """
     cells = wl.nu * wl.nv * wl.nw
     img = wl.nu * wl.nv
-    rec = 32 if elem == 8 else 48
-    vis_b = elem
-    return {
-        "fft_cols": 2 * cells * elem,
-        "row_screen_sum": cells * elem + 2 * img * elem,
-        "grid": cells * elem + m * rec,
-        "bin_count": m * (24 + 8),
-        "bin_scatter": m * (24 + vis_b + 4 + 8 + rec),
-    }.get(name)
+    rec = record_bytes(elem)
+    if st is None:
+        full = {
+            "fft_cols": 2 * cells * elem,
+            "row_screen_sum": cells * elem + 2 * img * elem,
+            "grid": cells * elem + m * rec,
+        }
+    else:
+        tile_b = st["tile"] ** 2 * elem
+        strip_b = wl.nv * st["tile"] * elem
+        parts = st["split"] + st["extra_items"]
+        full = {
+            "fft_cols": st["busy"] * tile_b + st["strips"] * strip_b,
+            "row_screen_sum": st["strips"] * strip_b + 2 * img * elem,
+            "grid": (st["busy"] * tile_b + st["record_reads"] * rec +
+                     2 * parts * tile_b),
+        }
+    full["bin_count"] = m * (24 + 8)
+    full["bin_scatter"] = m * (24 + elem + 4 + 8 + 4 + rec)
+    return full.get(name)
 
 
 def source_digest(path):
@@ -90,6 +121,85 @@ def pmc_traffic(kernel):
         return None
 
 
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on the host cores (run before any GPU use)
+# ---------------------------------------------------------------------------
+
+_CPU = {}
+
+
+def _plane_job(k):
+    """Oracle steps for plane k of the workload held in _CPU (inherited by
+    the forked workers): grid its visibilities, transform, screen + sum."""
+    from oracle import wstack as o
+    wl, kall = _CPU["wl"], _CPU["k"]
+    p = o.Params.of(wl)
+    dw = o.plane_spacing(p)
+    sel = kall == k
+    ps = o.Params(p.nu, p.nv, 1, p.fov_l, p.fov_m, p.w_min + k * dw,
+                  p.w_min + (k + 1) * dw, p.support, p.sigma)
+    t0 = time.perf_counter()
+    planes, _ = o.grid(ps, wl.uvw[sel], wl.vis[sel].astype(np.complex128),
+                       wl.weight[sel])
+    t1 = time.perf_counter()
+    f = o.fft_planes(ps, planes, +1)
+    t2 = time.perf_counter()
+    o.wcorrect(ps, f)
+    t3 = time.perf_counter()
+    return t1 - t0, t2 - t1, t3 - t2, int(sel.sum())
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, max_procs=16):
+    """The FP64 oracle on the whole headline workload, plane-parallel over
+    the host cores: one process per core (at most ``max_procs``), each
+    taking whole w-planes (grid that plane's visibilities, transform it,
+    apply its screen into an image).  value = visibilities / wall time.
+    The final sum of the per-process images is not included."""
+    from oracle import wstack as o
+    p = o.Params.of(wl)
+    _CPU["wl"] = wl
+    _CPU["k"] = o.plane_index(p, wl.uvw[:, 2])
+    procs = max(1, min(max_procs, len(os.sched_getaffinity(0))))
+    order = list(range(wl.nw))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        res = pool.map(_plane_job, order, chunksize=1)
+    wall = time.perf_counter() - t0
+    _CPU.clear()
+    tg = sum(r[0] for r in res)
+    tf = sum(r[1] for r in res)
+    ts = sum(r[2] for r in res)
+    nvis = sum(r[3] for r in res)
+    return {
+        "value": wl.m / wall / 1e6, "unit": "Mvis/s", "cores": procs,
+        "kind": "oracle",
+        "sample": (f"whole workload ({nvis} visibilities, {wl.nw} planes) "
+                   f"through the FP64 NumPy oracle, one process per core "
+                   f"taking whole planes; {wall:.1f} s wall; summed stage "
+                   f"times grid {tg:.1f} s, FFT {tf:.1f} s, screen + sum "
+                   f"{ts:.1f} s"),
+        "nproc": os.cpu_count(),
+        "cpu_model": cpu_model(),
+        "wall_s": wall,
+        "stage_cpu_s": {"grid": tg, "fft": tf, "screen": ts},
+    }
+
+
+# ---------------------------------------------------------------------------
+# GPU legs
+# ---------------------------------------------------------------------------
+
 def time_path(plan, uvw, vis, wt, img, steps, warmup, torch):
     def step():
         plan.reset()
@@ -101,11 +211,9 @@ def time_path(plan, uvw, vis, wt, img, steps, warmup, torch):
     torch.cuda.synchronize()
     plan.kernel_times(reset=True)
     plan.set_profiling(True)
-    t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     kt = plan.kernel_times(reset=True)
     plan.set_profiling(False)
     # A second timed pass without per-kernel events for the headline time.
@@ -115,51 +223,85 @@ def time_path(plan, uvw, vis, wt, img, steps, warmup, torch):
         step()
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    return (t3 - t2) / steps, (t1 - t0) / steps, kt
+    return (t3 - t2) / steps, kt
 
 
-def cpu_baseline(wl, budget_s=12.0):
-    """The FP64 oracle on a bounded sample of the same workload.
+def kernel_table(kt, wl, elem, m, st, steps):
+    """Per kernel: average launch time, the bytes the launch has to move
+    (see algorithmic_bytes), that rate against the HBM peak, and the
+    counter-measured bytes where a current summary exists."""
+    out = {}
+    for k, (tot, cnt) in kt.items():
+        avg = tot / max(cnt, 1)
+        e = {"avg_ms": avg, "launches": cnt}
+        ab = algorithmic_bytes(k, wl, elem, m, st)
+        if ab is not None and avg > 0:
+            e["bytes"] = ab
+            e["gbs"] = ab / (avg / 1e3) / 1e9
+            e["frac"] = e["gbs"] / HBM_PEAK_GBS
+            tr = pmc_traffic(k) if elem == 8 else None
+            if tr is not None:
+                e["counter_bytes"] = tr
+                e["counter_gbs"] = tr / (avg / 1e3) / 1e9
+        out[k] = e
+    g = [k for k in ("grid_tiles", "grid_merge") if k in kt]
+    if g:
+        ms = sum(kt[k][0] for k in g) / steps
+        ab = algorithmic_bytes("grid", wl, elem, m, st)
+        out["grid_step"] = {"kernels": g, "avg_ms": ms, "bytes": ab,
+                            "gbs": ab / (ms / 1e3) / 1e9,
+                            "frac": ab / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    return out
 
-    Sample: w-planes taken one at a time from the middle outwards, each with
-    the visibilities that fall on it, gridded and then transformed and
-    screened, until about ``budget_s`` seconds of oracle time are spent; the
-    time is scaled to the whole job (gridding by visibility count, FFT and
-    screen by plane count).  NumPy runs these steps on one core.
-    """
-    from oracle import wstack as o
-    p = o.Params.of(wl)
-    kall = o.plane_index(p, wl.uvw[:, 2])
-    dw = o.plane_spacing(p)
-    order = sorted(range(wl.nw), key=lambda k: abs(k - (wl.nw - 1) / 2))
-    t_grid = t_fft = 0.0
-    nvis = nplanes = 0
-    for k in order:
-        sel = kall == k
-        ps = o.Params(p.nu, p.nv, 1, p.fov_l, p.fov_m, p.w_min + k * dw,
-                      p.w_min + (k + 1) * dw, p.support, p.sigma)
-        t0 = time.perf_counter()
-        planes, _ = o.grid(ps, wl.uvw[sel], wl.vis[sel].astype(np.complex128),
-                           wl.weight[sel])
-        t1 = time.perf_counter()
-        o.wcorrect(ps, o.fft_planes(ps, planes, +1))
-        t2 = time.perf_counter()
-        t_grid += t1 - t0
-        t_fft += t2 - t1
-        nvis += int(sel.sum())
-        nplanes += 1
-        if t_grid + t_fft >= budget_s:
-            break
-    est = t_grid * wl.m / max(nvis, 1) + t_fft * wl.nw / nplanes
-    return {
-        "value": wl.m / est / 1e6, "unit": "Mvis/s", "cores": 1,
-        "kind": "oracle",
-        "sample": (f"FP64 NumPy oracle on {nplanes} of {wl.nw} w-planes: "
-                   f"{nvis} visibilities gridded in {t_grid:.1f} s, FFT + "
-                   f"screen of those planes in {t_fft:.1f} s; scaled to "
-                   f"{wl.m} visibilities and {wl.nw} planes = {est:.0f} s "
-                   f"per image"),
-    }
+
+def grid_ms(kt, steps):
+    """Gridding step time: everything but the two transform passes."""
+    return sum(v[0] for k, v in kt.items()
+               if k not in ("fft_cols", "row_screen_sum", "fft_cols4",
+                            "fft_rows", "wcorrect")) / steps
+
+
+def bench_large(args, torch, ws, synth):
+    """Large single image: 1e8 visibilities, 16384^2 x 32 planes, K = 9,
+    8 deg; FP32 and FP64 paths, a few steps each."""
+    dev = torch.device("cuda", 0)
+    t = time.perf_counter()
+    wl = synth.config3(m=args.m3, precision=0)
+    log(f"config3: {wl.m} vis drawn in {time.perf_counter() - t:.1f} s")
+    uvw = torch.from_numpy(wl.uvw).to(dev)
+    vis32 = torch.from_numpy(wl.vis).to(dev)
+    wt = torch.from_numpy(wl.weight).to(dev)
+    del wl.uvw, wl.vis, wl.weight
+    out = {"workload": "dense-core 1e8 vis, 16384^2 x 32 w-planes, K=9 "
+                       "Gaussian, 8 deg", "m": int(uvw.shape[0])}
+    steps = max(1, min(args.steps, 3))
+    imgs = {}
+    for prec in ("fp32", "fp64"):
+        vis = vis32 if prec == "fp32" else vis32.to(torch.complex128)
+        plan = ws.WStackPlan(16384, 16384, 32, wl.fov_l, wl.fov_m, wl.w_min,
+                             wl.w_max, 9, 0.0, prec,
+                             max_vis=int(uvw.shape[0]))
+        img = plan.new_image()
+        sec, kt = time_path(plan, uvw, vis, wt, img, steps, 1, torch)
+        g = grid_ms(kt, steps)
+        out[prec] = {"ms_per_step": sec * 1e3,
+                     "mvis_per_s": out["m"] / sec / 1e6,
+                     "grid_ms": g, "grid_mvis_per_s": out["m"] / g / 1e3,
+                     "kernels": {k: v[0] / max(v[1], 1)
+                                 for k, v in kt.items()}}
+        log(f"config3 {prec}: {sec * 1e3:.2f} ms/step, grid {g:.2f} ms")
+        imgs[prec] = img
+        del plan, vis
+        torch.cuda.empty_cache()
+    a = imgs["fp32"].to(torch.complex128)
+    out["rel_l2_fp32_vs_fp64"] = float(
+        torch.linalg.vector_norm(a - imgs["fp64"]) /
+        torch.linalg.vector_norm(imgs["fp64"]))
+    out["fp32_speedup"] = (out["fp64"]["ms_per_step"] /
+                           out["fp32"]["ms_per_step"])
+    del imgs, a, uvw, vis32, wt
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_degrid(args, torch, ws, synth):
@@ -179,54 +321,108 @@ def bench_degrid(args, torch, ws, synth):
         loss = (imaging_op(xt, plan, uvw, wt) - vis).abs().pow(2).sum()
         loss.backward()
 
-    for _ in range(args.warmup):
+    steps = max(1, min(args.steps, 10))
+    for _ in range(max(1, args.warmup)):
         step()
     torch.cuda.synchronize()
     plan.set_profiling(True)
     plan.kernel_times(reset=True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
+    sec = (time.perf_counter() - t0) / steps
     kt = plan.kernel_times(reset=True)
     plan.set_profiling(False)
     deg = sum(v[0] for k, v in kt.items()
-              if k in ("screen_row_bcast", "degrid_tiles", "bin_count",
-                       "bin_scatter", "scan_keys", "tile_work",
-                       "zero_counts")) / args.steps
+              if k in ("screen_row_bcast", "degrid_tiles")) / steps
     log(f"config5 forward+backward: {sec * 1e3:.3f} ms/step")
+    del plan, uvw, vis, wt, xt
+    torch.cuda.empty_cache()
     return {"ms_per_step": sec * 1e3, "mvis_per_s": wl.m / sec / 1e6,
+            "degrid_kernels_ms": deg,
             "kernels": {k: v[0] / max(v[1], 1) for k, v in kt.items()},
-            "note": "degrid forward + grid/FFT/screen backward; kernel "
-                    "times include both directions' shared binning"}
+            "note": "degrid forward + grid/FFT/screen backward (two binning "
+                    "passes, one per direction)"}
 
 
 def bench_batch(args, torch, ws, synth):
     """Config 4: 64 channels (1e5-5e6 visibilities each, 1024^2-4096^2
-    grids, 16-32 planes) imaged as one batch replayed from a HIP graph."""
+    grids, 16-32 planes) imaged as one batch replayed from a HIP graph, with
+    the (tile, chunk) of each shape class chosen by the autotuner."""
     from paper_2301_06061_amd.batch import BatchedImager
     dev = torch.device("cuda", 0)
+    os.environ.setdefault("WSTACK_AUTOTUNE_CACHE",
+                          os.path.join("/tmp", f"wstack_autotune_{os.getpid()}"
+                                       ".json"))
     wls = synth.config4()
     uvw = [torch.from_numpy(w.uvw).to(dev) for w in wls]
     vis = [torch.from_numpy(w.vis).to(dev) for w in wls]
     wt = [torch.from_numpy(w.weight).to(dev) for w in wls]
-    b = BatchedImager(wls, uvw, vis, wt, precision="fp32")
-    for _ in range(args.warmup):
+    t = time.perf_counter()
+    b = BatchedImager(wls, uvw, vis, wt, precision="fp32", tune=True)
+    tune_s = time.perf_counter() - t
+    for _ in range(max(1, args.warmup)):
         b.run()
     b.capture()
     b.replay()
     torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 10))
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         b.replay()
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
+    sec = (time.perf_counter() - t0) / steps
     m = sum(w.m for w in wls)
-    log(f"config4 batch of {len(wls)}: {sec * 1e3:.3f} ms/step")
+    choice = {}
+    for tc in b.tuned:
+        key = f"T{tc[0]}_C{tc[1]}"
+        choice[key] = choice.get(key, 0) + 1
+    log(f"config4 batch of {len(wls)}: {sec * 1e3:.3f} ms/step "
+        f"(tuning {tune_s:.1f} s: {choice})")
     b.close()
+    del uvw, vis, wt
+    torch.cuda.empty_cache()
     return {"ms_per_step": sec * 1e3, "mvis_per_s": m / sec / 1e6,
-            "channels": len(wls), "visibilities": m}
+            "channels": len(wls), "visibilities": m,
+            "autotune_s": tune_s, "tuned_tile_chunk": choice}
+
+
+def bench_with_copies(args, torch, plan, wl, img):
+    """The headline FP32 step with its input copies from pinned host memory
+    (uvw, vis, weight) and the image copy back inside the timing, as the
+    paper's GPU timings include host-device transfers."""
+    dev = torch.device("cuda", 0)
+    h_uvw = torch.from_numpy(wl.uvw).pin_memory()
+    h_vis = torch.from_numpy(wl.vis).pin_memory()
+    h_wt = torch.from_numpy(wl.weight).pin_memory()
+    h_img = torch.empty(img.shape, dtype=img.dtype).pin_memory()
+    d_uvw = torch.empty(h_uvw.shape, dtype=h_uvw.dtype, device=dev)
+    d_vis = torch.empty(h_vis.shape, dtype=h_vis.dtype, device=dev)
+    d_wt = torch.empty(h_wt.shape, dtype=h_wt.dtype, device=dev)
+
+    def step():
+        d_uvw.copy_(h_uvw, non_blocking=True)
+        d_vis.copy_(h_vis, non_blocking=True)
+        d_wt.copy_(h_wt, non_blocking=True)
+        plan.reset()
+        img.zero_()
+        plan.grid_image(d_uvw, d_vis, d_wt, image=img)
+        h_img.copy_(img, non_blocking=True)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 10))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    log(f"fp32 with pinned H2D inputs + D2H image: {sec * 1e3:.3f} ms/step")
+    return {"ms_per_step": sec * 1e3, "mvis_per_s": wl.m / sec / 1e6,
+            "h2d_bytes": int(h_uvw.nbytes + h_vis.nbytes + h_wt.nbytes),
+            "d2h_bytes": int(h_img.nbytes)}
 
 
 def main(argv=None):
@@ -235,26 +431,49 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--m", type=int, default=10_000_000)
+    ap.add_argument("--m3", type=int, default=100_000_000,
+                    help="visibilities of the large-image leg")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 16384^2 x 32, 1e8-visibility leg")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64 batched channels")
+    ap.add_argument("--no-degrid", action="store_true",
+                    help="skip the differentiable operator")
+    ap.add_argument("--no-copies", action="store_true",
+                    help="skip the copy-inclusive headline step")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline workload (no further legs, no "
+                         "CPU baseline)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run one plain elementwise kernel that reads "
                          "1 GiB and writes 1 GiB (a reference for HBM byte "
                          "counters)")
-    ap.add_argument("--degrid", action="store_true",
-                    help="also time the differentiable operator on the "
-                         "config-5 workload (degrid forward + grid backward)")
-    ap.add_argument("--batch", action="store_true",
-                    help="also time 64 batched channels (config-4 workload)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; "
+        print(json.dumps({"error": "this benchmark runs on one GPU only "
+                          "(the imaging path has no multi-GPU mode); "
                           "--gpus must be 1"}))
         return 2
+    if args.headline_only:
+        args.no_cpu_baseline = args.no_large = args.no_batch = True
+        args.no_degrid = args.no_copies = True
+
+    import synth
+    t = time.perf_counter()
+    wl = synth.config2(m=args.m, precision=0)
+    log(f"workload: {wl.m} vis, {wl.nu}^2 x {wl.nw} planes, K={wl.support} "
+        f"({time.perf_counter() - t:.1f} s to draw)")
+    cpu = None
+    if not args.no_cpu_baseline:
+        # Before any GPU use: the worker processes are forked from here.
+        cpu = cpu_baseline(wl)
+        log(f"cpu baseline: {cpu['value']:.3f} Mvis/s on {cpu['cores']} "
+            f"cores ({cpu['wall_s']:.1f} s)")
 
     import torch
     import paper_2301_06061_amd as ws
-    import synth
 
     dev = torch.device("cuda", 0)
     if args.probe_copy:
@@ -263,97 +482,75 @@ def main(argv=None):
         torch.mul(a, 2.0, out=b)  # one elementwise kernel: 1 GiB in, 1 GiB out
         torch.cuda.synchronize()
         del a, b
-    t = time.perf_counter()
-    wl = synth.config2(m=args.m, precision=0)
-    log(f"workload: {wl.m} vis, {wl.nu}^2 x {wl.nw} planes, K={wl.support} "
-        f"({time.perf_counter() - t:.1f} s to draw)")
     uvw = torch.from_numpy(wl.uvw).to(dev)
     vis32 = torch.from_numpy(wl.vis).to(dev)
     wt = torch.from_numpy(wl.weight).to(dev)
 
     plan32 = ws.WStackPlan.from_workload(wl, precision="fp32")
     img32 = plan32.new_image()
-    sec32, sec32_prof, kt32 = time_path(plan32, uvw, vis32, wt, img32,
-                                        args.steps, args.warmup, torch)
+    sec32, kt32 = time_path(plan32, uvw, vis32, wt, img32, args.steps,
+                            args.warmup, torch)
     stats32 = plan32.tile_stats()
     log(f"fp32: {sec32 * 1e3:.3f} ms/step; tiles {stats32}")
     for n_, (ms_, c_) in sorted(kt32.items(), key=lambda x: -x[1][0]):
         log(f"  {n_:18s} {ms_ / max(c_, 1):8.3f} ms x {c_}")
+    grid32 = grid_ms(kt32, args.steps)
 
     res = {}
     if not args.no_fp64:
         plan64 = ws.WStackPlan.from_workload(wl, precision="fp64")
         vis64 = vis32.to(torch.complex128)
         img64 = plan64.new_image()
-        sec64, _, kt64 = time_path(plan64, uvw, vis64, wt, img64, args.steps,
-                                   args.warmup, torch)
+        sec64, kt64 = time_path(plan64, uvw, vis64, wt, img64, args.steps,
+                                args.warmup, torch)
+        stats64 = plan64.tile_stats()
         log(f"fp64: {sec64 * 1e3:.3f} ms/step")
         for n_, (ms_, c_) in sorted(kt64.items(), key=lambda x: -x[1][0]):
             log(f"  {n_:18s} {ms_ / max(c_, 1):8.3f} ms x {c_}")
         a = img32.to(torch.complex128)
         rel = float(torch.linalg.vector_norm(a - img64) /
                     torch.linalg.vector_norm(img64))
-        grid64 = sum(kt64[k][0] for k in kt64 if k not in (
-            "fft_cols", "row_screen_sum")) / args.steps
+        grid64 = grid_ms(kt64, args.steps)
         res["fp64"] = {
             "ms_per_step": sec64 * 1e3,
             "mvis_per_s": wl.m / sec64 / 1e6,
             "grid_mvis_per_s": wl.m / (grid64 / 1e3) / 1e6,
             "fp32_speedup": sec64 / sec32,
-            "fp32_grid_speedup": None,
+            "fp32_grid_speedup": grid64 / grid32,
+            "kernels": kernel_table(kt64, wl, 16, wl.m, stats64, args.steps),
         }
         res["rel_l2_fp32_vs_fp64"] = rel
-        del plan64, img64, vis64
-    grid32 = sum(kt32[k][0] for k in kt32 if k not in (
-        "fft_cols", "row_screen_sum")) / args.steps
-    if "fp64" in res:
-        res["fp64"]["fp32_grid_speedup"] = (res["fp64"]["grid_mvis_per_s"] and
-                                            (wl.m / (grid32 / 1e3) / 1e6) /
-                                            res["fp64"]["grid_mvis_per_s"])
+        del plan64, img64, vis64, a
+        torch.cuda.empty_cache()
 
-    # Roofline of the dominant kernel (largest share of the step), from its
-    # average launch time measured with HIP events on the plan's stream.
+    # Roofline of the dominant kernel (largest share of the step): the
+    # bytes this launch has to move, over its average launch time from HIP
+    # events on the plan's stream.
+    table = kernel_table(kt32, wl, 8, wl.m, stats32, args.steps)
     name, (tot, cnt) = max(kt32.items(), key=lambda x: x[1][0])
-    avg_ms = tot / max(cnt, 1)
-    ab = algorithmic_bytes(name, wl, 8, wl.m)
+    e = table[name]
     roof = None
-    if ab is not None:
-        ach = ab / (avg_ms / 1e3) / 1e9
-        tr = pmc_traffic(name)
-        roof = {"kernel": name, "bound": "hbm", "achieved": ach,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": tr,
-                "avg_ms": avg_ms, "algorithmic_bytes": ab}
-    kernels = {k: {"avg_ms": v[0] / max(v[1], 1), "launches": v[1]}
-               for k, v in kt32.items()}
-    # The gridding step as a whole (its kernels write the stack together).
-    # Without zero_idle (the one-call path) only the tiles that received
-    # records are written: the step moves those cells plus the records.
-    gk = [k for k in ("zero_idle", "grid_tiles", "grid_merge") if k in kt32]
-    gb = None
-    if gk:
-        g_ms = sum(kt32[k][0] for k in gk) / args.steps
-        gab = algorithmic_bytes("grid", wl, 8, wl.m)
-        if "zero_idle" not in kt32:
-            gab = (wl.m * 32 +
-                   stats32["busy"] * stats32["tile"] ** 2 * 8)
-        gb = {"kernels": gk, "ms": g_ms, "bytes": gab,
-              "tiles_written": stats32["busy"],
-              "achieved_gbs": gab / (g_ms / 1e3) / 1e9,
-              "frac": gab / (g_ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    if "bytes" in e:
+        roof = {"kernel": name, "bound": "hbm", "achieved": e["gbs"],
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": e["frac"],
+                "traffic": e.get("counter_bytes"), "avg_ms": e["avg_ms"],
+                "algorithmic_bytes": e["bytes"],
+                "full_stack_bytes": algorithmic_bytes(name, wl, 8, wl.m),
+                "full_stack_effective_gbs": algorithmic_bytes(
+                    name, wl, 8, wl.m) / (e["avg_ms"] / 1e3) / 1e9}
 
     extra = {}
-    if args.degrid:
+    if not args.no_copies:
+        extra["fp32_with_copies"] = bench_with_copies(args, torch, plan32, wl,
+                                                      img32)
+    del plan32, img32, uvw, vis32, wt
+    torch.cuda.empty_cache()
+    if not args.no_degrid:
         extra["degrid_config5"] = bench_degrid(args, torch, ws, synth)
-    if args.batch:
+    if not args.no_batch:
         extra["batch_config4"] = bench_batch(args, torch, ws, synth)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        t = time.perf_counter()
-        cpu = cpu_baseline(wl)
-        log(f"cpu baseline: {cpu['value']:.3f} Mvis/s "
-            f"({time.perf_counter() - t:.1f} s)")
+    if not args.no_large:
+        extra["large_config3"] = bench_large(args, torch, ws, synth)
 
     out = {
         "metric": "Mvis/s gridded + image s, 1 GPU; FP32 vs FP64 path at "
@@ -377,8 +574,8 @@ def main(argv=None):
         "grid_mvis_per_s": wl.m / (grid32 / 1e3) / 1e6,
         "ggpas": wl.m * wl.support ** 2 / (grid32 / 1e3) / 1e9,
         "roofline": roof,
-        "grid_step_roofline": gb,
-        "kernels_fp32": kernels,
+        "tile_stats": stats32,
+        "kernels_fp32": table,
         "cpu_baseline": cpu,
     }
     out.update(res)

@@ -139,7 +139,10 @@ ws_status ws_fft_planes(ws_plan* plan, int32_t direction);
 /* w-correction and plane reduction (Eq. 2, outer integral):
  * image[q][p] += sum_k F_k[q][p] exp(+2 pi i w_k (n_pq - 1)), reading the
  * transformed stack.  image: device [nv][nu] complex, same precision as the
- * plan.  The caller zeroes the image before the first accumulation. */
+ * plan.  The caller zeroes the image before the first accumulation.
+ * Needs a transformed stack (after ws_fft_planes): on an empty plan it adds
+ * nothing and returns WS_OK; on gridded, untransformed planes it fails with
+ * WS_BAD_STATE. */
 ws_status ws_wcorrect_accumulate(ws_plan* plan, void* image);
 
 /* Fused form of ws_fft_planes(+1) followed by ws_wcorrect_accumulate():
@@ -170,7 +173,9 @@ ws_status ws_grid_image(ws_plan* plan, int64_t m, const double* uvw,
  * and w-correction.  vis_out[m] = w_m sum_taps c g g Q_k(m)[j][i] with
  * Q_k = FFT(-1)(conj(screen_k) * X).  image: device [nv][nu], complex in the
  * plan's precision, or real (float32 on the FP32 path, float64 on the FP64
- * path) when image_is_real != 0.  vis_out: device [m] complex, overwritten.
+ * path) when image_is_real != 0.  vis_out: device [m] complex, every entry
+ * overwritten; a visibility with no tap on the grid (a non-finite
+ * coordinate, or a footprint wholly off the grid) gets 0.
  * Uses the plane stack as scratch and leaves the plan reset (empty). */
 ws_status ws_degrid(ws_plan* plan, const void* image, int32_t image_is_real,
                     int64_t m, const double* uvw, const float* weight,
@@ -189,10 +194,15 @@ ws_status ws_sync(ws_plan* plan);
  * (ws_grid_visibilities, ws_grid_image, ws_degrid, or the plan's part of a
  * batch): out[0] the tile edge in cells, out[1] tiles (of all planes) that
  * received records, out[2] tiles that received none, out[3] tiles split
- * into several work items, out[4] the further items of split tiles.  Waits
- * for the plan's stream.  Diagnostics of the binning (Sec. 3.4); before any
- * such call the counts are unspecified. */
-ws_status ws_tile_stats(ws_plan* plan, int64_t out[5]);
+ * into several work items, out[4] the further items of split tiles, out[5]
+ * the column strips (tile-wide column ranges of one plane) marked as
+ * holding records since the last reset (gridding; unspecified after
+ * ws_degrid), out[6] the records read by all work items together (a
+ * record is read by its own tile and by each neighbouring tile its
+ * footprint reaches; degridding: one read per record).  Waits for the
+ * plan's stream.  Diagnostics of the binning (Sec. 3.4); before any such
+ * call the counts are unspecified. */
+ws_status ws_tile_stats(ws_plan* plan, int64_t out[7]);
 
 /* Per-kernel timing: when enabled, every kernel launch of the plan is
  * bracketed by HIP events on the plan's stream and its duration is added

@@ -196,10 +196,11 @@ class WStackPlan:
 
     def tile_stats(self) -> dict:
         """Work counts of the last binning call (waits for the stream)."""
-        out = (C.c_int64 * 5)()
+        out = (C.c_int64 * 7)()
         _abi.call("ws_tile_stats", self._h, out)
         return {"tile": out[0], "busy": out[1], "idle": out[2],
-                "split": out[3], "extra_items": out[4]}
+                "split": out[3], "extra_items": out[4], "strips": out[5],
+                "record_reads": out[6]}
 
     def set_profiling(self, enable: bool):
         _abi.call("ws_set_profiling", self._h, int(bool(enable)))

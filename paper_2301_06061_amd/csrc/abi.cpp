@@ -297,7 +297,8 @@ template <typename R>
 ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
                       const void* vis, const float* weight, int degrid,
                       int64_t* n_dropped, uint32_t* max_items,
-                      uint32_t* strips = nullptr, bool clear_strips = false) {
+                      uint32_t* strips = nullptr, bool clear_strips = false,
+                      void* vis_out = nullptr) {
   const Layout& L = pl->L;
   const Geo& g = pl->g;
   hipStream_t st = pl->stream;
@@ -328,7 +329,7 @@ ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
   }));
   WS_TRY(launch(pl, "bin_scatter", [&] {
     launch_bin_scatter<R>(g, uvw, vis, weight, m, keyrank, copies, nkeys,
-                          pl->work + L.o_rec, degrid, st);
+                          pl->work + L.o_rec, degrid, vis_out, st);
   }));
   WS_TRY(launch(pl, "tile_work", [&] {
     launch_tile_work(g, counts, degrid, chunk, chunks, slot, counters, split,
@@ -534,7 +535,8 @@ ws_status degrid_impl(ws_plan* pl, const void* image, int image_is_real,
   WS_TRY(cols_impl<R>(pl, -1, &g));
   if (m == 0) return WS_OK;
   uint32_t max_items = 0;
-  WS_TRY(bin_records<R>(pl, m, uvw, nullptr, weight, 1, nullptr, &max_items));
+  WS_TRY(bin_records<R>(pl, m, uvw, nullptr, weight, 1, nullptr, &max_items,
+                        nullptr, false, vis_out));
   WS_TRY(launch(pl, "degrid_tiles", [&] {
     launch_degrid_tiles<R>(g, pl->w<uint32_t>(L.o_counts),
                            pl->w<uint32_t>(L.o_counters),
@@ -670,6 +672,39 @@ ws_status run_batch(ws_batch* b, const int64_t* m, const double* const* uvw,
              : batch_image_impl<float>(b, m, uvw, vis, weight, images);
 }
 
+// Fills a plan over the given buffers and enqueues its twiddle tables.
+ws_status init_plan(ws_plan* pl, const ws_params* params, int64_t max_vis,
+                    const Layout& L, int dev, void* planes, void* work,
+                    void* hip_stream) {
+  pl->p = *params;
+  pl->max_vis = max_vis;
+  pl->L = L;
+  pl->g = make_geo(params, L);
+  pl->planes = planes;
+  pl->work = static_cast<unsigned char*>(work);
+  pl->stream = static_cast<hipStream_t>(hip_stream);
+  pl->state = kEmpty;
+  pl->device = dev;
+  pl->cus = 256;
+  {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount,
+                              dev) == hipSuccess && n > 0)
+      pl->cus = n;
+  }
+  pl->profile = false;
+  if (params->precision == WS_FP64) {
+    return launch(pl, "twiddles", [&] {
+      launch_twiddles<double>(pl->work + L.o_tw_u, params->nu, pl->stream);
+      launch_twiddles<double>(pl->work + L.o_tw_v, params->nv, pl->stream);
+    });
+  }
+  return launch(pl, "twiddles", [&] {
+    launch_twiddles<float>(pl->work + L.o_tw_u, params->nu, pl->stream);
+    launch_twiddles<float>(pl->work + L.o_tw_v, params->nv, pl->stream);
+  });
+}
+
 }  // namespace
 
 extern "C" {
@@ -709,35 +744,8 @@ ws_status ws_grid_init(const ws_params* params, int64_t max_vis, void* planes,
     return fail(WS_HIP_ERROR, "hipGetDevice failed (no GPU?)");
   ws_plan* pl = new (std::nothrow) ws_plan();
   if (pl == nullptr) return fail(WS_INVALID_ARG, "out of host memory");
-  pl->p = *params;
-  pl->max_vis = max_vis;
-  pl->L = L;
-  pl->g = make_geo(params, L);
-  pl->planes = planes;
-  pl->work = static_cast<unsigned char*>(work);
-  pl->stream = static_cast<hipStream_t>(hip_stream);
-  pl->state = kEmpty;
-  pl->device = dev;
-  pl->cus = 256;
-  {
-    int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount,
-                              dev) == hipSuccess && n > 0)
-      pl->cus = n;
-  }
-  pl->profile = false;
-  ws_status st;
-  if (params->precision == WS_FP64) {
-    st = launch(pl, "twiddles", [&] {
-      launch_twiddles<double>(pl->work + L.o_tw_u, params->nu, pl->stream);
-      launch_twiddles<double>(pl->work + L.o_tw_v, params->nv, pl->stream);
-    });
-  } else {
-    st = launch(pl, "twiddles", [&] {
-      launch_twiddles<float>(pl->work + L.o_tw_u, params->nu, pl->stream);
-      launch_twiddles<float>(pl->work + L.o_tw_v, params->nv, pl->stream);
-    });
-  }
+  const ws_status st = init_plan(pl, params, max_vis, L, dev, planes, work,
+                                 hip_stream);
   if (st != WS_OK) {
     delete pl;
     return st;
@@ -784,6 +792,10 @@ ws_status ws_wcorrect_accumulate(ws_plan* plan, void* image) {
   if (!aligned(image, plan->L.elem))
     return fail(WS_INVALID_ARG, "misaligned image");
   if (plan->state == kEmpty) return WS_OK;  // all planes are zero
+  if (plan->state != kTransformed)
+    return fail(WS_BAD_STATE,
+                "the stack holds gridded planes, not transforms; call "
+                "ws_fft_planes first (or ws_image_accumulate)");
   return launch(plan, "wcorrect", [&] {
     if (plan->p.precision == WS_FP64)
       launch_wcorrect<double>(plan->planes, image, plan->g, plan->stream);
@@ -875,22 +887,31 @@ ws_status ws_sync(ws_plan* plan) {
   return WS_OK;
 }
 
-ws_status ws_tile_stats(ws_plan* plan, int64_t out[5]) {
+ws_status ws_tile_stats(ws_plan* plan, int64_t out[7]) {
   WS_TRY(check_plan(plan));
   if (out == nullptr) return fail(WS_INVALID_ARG, "out is NULL");
   uint32_t c[8];
+  const size_t nstrips = (size_t)plan->g.nw * plan->g.tiles_u;
+  std::vector<uint32_t> marks(nstrips);
   hipError_t e = hipStreamSynchronize(plan->stream);
   if (e == hipSuccess)
     e = hipMemcpy(c, plan->w<uint32_t>(plan->L.o_counters), sizeof(c),
                   hipMemcpyDeviceToHost);
+  if (e == hipSuccess)
+    e = hipMemcpy(marks.data(), plan->w<uint32_t>(plan->L.o_strips),
+                  nstrips * sizeof(uint32_t), hipMemcpyDeviceToHost);
   if (e != hipSuccess)
     return fail(WS_HIP_ERROR, "reading the tile counts: %s",
                 hipGetErrorString(e));
+  int64_t marked = 0;
+  for (uint32_t v : marks) marked += v != 0u;
   out[0] = plan->g.T;
   out[1] = c[4];
   out[2] = c[5];
   out[3] = c[1];
   out[4] = c[2];
+  out[5] = marked;
+  out[6] = (int64_t)((uint64_t)c[6] | ((uint64_t)c[7] << 32));
   return WS_OK;
 }
 

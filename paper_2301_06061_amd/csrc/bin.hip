@@ -247,11 +247,17 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
     Geo g, const double* __restrict__ uvw, const cplx<R>* __restrict__ vis,
     const float* __restrict__ weight, int64_t m,
     const uint2* __restrict__ keyrank, const uint32_t* __restrict__ offsets,
-    uint32_t nkeys, Record<R>* __restrict__ rec, int degrid) {
+    uint32_t nkeys, Record<R>* __restrict__ rec, int degrid,
+    cplx<R>* __restrict__ vis_out) {
   const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= m) return;
   const uint2 kr = keyrank[gi];
-  if (kr.x == kNoKey) return;
+  if (kr.x == kNoKey) {
+    // No tap on the grid: no record, and a degridded value of zero (the
+    // gather writes only the visibilities it has records for).
+    if (degrid) vis_out[gi] = cplx<R>{(R)0, (R)0};
+    return;
+  }
   double x, y;
   int i0, j0, k;
   place(g, uvw[3 * gi], uvw[3 * gi + 1], uvw[3 * gi + 2], x, y, i0, j0, k);
@@ -300,7 +306,8 @@ __global__ __launch_bounds__(256) void k_tile_work(
     uint32_t* __restrict__ busy, uint32_t* __restrict__ idle,
     uint32_t* __restrict__ strips) {
   // counters[0]: scratch slots taken, [1]: split tiles, [2]: extra items,
-  // [4]: tiles with records (listed in busy), [5]: tiles without (idle).
+  // [4]: tiles with records (listed in busy), [5]: tiles without (idle),
+  // [6..7]: 64-bit sum of the records every tile reads.
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = t < g.ntiles;
   uint32_t work = 0;
@@ -318,6 +325,14 @@ __global__ __launch_bounds__(256) void k_tile_work(
   }
   const uint32_t ib = wave_append(&counters[4], live && work > 0);
   const uint32_t ii = wave_append(&counters[5], live && work == 0);
+  // Total record reads of the gridding items (diagnostics): one 64-bit
+  // atomic per wavefront.
+  unsigned long long wsum = work;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+    wsum += (unsigned long long)__shfl_xor((long long)wsum, o, 64);
+  if ((threadIdx.x & 63) == 0 && wsum != 0)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&counters[6]), wsum);
   if (!live) return;
   if (work > 0) busy[ib] = (uint32_t)t;
   else idle[ii] = (uint32_t)t;
@@ -393,22 +408,24 @@ template <typename R>
 void launch_bin_scatter(const Geo& g, const double* uvw, const void* vis,
                         const float* weight, int64_t m, const uint2* keyrank,
                         const uint32_t* offsets, uint32_t nkeys,
-                        void* records, int degrid, hipStream_t st) {
+                        void* records, int degrid, void* vis_out,
+                        hipStream_t st) {
   if (m == 0) return;
   const int64_t nb = (m + 255) / 256;
   hipLaunchKernelGGL(k_bin_scatter<R>, dim3((unsigned)nb), dim3(256), 0, st, g,
                      uvw, (const cplx<R>*)vis, weight, m, keyrank, offsets,
-                     nkeys, (Record<R>*)records, degrid);
+                     nkeys, (Record<R>*)records, degrid, (cplx<R>*)vis_out);
 }
 
 template void launch_bin_scatter<float>(const Geo&, const double*, const void*,
                                         const float*, int64_t, const uint2*,
                                         const uint32_t*, uint32_t, void*, int,
-                                        hipStream_t);
+                                        void*, hipStream_t);
 template void launch_bin_scatter<double>(const Geo&, const double*,
                                          const void*, const float*, int64_t,
                                          const uint2*, const uint32_t*,
-                                         uint32_t, void*, int, hipStream_t);
+                                         uint32_t, void*, int, void*,
+                                         hipStream_t);
 
 void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t chunk, uint32_t* tile_chunks,

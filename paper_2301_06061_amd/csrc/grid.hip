@@ -336,7 +336,11 @@ struct RowLanes {
 // a = 0 .. K-1, times the row weight gy.  FP32: one hardware exp2 per tap.
 // FP64: the ratio of neighbouring taps, q(a) = w(a+1) / w(a), itself
 // changes by the constant factor d = exp(-1 / sigma^2), so a row costs two
-// exps and two products a tap (relative rounding a few ulps of FP64).
+// exps and two products a tap (relative rounding a few ulps of FP64).  The
+// recurrence starts at the far-left tap, whose weight underflows (and the
+// first ratio overflows) once (h + 1/2)^2 / (2 sigma^2) nears the FP64
+// exponent range; such narrow kernels (`direct`, a uniform flag) take one
+// exp per tap instead.
 template <typename R, int K>
 struct RowWeights;
 template <int K>
@@ -352,14 +356,23 @@ struct RowWeights<float, K> {
 };
 template <int K>
 struct RowWeights<double, K> {
-  double w, q, d;
-  __device__ __forceinline__ RowWeights(const Geo& g, double dx, double d_) {
-    const double e0 = (double)(-(K - 1) / 2) - dx;
+  double w, q, d, dx, inv2s2;
+  bool direct;
+  __device__ __forceinline__ RowWeights(const Geo& g, double dx_, double d_) {
+    const double e0 = (double)(-(K - 1) / 2) - dx_;
+    // (h + 1)^2 / (2 sigma^2) bounds the exponents of w and q below.
+    direct = g.inv2s2 * (double)(((K + 1) / 2) * ((K + 1) / 2)) > 500.0;
     w = exp(-g.inv2s2 * (e0 * e0));
-    q = exp(-g.inv2s2 * (2.0 * e0 + 1.0));
+    q = direct ? 0.0 : exp(-g.inv2s2 * (2.0 * e0 + 1.0));
     d = d_;
+    dx = dx_;
+    inv2s2 = g.inv2s2;
   }
-  __device__ __forceinline__ double at(int) {
+  __device__ __forceinline__ double at(int a) {
+    if (direct) {
+      const double ex = (double)(a - (K - 1) / 2) - dx;
+      return exp(-inv2s2 * (ex * ex));
+    }
     const double v = w;
     w *= q;
     q *= d;

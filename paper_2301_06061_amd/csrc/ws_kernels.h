@@ -29,7 +29,8 @@ template <typename R>
 void launch_bin_scatter(const Geo& g, const double* uvw, const void* vis,
                         const float* weight, int64_t m, const uint2* keyrank,
                         const uint32_t* offsets, uint32_t nkeys,
-                        void* records, int degrid, hipStream_t st);
+                        void* records, int degrid, void* vis_out,
+                        hipStream_t st);
 void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t chunk, uint32_t* tile_chunks,
                       uint32_t* tile_slot, uint32_t* counters,

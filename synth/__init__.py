@@ -15,5 +15,6 @@ from .workloads import (  # noqa: F401
     config5,
     random_case,
     hermitian_pairs,
+    edge_case,
     CONFIGS,
 )

@@ -246,3 +246,65 @@ def hermitian_pairs(wl: Workload) -> Workload:
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3}
+
+
+def edge_case(seed: int, n: int = 128, nv: int = None, nw: int = 4,
+              support: int = 7, m: int = 3000, fov_deg: float = 2.0,
+              precision: int = 1, bad: bool = True) -> Workload:
+    """Footprints that hang off every edge and corner of the grid, and w
+    values outside the plane range and exactly on plane boundaries.
+
+    Positions (in cells, then wavelengths):
+      * a quarter near the low or high u edge, a quarter near the low or high
+        v edge, a quarter near a corner: the nearest cell lies within h + 1
+        cells of the edge on either side, so that anywhere from none to all
+        but one column (row) of the K x K taps is on the grid;
+      * the rest uniform over the whole grid.
+    w: the planes span [-2048, 2048] wavelengths (dw an exact power of two
+    for nw a power of two); an eighth of the visibilities each below w_min,
+    above w_max, and exactly at w_min + k dw (k = 0 .. nw, both ends
+    included); the rest uniform in the range.
+    With ``bad``, four visibilities get a NaN, an infinite or a far-off
+    coordinate.  Weights U[0.5, 1.5].
+    """
+    nv = n if nv is None else nv
+    fov_l = math.radians(fov_deg)
+    fov_m = fov_l * nv / n
+    h = (support - 1) // 2
+    rng = np.random.default_rng(seed)
+
+    def near_edge(size, cnt):
+        # Offset of the nearest cell from the edge in [-(h+1), h+1], plus a
+        # fraction of a cell, on the low or the high side.
+        off = rng.integers(-(h + 1), h + 2, cnt) + rng.uniform(-0.45, 0.45, cnt)
+        high = rng.random(cnt) < 0.5
+        return np.where(high, size - 1 - off, off)
+
+    q = m // 4
+    xs = rng.uniform(-0.5, n - 0.5, m)
+    ys = rng.uniform(-0.5, nv - 0.5, m)
+    xs[:q] = near_edge(n, q)
+    ys[q:2 * q] = near_edge(nv, q)
+    xs[2 * q:3 * q] = near_edge(n, q)
+    ys[2 * q:3 * q] = near_edge(nv, q)
+    w_min, w_max = -2048.0, 2048.0
+    dw = (w_max - w_min) / nw
+    w = rng.uniform(w_min, w_max, m)
+    e = m // 8
+    w[:e] = w_min - rng.uniform(0.0, 3.0 * dw, e)
+    w[e:2 * e] = w_max + rng.uniform(0.0, 3.0 * dw, e)
+    w[2 * e:3 * e] = w_min + rng.integers(0, nw + 1, e) * dw
+    perm = rng.permutation(m)
+    xs, ys = xs[perm], ys[perm]
+    uvw = np.stack([(xs - n / 2) / fov_l, (ys - nv / 2) / fov_m, w], axis=1)
+    if bad and m >= 8:
+        uvw[0, 0] = np.nan
+        uvw[1, 1] = np.inf
+        uvw[2, 2] = np.nan
+        uvw[3, 0] = 1e30
+    cdt = np.complex128 if precision == 1 else np.complex64
+    vis = _cn01(rng, m, cdt)
+    wt = rng.uniform(0.5, 1.5, m).astype(np.float32)
+    return Workload(n, nv, nw, fov_l, fov_m, w_min, w_max, support, 0.0,
+                    precision, np.ascontiguousarray(uvw), vis, wt,
+                    name=f"edge{seed}")

@@ -58,3 +58,28 @@ def test_committed_column_pass_counters_match_their_source():
     t = bench.pmc_traffic("fft_cols")
     if t is not None:
         assert 0 < t < bench.algorithmic_bytes("fft_cols", _W, 8, 10**7)
+
+
+def test_algorithmic_bytes_from_tile_statistics():
+    """With the binning's tile counts, each pass is charged only for what
+    the one-call path has to touch: busy tiles, marked strips, record reads
+    and split-tile partials."""
+    st = {"tile": 64, "busy": 100, "idle": 5, "split": 3, "extra_items": 7,
+          "strips": 10, "record_reads": 12345}
+    tile_b = 64 * 64 * 8
+    strip_b = 4096 * 64 * 8
+    assert bench.algorithmic_bytes("fft_cols", _W, 8, 10**7, st) == (
+        100 * tile_b + 10 * strip_b)
+    assert bench.algorithmic_bytes("row_screen_sum", _W, 8, 10**7, st) == (
+        10 * strip_b + 2 * 4096 * 4096 * 8)
+    assert bench.algorithmic_bytes("grid", _W, 8, 10**7, st) == (
+        100 * tile_b + 12345 * 32 + 2 * 10 * tile_b)
+    # binning is charged per visibility either way
+    assert bench.algorithmic_bytes("bin_count", _W, 8, 10, st) == 10 * 32
+    assert bench.algorithmic_bytes("bin_scatter", _W, 8, 10, st) == (
+        10 * (24 + 8 + 4 + 8 + 4 + 32))
+
+
+def test_gpu_count_other_than_one_is_refused(capsys):
+    assert bench.main(["--gpus", "2"]) == 2
+    assert "one GPU" in capsys.readouterr().out

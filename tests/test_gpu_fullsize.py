@@ -2,6 +2,8 @@
 compute one by one: grid cells summed visibility by visibility, and dirty-
 image pixels from the definition (no FFT), in the launch configuration the
 benchmark times (ws_grid_visibilities + ws_image_accumulate)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -107,3 +109,54 @@ def test_config3_full_size_sampled(config3_data, precision):
                       2e-6 * np.abs(ref_cells) +
                       1e-6 * np.abs(ref_cells).max())
         assert np.abs(got_pix - ref_pix).max() <= 1e-5 * rms
+
+
+def _golden_pixels():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "config2_pixels.txt")
+    px, val = [], []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            q, p, re, im = line.split()
+            px.append((int(q), int(p)))
+            val.append(complex(float(re), float(im)))
+    return px, np.array(val)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_config2_timed_path_pixels(precision):
+    """The call the benchmark times (ws_grid_image on the dense-core 1e7
+    visibility workload, default plan) against 64 pixels of the oracle's
+    per-pixel definition (written by tests/golden/make_config2_pixels.py):
+    corners, edges, the centre and random pixels.  FP32: the sampled
+    pixels' rel-L2 <= 1e-5 and every pixel within 1e-5 of the image rms;
+    FP64: within 1e-11 of the rms."""
+    px, ref = _golden_pixels()
+    assert len(px) == 64
+    wl = synth.config2(precision=0)
+    dev = torch.device("cuda", 0)
+    plan = ws.WStackPlan.from_workload(wl, precision=precision)
+    uvw = torch.from_numpy(wl.uvw).to(dev)
+    vis = torch.from_numpy(wl.vis).to(dev)
+    if precision == "fp64":
+        vis = vis.to(torch.complex128)
+    wt = torch.from_numpy(wl.weight).to(dev)
+    img = plan.new_image()
+    plan.reset()
+    plan.grid_image(uvw, vis, wt, image=img)
+    torch.cuda.synchronize()
+    qi = torch.tensor([q for q, _ in px], device=dev)
+    pi = torch.tensor([p for _, p in px], device=dev)
+    got = img[qi, pi].cpu().numpy().astype(np.complex128)
+    rms = float(img.abs().pow(2).mean().sqrt())
+    err = np.abs(got - ref)
+    if precision == "fp64":
+        assert err.max() <= 1e-11 * rms, err.max() / rms
+    else:
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5
+        assert err.max() <= 1e-5 * rms, err.max() / rms
+    del plan
+    torch.cuda.empty_cache()

@@ -137,8 +137,10 @@ def test_wcorrect_matches_oracle(precision, fov_deg):
             1j * rng.standard_normal((nw, nv, nu))).astype(cdt)
     plan = ws.WStackPlan(nu, nv, nw, p.fov_l, p.fov_m, p.w_min, p.w_max, 7,
                          precision=precision, max_vis=16, tile=16)
-    e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
-    plan.grid(e, torch.empty(0, dtype=plan.cdtype, device="cuda"))
+    # An empty plan transformed: zero planes in the transformed state, which
+    # the screen then reads (here with arbitrary data written in).
+    plan.reset()
+    plan.fft(+1)
     plan.planes.copy_(torch.from_numpy(data))
     img = plan.new_image()
     img += 1.0  # accumulation adds to what is there
@@ -396,6 +398,27 @@ def test_tile_stats_cover_the_tiles_the_oracle_writes(tile):
     nz = np.abs(planes).reshape(wl.nw, tv, tile, tu, tile).max(axis=(2, 4))
     assert st["busy"] >= int((nz > 0).sum()) > 0
     assert 0 <= st["split"] <= st["busy"]
+    # Exact counts: a visibility's record is read by its home tile (the
+    # tile of its nearest cell) and by each neighbour whose edge strip of
+    # width h it lies in (corner strips: three neighbours).
+    h = (wl.support - 1) // 2
+    _, _, i0, j0, k = o.coordinates(o.Params.of(wl), wl.uvw)
+    reads, tiles = 0, set()
+    for ii, jj, kk in zip(np.clip(i0, 0, wl.nu - 1), np.clip(j0, 0, wl.nv - 1),
+                          k):
+        tx, ty = ii // tile, jj // tile
+        lx, ly = ii - tx * tile, jj - ty * tile
+        dxs = [0] + ([-1] if lx < h and tx > 0 else []) + \
+            ([1] if lx >= tile - h and tx + 1 < tu else [])
+        dys = [0] + ([-1] if ly < h and ty > 0 else []) + \
+            ([1] if ly >= tile - h and ty + 1 < tv else [])
+        for a in dxs:
+            for b in dys:
+                tiles.add((int(kk), int(ty + b), int(tx + a)))
+                reads += 1
+    assert st["busy"] == len(tiles)
+    assert st["record_reads"] == reads
+    assert st["strips"] == len({(t[0], t[2]) for t in tiles})
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
