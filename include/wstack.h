@@ -181,6 +181,30 @@ ws_status ws_degrid(ws_plan* plan, const void* image, int32_t image_is_real,
                     int64_t m, const double* uvw, const float* weight,
                     void* vis_out);
 
+/* ---- allocation-free imaging ---------------------------------------------
+ * For callers that cannot allocate device memory at all: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same dirty image as ws_grid_init + ws_grid_image (same kernels, same
+ * arguments), with no plan and no caller buffers besides the inputs and the
+ * image: the plane stack and the workspace live in a static device array of
+ * WS_NOALLOC_SCRATCH_BYTES bytes inside the library (one per GPU, held until
+ * the process ends).  The call allocates nothing, host or device.
+ *   params, m, uvw, vis, weight, n_dropped_taps: as for ws_grid_image;
+ *   image: device [nv][nu] complex of the plan precision, ADDED to;
+ *   hip_stream: the stream to enqueue on (NULL = the null stream).
+ * A problem whose stack plus workspace (ws_workspace_bytes with max_vis =
+ * m, the stack rounded up to 256 bytes) exceeds WS_NOALLOC_SCRATCH_BYTES is
+ * refused with WS_WORKSPACE_TOO_SMALL before any device work.  Every call
+ * on one GPU shares that GPU's scratch: calls that overlap in time on one
+ * GPU (two streams, two threads) race and give wrong images; serialise
+ * them.  The scratch keeps the last call's contents; each call clears what
+ * it needs. */
+#define WS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ws_status ws_grid_image_noalloc(const ws_params* params, int64_t m,
+                                const double* uvw, const void* vis,
+                                const float* weight, void* image,
+                                int64_t* n_dropped_taps, void* hip_stream);
+
 /* Start a new image: the stack counts as empty again (cleared lazily). */
 ws_status ws_plan_reset(ws_plan* plan);
 

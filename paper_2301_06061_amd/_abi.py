@@ -21,6 +21,7 @@ WS_HIP_ERROR = -4
 WS_BAD_STATE = -5
 WS_FP32 = 0
 WS_FP64 = 1
+WS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class WStackError(RuntimeError):
@@ -54,6 +55,8 @@ _SIGS = {
     "ws_grid_image": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P, _P]),
     "ws_tile_stats": (C.c_int32, [_P, _P]),
     "ws_degrid": (C.c_int32, [_P, _P, C.c_int32, C.c_int64, _P, _P, _P]),
+    "ws_grid_image_noalloc": (C.c_int32, [C.POINTER(Params), C.c_int64, _P,
+                                          _P, _P, _P, _P, _P]),
     "ws_plan_reset": (C.c_int32, [_P]),
     "ws_set_stream": (C.c_int32, [_P, _P]),
     "ws_sync": (C.c_int32, [_P]),

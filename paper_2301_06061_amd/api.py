@@ -42,6 +42,38 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def grid_image_noalloc(params: _abi.Params, uvw, vis, weight=None,
+                       image=None, dropped=None):
+    """ws_grid_image_noalloc: grid and image with the library's static
+    scratch (no plan, no stack or workspace tensors).  Adds into ``image``
+    (a new zero image if None, the only allocation here, made by torch
+    before the call) on the current stream and returns it."""
+    fp64 = params.precision == _abi.WS_FP64
+    cdt = torch.complex128 if fp64 else torch.complex64
+    m = int(uvw.shape[0])
+    if image is None:
+        image = torch.zeros((params.nv, params.nu), dtype=cdt,
+                            device=uvw.device)
+    for t, dt, shape, name in ((uvw, torch.float64, (m, 3), "uvw"),
+                               (vis, cdt, (m,), "vis"),
+                               (weight, torch.float32, (m,), "weight"),
+                               (image, cdt, (params.nv, params.nu), "image"),
+                               (dropped, torch.int64, (1,), "dropped")):
+        if t is None:
+            continue
+        if t.dtype != dt or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"{name}: need a contiguous {dt} of shape "
+                             f"{shape}")
+        if t.device != image.device:
+            raise ValueError(f"{name} is not on {image.device}")
+    with torch.cuda.device(image.device):
+        stream = torch.cuda.current_stream(image.device).cuda_stream
+        _abi.call("ws_grid_image_noalloc", C.byref(params), m, _ptr(uvw),
+                  _ptr(vis), _ptr(weight), _ptr(image), _ptr(dropped),
+                  C.c_void_p(stream))
+    return image
+
+
 class WStackPlan:
     """One imaging geometry bound to a plane stack and a workspace.
 

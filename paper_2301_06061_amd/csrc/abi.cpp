@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -705,6 +706,37 @@ ws_status init_plan(ws_plan* pl, const ws_params* params, int64_t max_vis,
   });
 }
 
+// ---- allocation-free imaging ---------------------------------------------
+// The plane stack and the workspace of ws_grid_image_noalloc live in this
+// fixed device array (one copy per GPU the library runs on, held until the
+// process ends).  Host code never passes `scratch` itself to a kernel: the
+// name is a host-side stand-in, so the device address of each GPU's copy is
+// looked up once per device with hipGetSymbolAddress and used instead.
+constexpr size_t kNoAllocBytes = WS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (dev must be current).
+ws_status scratch_of_device(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(WS_UNSUPPORTED_SIZE, "device %d: at most %d devices", dev,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(WS_HIP_ERROR, "hipGetSymbolAddress(scratch) on device %d: "
+                  "%s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return WS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -864,6 +896,49 @@ ws_status ws_degrid(ws_plan* plan, const void* image, int32_t image_is_real,
                      : degrid_impl<float>(plan, image, image_is_real != 0, m,
                                           uvw, weight, vis_out);
   plan->state = kEmpty;
+  return st;
+}
+
+ws_status ws_grid_image_noalloc(const ws_params* params, int64_t m,
+                                const double* uvw, const void* vis,
+                                const float* weight, void* image,
+                                int64_t* n_dropped_taps, void* hip_stream) {
+  // Sizes first (host only): a problem that does not fit the scratch is
+  // refused before any device work.
+  Layout L;
+  WS_TRY(make_layout(params, m > 0 ? m : 1, &L));
+  const size_t planes_at = 0;
+  const size_t work_at = align_up(L.planes_bytes, 256);
+  const size_t need = work_at + L.total;
+  if (need > kNoAllocBytes)
+    return fail(WS_WORKSPACE_TOO_SMALL,
+                "this problem needs %zu bytes of stack and workspace; the "
+                "allocation-free call has a %zu-byte static scratch (use "
+                "ws_grid_init with caller buffers instead)",
+                need, kNoAllocBytes);
+  if (image == nullptr) return fail(WS_INVALID_ARG, "image is NULL");
+  if (m > 0 && vis == nullptr) return fail(WS_INVALID_ARG, "vis is NULL");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess)
+    return fail(WS_HIP_ERROR, "hipGetDevice failed (no GPU?)");
+  unsigned char* base = nullptr;
+  WS_TRY(scratch_of_device(dev, &base));
+  ws_plan pl;  // host object on this stack frame: nothing is allocated
+  WS_TRY(init_plan(&pl, params, m > 0 ? m : 1, L, dev, base + planes_at,
+                   base + work_at, hip_stream));
+  WS_TRY(check_vis_args(&pl, m, uvw, weight));
+  if (!aligned(vis, L.elem) || !aligned(image, L.elem) ||
+      !aligned(n_dropped_taps, 8))
+    return fail(WS_INVALID_ARG, "misaligned vis, image or n_dropped_taps");
+  const bool lazy = lazy_ok(&pl);
+  const bool f64 = params->precision == WS_FP64;
+  ws_status st = f64 ? grid_impl<double>(&pl, m, uvw, vis, weight,
+                                         n_dropped_taps, lazy)
+                     : grid_impl<float>(&pl, m, uvw, vis, weight,
+                                        n_dropped_taps, lazy);
+  if (st == WS_OK)
+    st = f64 ? image_impl<double>(&pl, image, lazy)
+             : image_impl<float>(&pl, image, lazy);
   return st;
 }
 

@@ -112,3 +112,19 @@ def test_null_and_status_strings():
     assert st == _abi.WS_INVALID_ARG and out.value is None
     assert lib.ws_plan_reset(None) == _abi.WS_INVALID_ARG
     lib.ws_plan_destroy(None)
+
+
+def test_noalloc_refuses_before_touching_a_device():
+    """A problem larger than the static scratch is refused by the size
+    check alone (no GPU here)."""
+    p = _p(nu=4096, nv=4096, nw=32, precision="fp32")
+    st = _abi.lib().ws_grid_image_noalloc(C.byref(p), 10, None, None, None,
+                                          None, None, None)
+    assert st == _abi.WS_WORKSPACE_TOO_SMALL
+    msg = _abi.lib().ws_last_error().decode()
+    assert "static scratch" in msg and str(64 << 20) in msg
+    # and a bad parameter set is still reported as such
+    bad = _p(nu=100)
+    assert _abi.lib().ws_grid_image_noalloc(C.byref(bad), 10, None, None,
+                                            None, None, None, None) == \
+        _abi.WS_UNSUPPORTED_SIZE
