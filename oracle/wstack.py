@@ -28,6 +28,16 @@ happens to taps that fall off the grid).  The readings taken here are:
   - 1 evaluated as -r^2 / (1 + sqrt(1 - r^2)) (no cancellation near r = 0);
 * the dirty image is the plain sum over planes (the right-hand side of
   Eq. (2), no 1/n or (w_max - w_min) factor).
+
+Production kernels (Sec. 2 names the Gaussian as the paper's choice and
+better kernels as the alternative; Sec. 5 lists them as future work): the
+"exponential of semicircle" kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1)),
+z = 2 d / K, over the same K x K support, normalised so that its continuous
+2-D integral is one.  With ``correct`` the image is divided by the gridding
+kernel's 2-D Fourier transform c psi(f_p) psi(f_q) (the grid correction),
+where psi is the transform of the 1-D kernel truncated to its support and
+f_p = (p - N/2)/N; the degridder multiplies its input image by the same
+factor (the correction is real and diagonal, so it is its own adjoint).
 """
 from __future__ import annotations
 
@@ -48,12 +58,17 @@ class Params:
     w_max: float
     support: int
     sigma: float = 0.0
+    kernel: str = "gauss"     # "gauss" or "es" (exponential of semicircle)
+    beta: float = 0.0         # ES shape; <= 0 selects 2.3 K
+    correct: bool = False     # divide the image by the kernel's transform
 
     @classmethod
     def of(cls, wl) -> "Params":
         """Take the geometry fields from any object that carries them."""
         return cls(wl.nu, wl.nv, wl.nw, wl.fov_l, wl.fov_m, wl.w_min,
-                   wl.w_max, wl.support, getattr(wl, "sigma", 0.0))
+                   wl.w_max, wl.support, getattr(wl, "sigma", 0.0),
+                   getattr(wl, "kernel", "gauss"), getattr(wl, "beta", 0.0),
+                   bool(getattr(wl, "correct", False)))
 
 
 # ---------------------------------------------------------------------------
@@ -66,7 +81,13 @@ def kernel_sigma(p: Params) -> float:
 
 
 def kernel_norm(p: Params) -> float:
-    """c = 1/(2 pi sigma^2): the continuous 2-D Gaussian integrates to one."""
+    """c: the continuous 2-D kernel c phi(x) phi(y) integrates to one.
+
+    Gaussian: c = 1/(2 pi sigma^2) (the untruncated integral).  ES kernel:
+    c = 1 / (integral of phi(2 d / K) over |d| <= K/2)^2, by quadrature.
+    """
+    if p.kernel == "es":
+        return 1.0 / float(kernel_ft(p, 0.0)) ** 2
     s = kernel_sigma(p)
     return 1.0 / (2.0 * math.pi * s * s)
 
@@ -75,6 +96,62 @@ def gauss(d, sigma):
     """One-dimensional Gaussian factor g(d) = exp(-d^2 / (2 sigma^2))."""
     d = np.asarray(d, dtype=np.float64)
     return np.exp(-(d * d) / (2.0 * sigma * sigma))
+
+
+def es_beta(p: Params) -> float:
+    """Shape of the exponential-of-semicircle kernel; 2.3 K unless given."""
+    return float(p.beta) if p.beta > 0 else 2.3 * p.support
+
+
+def es(d, support, beta):
+    """phi(2 d / K) = exp(beta (sqrt(1 - z^2) - 1)), zero for |z| > 1."""
+    z = 2.0 * np.asarray(d, dtype=np.float64) / support
+    inside = np.abs(z) <= 1.0
+    r = np.sqrt(np.where(inside, 1.0 - z * z, 0.0))
+    return np.where(inside, np.exp(beta * (r - 1.0)), 0.0)
+
+
+def kernel_1d(p: Params, d):
+    """The 1-D factor of the separable gridding kernel at offset d (cells)."""
+    if p.kernel == "es":
+        return es(d, p.support, es_beta(p))
+    if p.kernel != "gauss":
+        raise ValueError(f"unknown kernel {p.kernel!r}")
+    return gauss(d, kernel_sigma(p))
+
+
+_QUAD_NODES = 96
+
+
+def kernel_ft(p: Params, f):
+    """psi(f) = integral over |d| <= K/2 of phi(d) cos(2 pi f d) dd: the
+    Fourier transform of the truncated 1-D kernel (f in cycles per cell).
+
+    Gauss-Legendre quadrature: on d directly for the Gaussian; for the ES
+    kernel after z = 2 d / K = sin(t), which makes the integrand smooth
+    (phi has a square-root edge at |z| = 1).
+    """
+    f = np.asarray(f, dtype=np.float64)
+    x, w = np.polynomial.legendre.leggauss(_QUAD_NODES)
+    half = p.support / 2.0
+    if p.kernel == "es":
+        t = x * (math.pi / 2)
+        g = np.exp(es_beta(p) * (np.cos(t) - 1.0)) * np.cos(t)
+        d = half * np.sin(t)
+        wt = w * (math.pi / 2) * half * g
+    else:
+        d = x * half
+        wt = w * half * gauss(d, kernel_sigma(p))
+    return np.cos(2.0 * math.pi * f[..., None] * d) @ wt
+
+
+def grid_correction(p: Params):
+    """1 / (c psi(f_p) psi(f_q)) at pixel [q][p]: the factor that divides
+    the image by the gridding kernel's 2-D Fourier transform."""
+    fp = (np.arange(p.nu) - p.nu / 2) / p.nu
+    fq = (np.arange(p.nv) - p.nv / 2) / p.nv
+    c = kernel_norm(p)
+    return 1.0 / (c * kernel_ft(p, fq)[:, None] * kernel_ft(p, fp)[None, :])
 
 
 # ---------------------------------------------------------------------------
@@ -141,11 +218,12 @@ def _weights(weight, m):
 # ---------------------------------------------------------------------------
 
 def grid(p: Params, uvw, vis, weight=None):
-    """Grid visibilities onto P[k][j][i] (complex128) with the Gaussian kernel.
+    """Grid visibilities onto P[k][j][i] (complex128) with the kernel.
 
     For every tap (a, b) in [-h, h]^2 around the nearest cell, the cell
-    (i0 + a, j0 + b) of plane k receives w V c g(i - x) g(j - y) when it lies
-    on the grid; taps off the grid are dropped and counted.
+    (i0 + a, j0 + b) of plane k receives w V c phi(i - x) phi(j - y) when it
+    lies on the grid (phi the Gaussian g, or the ES kernel); taps off the
+    grid are dropped and counted.
     Returns (planes, n_dropped_taps).
     """
     vis = np.asarray(vis).astype(np.complex128)
@@ -153,7 +231,6 @@ def grid(p: Params, uvw, vis, weight=None):
     x, y, i0, j0, k = coordinates(p, uvw)
     wv = _weights(weight, m) * vis
     h = (p.support - 1) // 2
-    s = kernel_sigma(p)
     c = kernel_norm(p)
     ncell = p.nw * p.nv * p.nu
     re = np.zeros(ncell)
@@ -161,12 +238,12 @@ def grid(p: Params, uvw, vis, weight=None):
     dropped = 0
     for b in range(-h, h + 1):
         j = j0 + b
-        gy = gauss(j - y, s)
+        gy = kernel_1d(p, j - y)
         for a in range(-h, h + 1):
             i = i0 + a
             on = (i >= 0) & (i < p.nu) & (j >= 0) & (j < p.nv)
             dropped += int(m - np.count_nonzero(on))
-            val = wv[on] * (c * gauss(i[on] - x[on], s) * gy[on])
+            val = wv[on] * (c * kernel_1d(p, i[on] - x[on]) * gy[on])
             flat = (k[on] * p.nv + j[on]) * p.nu + i[on]
             re += np.bincount(flat, weights=val.real, minlength=ncell)
             im += np.bincount(flat, weights=val.imag, minlength=ncell)
@@ -219,11 +296,14 @@ def screen_nm1(p: Params):
 
 
 def wcorrect(p: Params, fplanes):
-    """I[q][p] = sum_k F_k[q][p] exp(+2 pi i w_k (n_pq - 1))."""
+    """I[q][p] = sum_k F_k[q][p] exp(+2 pi i w_k (n_pq - 1)), times the
+    grid correction when ``p.correct``."""
     nm1 = screen_nm1(p)
     img = np.zeros((p.nv, p.nu), dtype=np.complex128)
     for k, wk in enumerate(plane_centres(p)):
         img += fplanes[k] * np.exp(2j * math.pi * wk * nm1)
+    if p.correct:
+        img = img * grid_correction(p)
     return img
 
 
@@ -240,10 +320,13 @@ def image(p: Params, uvw, vis, weight=None):
 def degrid(p: Params, img, uvw, weight=None):
     """Exact adjoint of ``image``: image -> visibilities.
 
-    Q_k = FFT^-(conj(screen_k) X); V_m = w_m sum_taps c g g Q_{k(m)}[j][i],
-    taps off the grid contributing nothing.
+    Q_k = FFT^-(conj(screen_k) X); V_m = w_m sum_taps c phi phi Q_{k(m)}[j][i],
+    taps off the grid contributing nothing (X first multiplied by the grid
+    correction when ``p.correct``).
     """
     img = np.asarray(img).astype(np.complex128)
+    if p.correct:
+        img = img * grid_correction(p)
     nm1 = screen_nm1(p)
     wks = plane_centres(p)
     q = np.stack([img * np.exp(-2j * math.pi * wk * nm1) for wk in wks])
@@ -251,18 +334,17 @@ def degrid(p: Params, img, uvw, weight=None):
     m = np.asarray(uvw).shape[0]
     x, y, i0, j0, k = coordinates(p, uvw)
     h = (p.support - 1) // 2
-    s = kernel_sigma(p)
     c = kernel_norm(p)
     out = np.zeros(m, dtype=np.complex128)
     qflat = q.reshape(-1)
     for b in range(-h, h + 1):
         j = j0 + b
-        gy = gauss(j - y, s)
+        gy = kernel_1d(p, j - y)
         for a in range(-h, h + 1):
             i = i0 + a
             on = (i >= 0) & (i < p.nu) & (j >= 0) & (j < p.nv)
             flat = (k[on] * p.nv + j[on]) * p.nu + i[on]
-            out[on] += c * gauss(i[on] - x[on], s) * gy[on] * qflat[flat]
+            out[on] += c * kernel_1d(p, i[on] - x[on]) * gy[on] * qflat[flat]
     return _weights(weight, m) * out
 
 
@@ -276,13 +358,12 @@ def grid_cells_direct(p: Params, uvw, vis, weight, cells):
     x, y, i0, j0, kk = coordinates(p, uvw)
     wv = _weights(weight, vis.shape[0]) * vis
     h = (p.support - 1) // 2
-    s = kernel_sigma(p)
     c = kernel_norm(p)
     out = []
     for (k, j, i) in cells:
         sel = (kk == k) & (np.abs(i0 - i) <= h) & (np.abs(j0 - j) <= h)
-        out.append(np.sum(wv[sel] * c * gauss(i - x[sel], s)
-                          * gauss(j - y[sel], s)))
+        out.append(np.sum(wv[sel] * c * kernel_1d(p, i - x[sel])
+                          * kernel_1d(p, j - y[sel])))
     return np.array(out, dtype=np.complex128)
 
 
@@ -298,7 +379,6 @@ def image_pixels_direct(p: Params, uvw, vis, weight, pixels, block=1 << 20):
     m = vis.shape[0]
     wts = _weights(weight, m)
     h = (p.support - 1) // 2
-    s = kernel_sigma(p)
     c = kernel_norm(p)
     wks = plane_centres(p)
     l_all, m_all = sky_coords(p)
@@ -315,15 +395,18 @@ def image_pixels_direct(p: Params, uvw, vis, weight, pixels, block=1 << 20):
             for a in range(-h, h + 1):
                 i = i0 + a
                 onu = (i >= 0) & (i < p.nu)
-                su += np.where(onu, gauss(i - x, s), 0.0) * np.exp(
+                su += np.where(onu, kernel_1d(p, i - x), 0.0) * np.exp(
                     2j * math.pi * (i - p.nu / 2) * fu)
                 j = j0 + a
                 onv = (j >= 0) & (j < p.nv)
-                sv += np.where(onv, gauss(j - y, s), 0.0) * np.exp(
+                sv += np.where(onv, kernel_1d(p, j - y), 0.0) * np.exp(
                     2j * math.pi * (j - p.nv / 2) * fv)
             nm1 = n_minus_one(l_all[pp], m_all[qq])
             ph = np.exp(2j * math.pi * wks[k] * nm1)
             res[t] += np.sum(wv * c * su * sv * ph)
+    if p.correct:
+        corr = grid_correction(p)
+        res *= np.array([corr[qq, pp] for qq, pp in pixels])
     return res
 
 

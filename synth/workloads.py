@@ -43,6 +43,9 @@ class Workload:
     weight: Optional[np.ndarray] = None
     name: str = ""
     extra: dict = field(default_factory=dict)
+    kernel: str = "gauss"   # gridding kernel: "gauss" or "es"
+    beta: float = 0.0       # ES kernel shape (<= 0: the default)
+    correct: bool = False   # divide the image by the kernel's transform
 
     @property
     def m(self) -> int:
@@ -52,7 +55,8 @@ class Workload:
         return dict(nu=self.nu, nv=self.nv, nw=self.nw, fov_l=self.fov_l,
                     fov_m=self.fov_m, w_min=self.w_min, w_max=self.w_max,
                     support=self.support, sigma=self.sigma,
-                    precision=self.precision)
+                    precision=self.precision, kernel=self.kernel,
+                    beta=self.beta, correct=self.correct)
 
     def as_precision(self, precision: int) -> "Workload":
         """Same draw in the other precision path (values upcast/downcast)."""

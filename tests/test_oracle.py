@@ -374,3 +374,162 @@ def test_degrid_explicit_matrix():
         e[t] = 1
         a_deg[:, t] = o.degrid(p, e.reshape(16, 16), wl.uvw, wl.weight)
     assert np.allclose(a_deg, a_img.conj().T, rtol=1e-12, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Production kernel (exponential of semicircle) and grid correction
+# (Sec. 2: the Gaussian is the paper's choice, better kernels the production
+# alternative; Sec. 5: future work)
+# ---------------------------------------------------------------------------
+
+def _es_params(n=32, nw=1, k=7, beta=0.0, correct=True, **kw):
+    p = _params(n=n, nw=nw, k=k, **kw)
+    p.kernel, p.beta, p.correct = "es", beta, correct
+    return p
+
+
+def test_es_kernel_shape():
+    """phi(0) = 1, phi at the support edge = exp(-beta), zero outside,
+    even, decreasing in |d|; default beta = 2.3 K."""
+    p = _es_params(k=9)
+    assert o.es_beta(p) == pytest.approx(2.3 * 9, rel=1e-15)
+    d = np.array([0.0, 4.5, -4.5, 4.5000001, 10.0])
+    v = o.kernel_1d(p, d)
+    assert v[0] == 1.0
+    assert v[1] == pytest.approx(math.exp(-2.3 * 9), rel=1e-12)
+    assert v[2] == v[1] and v[3] == 0.0 and v[4] == 0.0
+    dd = np.linspace(0, 4.5, 200)
+    assert np.all(np.diff(o.kernel_1d(p, dd)) < 0)
+    assert np.allclose(o.kernel_1d(p, -dd), o.kernel_1d(p, dd), rtol=0,
+                       atol=0)
+
+
+@pytest.mark.parametrize("kernel,k,sigma", [("es", 7, 0.0), ("es", 9, 0.0),
+                                            ("es", 15, 0.0),
+                                            ("gauss", 7, 0.0),
+                                            ("gauss", 9, 1.4)])
+def test_kernel_transform_matches_adaptive_quadrature(kernel, k, sigma):
+    """psi(f) (Gauss-Legendre after a change of variable) against scipy's
+    adaptive quadrature of the plain integrand over |d| <= K/2."""
+    from scipy import integrate
+    p = _params(k=k, sigma=sigma)
+    p.kernel = kernel
+    for f in (0.0, 0.13, 0.25, 0.4, 0.5, 0.75, 1.0):
+        ref = integrate.quad(lambda d: float(o.kernel_1d(p, d)) *
+                             math.cos(2 * math.pi * f * d), -k / 2, k / 2,
+                             epsabs=1e-15, epsrel=1e-12, limit=400)[0]
+        assert float(o.kernel_ft(p, f)) == pytest.approx(ref, rel=1e-11,
+                                                         abs=1e-13)
+
+
+def test_gaussian_transform_closed_form():
+    """Truncated Gaussian: psi(f) = sigma sqrt(2 pi) exp(-2 pi^2 sigma^2 f^2)
+    Re erf((K/2 + 2 pi i f sigma^2) / (sigma sqrt 2))."""
+    from scipy.special import erf
+    p = _params(k=7, sigma=1.1)
+    s = 1.1
+    for f in (0.0, 0.1, 0.3, 0.5):
+        z = (3.5 + 2j * math.pi * f * s * s) / (s * math.sqrt(2))
+        ref = s * math.sqrt(2 * math.pi) * math.exp(
+            -2 * math.pi ** 2 * s * s * f * f) * erf(z).real
+        assert float(o.kernel_ft(p, f)) == pytest.approx(ref, rel=1e-13)
+
+
+def test_es_norm_unit_integral():
+    """c makes the 2-D kernel integrate to one: c (integral of phi)^2 = 1,
+    the integral by scipy's adaptive quadrature."""
+    from scipy import integrate
+    for k in (5, 7, 9):
+        p = _es_params(k=k)
+        one = integrate.quad(lambda d: float(o.kernel_1d(p, d)), -k / 2,
+                             k / 2, epsabs=0, epsrel=1e-13, limit=400)[0]
+        assert o.kernel_norm(p) * one * one == pytest.approx(1.0, rel=1e-12)
+
+
+def test_es_tap_sum_is_poisson_sum():
+    """A unit visibility's on-grid taps sum to c S(dx) S(dy) with
+    S(d) = sum_n psi(n) exp(2 pi i n d) (Poisson summation of the compactly
+    supported kernel), so the total is 1 up to the kernel's aliasing.
+    psi(n) falls to ~1e-8 of psi(0) by n = 3 (the exp(-beta) edge), so the
+    series is cut after n = 2 and compared to 3e-7."""
+    p = _es_params(n=64, k=7, correct=False)
+    for x, y in [(32.0, 32.0), (30.3, 33.71), (29.49, 31.02)]:
+        planes, _ = o.grid(p, _uvw_at_cell(p, x, y), np.array([1.0 + 0j]))
+        ns = np.arange(1, 3)
+        sx = float(o.kernel_ft(p, 0.0)) + 2 * np.sum(
+            o.kernel_ft(p, ns) * np.cos(2 * math.pi * ns * (x - round(x))))
+        sy = float(o.kernel_ft(p, 0.0)) + 2 * np.sum(
+            o.kernel_ft(p, ns) * np.cos(2 * math.pi * ns * (y - round(y))))
+        assert planes.sum().real == pytest.approx(
+            o.kernel_norm(p) * sx * sy, rel=3e-7)
+        assert abs(planes.sum() - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("kernel,k,tol", [("es", 7, 3e-6), ("es", 9, 1e-7),
+                                          ("gauss", 7, 2e-3)])
+def test_corrected_image_matches_ideal_dft(kernel, k, tol):
+    """With the grid correction, the w-stacked image reproduces the
+    measurement-equation image of Eqs. (1)-(2) itself (no taper to divide
+    out) on the central half of the field, to the kernel's aliasing: about
+    1e-6 for the ES kernel of support 7, 5e-8 for 9, 1e-3 for the Gaussian
+    of support 7 (whose transform the truncation at +-3.5 sigma widens).
+    w on plane centres, so gridding is the only approximation."""
+    n, nw = 32, 5
+    rng = np.random.default_rng(31)
+    p = _params(n=n, nw=nw, k=k, fov_deg=30.0, w_min=-500.0, w_max=500.0)
+    p.kernel, p.correct = kernel, True
+    m = 60
+    xs = rng.uniform(9, 23, m)
+    ys = rng.uniform(9, 23, m)
+    uvw = np.concatenate([_uvw_at_cell(p, x, y) for x, y in zip(xs, ys)])
+    uvw[:, 2] = o.plane_centres(p)[rng.integers(0, nw, m)]
+    vis = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    wt = rng.uniform(0.5, 1.5, m)
+    img = o.image(p, uvw, vis, wt)
+    ref = o.dft_image(p, uvw, vis, wt).reshape(n, n)
+    sl = slice(n // 4, 3 * n // 4 + 1)
+    err = np.abs(img[sl, sl] - ref[sl, sl]).max() / np.abs(ref).max()
+    assert err <= tol
+    # without the correction the image is the tapered one: far off
+    p.correct = False
+    raw = o.image(p, uvw, vis, wt)
+    assert np.abs(raw[sl, sl] - ref[sl, sl]).max() / np.abs(ref).max() > 0.1
+
+
+def test_correction_is_separable_and_axis_true():
+    """On a 32 x 16 grid the factor along l (32 columns) and along m (16
+    rows) differ; each is 1/(sqrt(c) psi(f)) of its own axis."""
+    p = _es_params(n=32, nv=16)
+    corr = o.grid_correction(p)
+    assert corr.shape == (16, 32)
+    c = o.kernel_norm(p)
+    fl = (np.arange(32) - 16) / 32
+    fm = (np.arange(16) - 8) / 16
+    row = 1 / (math.sqrt(c) * o.kernel_ft(p, fl))
+    col = 1 / (math.sqrt(c) * o.kernel_ft(p, fm))
+    assert np.allclose(corr, col[:, None] * row[None, :], rtol=1e-13)
+    assert corr[8, 16] == pytest.approx(1.0, rel=1e-13)   # centre: c psi0^2
+
+
+def test_es_corrected_degrid_is_adjoint():
+    wl = synth.random_case(29, n=32, nw=4, support=7, m=400)
+    wl.kernel, wl.correct = "es", True
+    p = o.Params.of(wl)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((32, 32)) + 1j * rng.standard_normal((32, 32))
+    ax = o.degrid(p, x, wl.uvw, wl.weight)
+    ahv = o.image(p, wl.uvw, wl.vis, wl.weight)
+    assert abs(np.vdot(wl.vis, ax) - np.vdot(ahv, x)) <= \
+        1e-12 * np.linalg.norm(ax) * np.linalg.norm(x)
+
+
+def test_es_image_matches_direct_definition():
+    """Grid + FFT + screen + correction = the per-pixel definition."""
+    wl = synth.random_case(37, n=16, nw=3, support=7, m=150, law="core")
+    wl.kernel, wl.correct = "es", True
+    p = o.Params.of(wl)
+    img = o.image(p, wl.uvw, wl.vis, wl.weight)
+    pix = [(q, pp) for q in range(16) for pp in range(16)]
+    direct = o.image_pixels_direct(p, wl.uvw, wl.vis, wl.weight, pix)
+    assert np.allclose(img.reshape(-1), direct, rtol=1e-11,
+                       atol=1e-11 * np.abs(direct).max())
