@@ -460,3 +460,53 @@ def grid_point_additions(p: Params, uvw) -> int:
 def mesh_bytes(nu: int, nv: int, nw: int, complex_bytes: int = 16) -> int:
     """Bytes of one N_u x N_v x N_w complex mesh (real + imaginary parts)."""
     return nu * nv * nw * complex_bytes
+
+
+# ---------------------------------------------------------------------------
+# Baseline-major data (Sec. 2: the data structures; Sec. 3.4.2: one GPU
+# thread per measurement convolves all of its frequencies and polarisations)
+# ---------------------------------------------------------------------------
+
+SPEED_OF_LIGHT = 299_792_458.0  # m/s
+
+
+def stokes_coefficients(stokes: str, feeds: str = "linear"):
+    """Coefficients a_p over the four correlations that give one Stokes
+    parameter as sum_p a_p V_p.
+
+    Reading: linear feeds correlate as XX = I + Q, XY = U + iV, YX = U - iV,
+    YY = I - Q; circular feeds as RR = I + V, RL = Q + iU, LR = Q - iU,
+    LL = I - V.  Solving for the Stokes parameters gives the rows below.
+    """
+    h = 0.5
+    lin = {"I": [h, 0, 0, h], "Q": [h, 0, 0, -h], "U": [0, h, h, 0],
+           "V": [0, -0.5j, 0.5j, 0]}
+    circ = {"I": [h, 0, 0, h], "V": [h, 0, 0, -h], "Q": [0, h, h, 0],
+            "U": [0, -0.5j, 0.5j, 0]}
+    table = lin if feeds == "linear" else circ
+    return np.array(table[stokes], dtype=np.complex128)
+
+
+def expand_rows(uvw_m, freq_hz, vis, weight, pol_coeff):
+    """Flatten baseline-major data to one visibility per (row, channel).
+
+    uvw_m [R, 3] in metres per (baseline, time) row; freq_hz [C]; vis
+    [R, C, P] complex; weight [R, P] (per measurement and polarisation) or
+    None (unit); pol_coeff [P] complex.  Returns (uvw [R*C, 3] in
+    wavelengths, vis [R*C], None): u_lambda = u_m (f / c) and the gridded
+    value sum_p a_p w_p V_p, each with unit weight.  Row r, channel c is
+    entry r*C + c.
+    """
+    uvw_m = np.asarray(uvw_m, dtype=np.float64)
+    scale = np.asarray(freq_hz, dtype=np.float64) / SPEED_OF_LIGHT
+    nr, nc = uvw_m.shape[0], scale.shape[0]
+    uvw = (uvw_m[:, None, :] * scale[None, :, None]).reshape(nr * nc, 3)
+    vis = np.asarray(vis).astype(np.complex128)
+    coeff = np.asarray(pol_coeff, dtype=np.complex128)
+    npol = coeff.shape[0]
+    w = (np.ones((nr, npol)) if weight is None
+         else np.asarray(weight, dtype=np.float64))
+    comb = np.zeros((nr, nc), dtype=np.complex128)
+    for p in range(npol):
+        comb += (coeff[p] * w[:, p])[:, None] * vis[:, :, p]
+    return uvw, comb.reshape(nr * nc), None

@@ -533,3 +533,91 @@ def test_es_image_matches_direct_definition():
     direct = o.image_pixels_direct(p, wl.uvw, wl.vis, wl.weight, pix)
     assert np.allclose(img.reshape(-1), direct, rtol=1e-11,
                        atol=1e-11 * np.abs(direct).max())
+
+
+# ---------------------------------------------------------------------------
+# Baseline-major data: uvw per (baseline, time) in metres, visibilities per
+# channel and polarisation, weights per measurement and polarisation (Sec. 2)
+# ---------------------------------------------------------------------------
+
+def _point_source_rows(n, feeds, stokes_vals, nr=40, freqs=(100e6, 130e6,
+                                                            170e6, 200e6)):
+    """Correlations of one point source at a pixel centre from Eq. (1)
+    (apparent amplitudes, coplanar baselines w = 0), for the given feeds."""
+    rng = np.random.default_rng(5)
+    p = _es_params(n=n, k=7, fov_deg=3.0)
+    f = np.array(freqs)
+    # baselines in metres, within the grid at the highest frequency
+    lam_max = o.SPEED_OF_LIGHT / f.max()
+    half = (n / 2 - 5) / p.fov_l * lam_max
+    uvw_m = np.stack([rng.uniform(-half, half, nr), rng.uniform(-half, half, nr),
+                      np.zeros(nr)], axis=1)
+    p0, q0 = n // 2 + 5, n // 2 - 3
+    l0 = (p0 - n / 2) * p.fov_l / n
+    m0 = (q0 - n / 2) * p.fov_m / n
+    lam = uvw_m[:, None, :] * (f / o.SPEED_OF_LIGHT)[None, :, None]
+    e = np.exp(-2j * math.pi * (lam[..., 0] * l0 + lam[..., 1] * m0))
+    I, Q, U, V = stokes_vals
+    if feeds == "linear":
+        corr = [I + Q, U + 1j * V, U - 1j * V, I - Q]
+    else:
+        corr = [I + V, Q + 1j * U, Q - 1j * U, I - V]
+    vis = np.stack([c * e for c in corr], axis=-1)
+    w_row = rng.uniform(0.5, 1.5, nr)
+    weight = np.repeat(w_row[:, None], 4, axis=1)
+    return p, uvw_m, f, vis, weight, (q0, p0), w_row.sum() * len(f)
+
+
+@pytest.mark.parametrize("feeds", ["linear", "circular"])
+def test_rows_point_source_gives_each_stokes_parameter(feeds):
+    """Expanded rows image a point source to S x (sum of weights) at its
+    pixel, for S in (I, Q, U, V): the ideal image of Eqs. (1)-(2) to 1e-12
+    (the phases cancel exactly only if u_lambda = u_m f/c), the gridded,
+    corrected image to the ES kernel's aliasing."""
+    vals = dict(zip("IQUV", (2.0, 0.5, -0.3, 0.2)))
+    p, uvw_m, f, vis, weight, (q0, p0), wsum = _point_source_rows(
+        48, feeds, tuple(vals.values()))
+    for s, v in vals.items():
+        a = o.stokes_coefficients(s, feeds)
+        uvw, comb, _ = o.expand_rows(uvw_m, f, vis, weight, a)
+        assert uvw.shape == (uvw_m.shape[0] * len(f), 3)
+        ideal = o.dft_image(p, uvw, comb, None, pixels=[(q0, p0)])[0]
+        assert ideal == pytest.approx(v * wsum, rel=1e-12, abs=1e-12 * wsum)
+        img = o.image(p, uvw, comb, None)
+        assert img[q0, p0] == pytest.approx(v * wsum, rel=5e-6,
+                                            abs=5e-6 * wsum)
+
+
+def test_rows_reduce_to_flat_visibilities():
+    """One channel at f = c (u_lambda = u_m) and one polarisation with
+    coefficient 1: the flat visibilities weighted by their weights."""
+    wl = synth.random_case(3, n=32, nw=3, m=200)
+    uvw, comb, wt = o.expand_rows(wl.uvw, [o.SPEED_OF_LIGHT],
+                                  wl.vis[:, None, None],
+                                  wl.weight[:, None], [1.0])
+    assert wt is None
+    assert np.array_equal(uvw, wl.uvw)
+    assert np.array_equal(comb, wl.vis.astype(np.complex128) * wl.weight)
+    p = o.Params.of(wl)
+    a = o.image(p, uvw, comb, None)
+    b = o.image(p, wl.uvw, wl.vis, wl.weight)
+    assert np.allclose(a, b, rtol=1e-13, atol=1e-13 * np.abs(b).max())
+
+
+def test_rows_entry_order_and_coefficients():
+    """Entry r*C + c holds row r, channel c; the combination is linear in
+    the coefficients and uses each polarisation's own weight."""
+    rng = np.random.default_rng(7)
+    nr, nc, npol = 3, 5, 2
+    uvw_m = rng.standard_normal((nr, 3)) * 100
+    f = np.linspace(1e8, 2e8, nc)
+    vis = rng.standard_normal((nr, nc, npol)) + 1j * rng.standard_normal(
+        (nr, nc, npol))
+    w = rng.uniform(0.5, 1.5, (nr, npol))
+    uvw, comb, _ = o.expand_rows(uvw_m, f, vis, w, [0.3, -2.0j])
+    for r in range(nr):
+        for c in range(nc):
+            e = r * nc + c
+            assert np.array_equal(uvw[e], uvw_m[r] * (f[c] / o.SPEED_OF_LIGHT))
+            want = 0.3 * w[r, 0] * vis[r, c, 0] - 2.0j * w[r, 1] * vis[r, c, 1]
+            assert comb[e] == pytest.approx(want, rel=1e-15)
