@@ -69,6 +69,17 @@ typedef int32_t ws_status;
 #define WS_FP64 1 /* complex128 data, everything in FP64 (the paper's
                      precision, Sec. 4.2 memory model) */
 
+/* Gridding kernels (Sec. 2, the paragraph after Eq. 3).  WS_KERNEL_GAUSS is
+ * the paper's Gaussian: phi(d) = exp(-d^2/(2 sigma^2)), c = 1/(2 pi sigma^2).
+ * WS_KERNEL_ES is the exponential of a semicircle, the analytic
+ * approximation of the production (prolate-spheroidal) kernels the paper
+ * names as the better choice at the same cost: phi(d) = exp(beta
+ * (sqrt(1 - z^2) - 1)), z = 2 d / K, over the same K x K support, with c = 1 /
+ * (integral of phi over |d| <= K/2)^2 so that the 2-D kernel integrates to
+ * one.  Either kernel enters as G = c phi(i - x) phi(j - y). */
+#define WS_KERNEL_GAUSS 0
+#define WS_KERNEL_ES 1
+
 /* Imaging geometry and kernel.
  *   nu, nv   grid size, each a power of two in [16, 16384]
  *   nw       number of w-planes, >= 1
@@ -82,7 +93,18 @@ typedef int32_t ws_status;
  *   tile     gridding tile edge in cells (power of two, 16..64, > K - 1);
  *            0 = automatic
  *   chunk    most visibilities one gridding work item accumulates before a
- *            split tile is merged; 0 = automatic (4096) */
+ *            split tile is merged; 0 = automatic (4096)
+ *   kernel   WS_KERNEL_GAUSS or WS_KERNEL_ES (sigma applies to the
+ *            Gaussian only)
+ *   beta     ES kernel shape; <= 0 selects 2.3 K; at most 200
+ *   correct  1: grid correction - the image is divided by the kernel's 2-D
+ *            Fourier transform c psi(f_p) psi(f_q), psi(f) the transform of
+ *            the 1-D kernel truncated to |d| <= K/2 and f_p = (p - nu/2)/nu
+ *            cycles per cell (the factor that undoes the kernel's taper of
+ *            the image); degridding multiplies its input image by the same
+ *            real factor, which keeps it the exact adjoint.  Refused
+ *            (WS_INVALID_ARG) when psi is not positive for |f| <= 1/2.
+ *            0: no correction (the dirty image of Eq. 2 as gridded). */
 typedef struct ws_params {
   int32_t nu, nv, nw;
   double fov_l, fov_m;
@@ -92,6 +114,9 @@ typedef struct ws_params {
   int32_t precision;
   int32_t tile;
   int32_t chunk;
+  int32_t kernel;
+  double beta;
+  int32_t correct;
 } ws_params;
 
 typedef struct ws_plan ws_plan;
@@ -105,6 +130,14 @@ ws_status ws_validate_params(const ws_params* params);
  * needs no GPU.  Either output pointer may be NULL. */
 ws_status ws_workspace_bytes(const ws_params* params, int64_t max_vis,
                              size_t* planes_bytes, size_t* work_bytes);
+
+/* The kernel's 1-D Fourier transform and norm, as the library uses them
+ * (host only; needs no GPU): psi[i] = integral over |d| <= K/2 of phi(d)
+ * cos(2 pi f[i] d) dd for i < n (f in cycles per cell; FP64 tanh-sinh
+ * quadrature), and *cnorm = c.  f, psi: host arrays of n doubles (may be
+ * NULL when n = 0); cnorm may be NULL. */
+ws_status ws_kernel_transform(const ws_params* params, int64_t n,
+                              const double* f, double* psi, double* cnorm);
 
 /* Build a plan over caller-owned device buffers (Sec. 2: the Cartesian
  * mesh of N_u x N_v x N_w cells).  planes and work must be device

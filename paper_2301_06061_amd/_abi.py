@@ -21,6 +21,8 @@ WS_HIP_ERROR = -4
 WS_BAD_STATE = -5
 WS_FP32 = 0
 WS_FP64 = 1
+WS_KERNEL_GAUSS = 0
+WS_KERNEL_ES = 1
 WS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -37,6 +39,7 @@ class Params(C.Structure):
         ("w_min", C.c_double), ("w_max", C.c_double),
         ("support", C.c_int32), ("sigma", C.c_double),
         ("precision", C.c_int32), ("tile", C.c_int32), ("chunk", C.c_int32),
+        ("kernel", C.c_int32), ("beta", C.c_double), ("correct", C.c_int32),
     ]
 
 
@@ -46,6 +49,8 @@ _SIGS = {
     "ws_workspace_bytes": (C.c_int32, [C.POINTER(Params), C.c_int64,
                                        C.POINTER(C.c_size_t),
                                        C.POINTER(C.c_size_t)]),
+    "ws_kernel_transform": (C.c_int32, [C.POINTER(Params), C.c_int64, _P, _P,
+                                        _P]),
     "ws_grid_init": (C.c_int32, [C.POINTER(Params), C.c_int64, _P, C.c_size_t,
                                  _P, C.c_size_t, _P, C.POINTER(_P)]),
     "ws_grid_visibilities": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P]),

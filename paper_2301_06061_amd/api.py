@@ -16,13 +16,30 @@ from . import _abi
 
 _PREC = {"fp32": _abi.WS_FP32, "fp64": _abi.WS_FP64,
          0: _abi.WS_FP32, 1: _abi.WS_FP64}
+_KERN = {"gauss": _abi.WS_KERNEL_GAUSS, "es": _abi.WS_KERNEL_ES,
+         0: _abi.WS_KERNEL_GAUSS, 1: _abi.WS_KERNEL_ES}
 
 
 def make_params(nu, nv, nw, fov_l, fov_m, w_min, w_max, support=7,
-                sigma=0.0, precision="fp32", tile=0, chunk=0) -> _abi.Params:
+                sigma=0.0, precision="fp32", tile=0, chunk=0,
+                kernel="gauss", beta=0.0, correct=False) -> _abi.Params:
     return _abi.Params(int(nu), int(nv), int(nw), float(fov_l), float(fov_m),
                        float(w_min), float(w_max), int(support), float(sigma),
-                       _PREC[precision], int(tile), int(chunk))
+                       _PREC[precision], int(tile), int(chunk),
+                       _KERN[kernel], float(beta), int(bool(correct)))
+
+
+def kernel_transform(params: _abi.Params, f):
+    """(psi(f), c): the library's 1-D kernel transform at the frequencies f
+    (cycles per cell) and its kernel norm (host only)."""
+    import numpy as np
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+    psi = np.empty_like(f)
+    c = C.c_double(0.0)
+    _abi.call("ws_kernel_transform", C.byref(params), int(f.size),
+              f.ctypes.data_as(C.c_void_p), psi.ctypes.data_as(C.c_void_p),
+              C.byref(c))
+    return psi, c.value
 
 
 def workspace_bytes(params: _abi.Params, max_vis: int):
@@ -84,9 +101,11 @@ class WStackPlan:
 
     def __init__(self, nu, nv, nw, fov_l, fov_m, w_min, w_max, support=7,
                  sigma=0.0, precision="fp32", max_vis=1 << 20, tile=0,
-                 chunk=0, device=None):
+                 chunk=0, device=None, kernel="gauss", beta=0.0,
+                 correct=False):
         self.params = make_params(nu, nv, nw, fov_l, fov_m, w_min, w_max,
-                                  support, sigma, precision, tile, chunk)
+                                  support, sigma, precision, tile, chunk,
+                                  kernel, beta, correct)
         self.fp64 = self.params.precision == _abi.WS_FP64
         self.cdtype = torch.complex128 if self.fp64 else torch.complex64
         self.rdtype = torch.float64 if self.fp64 else torch.float32
@@ -109,6 +128,9 @@ class WStackPlan:
     def from_workload(cls, wl, max_vis=None, precision=None, **kw):
         prec = precision if precision is not None else (
             "fp64" if wl.precision == 1 else "fp32")
+        kw.setdefault("kernel", getattr(wl, "kernel", "gauss"))
+        kw.setdefault("beta", getattr(wl, "beta", 0.0))
+        kw.setdefault("correct", bool(getattr(wl, "correct", False)))
         return cls(wl.nu, wl.nv, wl.nw, wl.fov_l, wl.fov_m, wl.w_min,
                    wl.w_max, wl.support, wl.sigma, prec,
                    max_vis=max(1, wl.m) if max_vis is None else max_vis, **kw)

@@ -52,7 +52,10 @@ class BatchedImager:
                                wl.w_min, wl.w_max, wl.support,
                                getattr(wl, "sigma", 0.0), precision,
                                max_vis=max(1, int(self.uvw[i].shape[0])),
-                               tile=tile, chunk=chunk, device=self.device)
+                               tile=tile, chunk=chunk, device=self.device,
+                               kernel=getattr(wl, "kernel", "gauss"),
+                               beta=getattr(wl, "beta", 0.0),
+                               correct=bool(getattr(wl, "correct", False)))
                 self.plans.append(p)
             self.images = [p.new_image() for p in self.plans]
         wb = C.c_size_t(0)

@@ -59,7 +59,7 @@ struct Layout {
   uint32_t max_extra;
   size_t planes_bytes;
   // workspace offsets
-  size_t o_tw_u, o_tw_v, o_counts, o_sums, o_keyrank, o_rec, o_chunks,
+  size_t o_tw_u, o_tw_v, o_corr, o_counts, o_sums, o_keyrank, o_rec, o_chunks,
       o_slot, o_counters, o_split, o_extra, o_busy, o_idle, o_copies, o_desc,
       o_strips, o_partials, o_scratch, total;
 };
@@ -90,6 +90,13 @@ ws_status check_params(const ws_params* p) {
     return fail(WS_INVALID_ARG, "w_max < w_min");
   if (!std::isfinite(p->sigma))
     return fail(WS_INVALID_ARG, "sigma must be finite");
+  if (p->kernel != WS_KERNEL_GAUSS && p->kernel != WS_KERNEL_ES)
+    return fail(WS_INVALID_ARG,
+                "kernel=%d: use WS_KERNEL_GAUSS or WS_KERNEL_ES", p->kernel);
+  if (!std::isfinite(p->beta) || p->beta > 200.0)
+    return fail(WS_INVALID_ARG, "beta must be finite and <= 200");
+  if (p->correct != 0 && p->correct != 1)
+    return fail(WS_INVALID_ARG, "correct=%d: use 0 or 1", p->correct);
   if (p->precision != WS_FP32 && p->precision != WS_FP64)
     return fail(WS_INVALID_ARG, "precision=%d: use WS_FP32 or WS_FP64",
                 p->precision);
@@ -113,6 +120,28 @@ ws_status check_params(const ws_params* p) {
   const int64_t cells = (int64_t)p->nu * p->nv;
   if (p->nw > (int64_t(1) << 40) / cells)
     return fail(WS_UNSUPPORTED_SIZE, "plane stack too large");
+  if (p->correct) {
+    // The correction divides by the kernel's transform, which must stay
+    // positive out to the highest pixel frequency, |f| = 1/2 cycle per cell
+    // (psi is even).  Checked on 257 frequencies; a kernel wide enough for
+    // a sign change of psi inside |f| <= 1/2 (a broad truncated Gaussian,
+    // a small beta) shows it on this grid.
+    const double sigma = p->sigma > 0 ? p->sigma : p->support / 7.0;
+    const double beta = p->beta > 0 ? p->beta : 2.3 * p->support;
+    const double psi0 = kernel_transform(p->kernel, p->support,
+                                         1.0 / (2.0 * sigma * sigma), beta,
+                                         0.0);
+    for (int i = 0; i <= 256; ++i) {
+      const double psi = kernel_transform(p->kernel, p->support,
+                                          1.0 / (2.0 * sigma * sigma), beta,
+                                          0.5 * i / 256.0);
+      if (!(psi > 1e-12 * psi0))
+        return fail(WS_INVALID_ARG,
+                    "grid correction: the kernel's transform is not positive "
+                    "at f = %.4f cycles per cell (psi = %g)", 0.5 * i / 256.0,
+                    psi);
+    }
+  }
   return WS_OK;
 }
 
@@ -155,6 +184,8 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   const int64_t nscan = L->nkeys > L->ntiles ? L->nkeys : L->ntiles;
   L->o_tw_u = take((size_t)p->nu * L->elem);
   L->o_tw_v = take((size_t)p->nv * L->elem);
+  // Grid-correction factors (u axis, then v axis), FP64.
+  L->o_corr = take((size_t)(p->nu + p->nv) * 8);
   // Key counts, scanned in place into key offsets (+ the total).
   L->o_counts = take((size_t)(L->nkeys + 1) * 4);
   // kCountCopies copies of the key counts, turned into per-copy offsets.
@@ -279,7 +310,21 @@ Geo make_geo(const ws_params* p, const Layout& L) {
   const double sigma = p->sigma > 0 ? p->sigma : p->support / 7.0;
   g.inv2s2 = 1.0 / (2.0 * sigma * sigma);
   g.kappa = (float)(1.4426950408889634074 / (2.0 * sigma * sigma));
-  g.cnorm = 1.0 / (2.0 * M_PI * sigma * sigma);
+  g.kern = p->kernel;
+  g.es_beta = p->beta > 0 ? p->beta : 2.3 * p->support;
+  g.es_zs = 2.0 / p->support;
+  g.es_beta2 = (float)(g.es_beta * 1.4426950408889634074);
+  g.es_zs_f = (float)g.es_zs;
+  if (p->kernel == WS_KERNEL_ES) {
+    // c = 1 / (integral of phi)^2: the continuous 2-D kernel integrates to
+    // one, as the Gaussian's 1 / (2 pi sigma^2) does.
+    const double psi0 = kernel_transform(g.kern, g.K, g.inv2s2, g.es_beta,
+                                         0.0);
+    g.cnorm = 1.0 / (psi0 * psi0);
+  } else {
+    g.cnorm = 1.0 / (2.0 * M_PI * sigma * sigma);
+  }
+  g.corr = nullptr;  // set by init_plan when the plan corrects
   return g;
 }
 
@@ -589,6 +634,7 @@ struct ws_batch {
   unsigned char* work;
   int precision;
   int K;
+  int kern;
   size_t lds;
   hipStream_t stream;
   hipGraph_t graph;
@@ -633,7 +679,8 @@ ws_status batch_image_impl(ws_batch* b, const int64_t* m,
   }
   WS_TRY(launch(p0, "grid_batch", [&] {
     launch_grid_batch<R>(reinterpret_cast<const GridJob<R>*>(b->work), b->n,
-                         b->K, b->lds, queue, items, p0->cus, b->stream);
+                         b->K, b->kern, b->lds, queue, items, p0->cus,
+                         b->stream);
   }));
   for (int i = 0; i < b->n; ++i) {
     ws_plan* pl = b->plans[i];
@@ -694,6 +741,12 @@ ws_status init_plan(ws_plan* pl, const ws_params* params, int64_t max_vis,
       pl->cus = n;
   }
   pl->profile = false;
+  if (params->correct) {
+    double* corr = pl->w<double>(L.o_corr);
+    pl->g.corr = corr;
+    WS_TRY(launch(pl, "correction",
+                  [&] { launch_correction(pl->g, corr, pl->stream); }));
+  }
   if (params->precision == WS_FP64) {
     return launch(pl, "twiddles", [&] {
       launch_twiddles<double>(pl->work + L.o_tw_u, params->nu, pl->stream);
@@ -751,6 +804,20 @@ ws_status ws_workspace_bytes(const ws_params* params, int64_t max_vis,
   WS_TRY(make_layout(params, max_vis, &L));
   if (planes_bytes) *planes_bytes = L.planes_bytes;
   if (work_bytes) *work_bytes = L.total;
+  return WS_OK;
+}
+
+ws_status ws_kernel_transform(const ws_params* params, int64_t n,
+                              const double* f, double* psi, double* cnorm) {
+  WS_TRY(check_params(params));
+  if (n < 0 || (n > 0 && (f == nullptr || psi == nullptr)))
+    return fail(WS_INVALID_ARG, "n=%lld with f or psi NULL", (long long)n);
+  Layout L{};
+  L.T = 16;
+  const Geo g = make_geo(params, L);
+  for (int64_t i = 0; i < n; ++i)
+    psi[i] = kernel_transform(g.kern, g.K, g.inv2s2, g.es_beta, f[i]);
+  if (cnorm != nullptr) *cnorm = g.cnorm;
   return WS_OK;
 }
 
@@ -1051,10 +1118,11 @@ ws_status ws_batch_create(int32_t n, ws_plan* const* plans, void* work,
     if (plans[i] == nullptr) return fail(WS_INVALID_ARG, "plan %d is NULL", i);
     if (plans[i]->p.precision != plans[0]->p.precision ||
         plans[i]->p.support != plans[0]->p.support ||
+        plans[i]->p.kernel != plans[0]->p.kernel ||
         plans[i]->device != plans[0]->device)
       return fail(WS_INVALID_ARG,
-                  "plan %d: all plans of a batch share precision, support "
-                  "and device", i);
+                  "plan %d: all plans of a batch share precision, support, "
+                  "kernel type and device", i);
     for (int j2 = 0; j2 < i; ++j2)
       if (plans[j2] == plans[i])
         return fail(WS_INVALID_ARG, "plan %d appears twice", i);
@@ -1067,6 +1135,7 @@ ws_status ws_batch_create(int32_t n, ws_plan* const* plans, void* work,
   b->work = static_cast<unsigned char*>(work);
   b->precision = plans[0]->p.precision;
   b->K = plans[0]->p.support;
+  b->kern = plans[0]->p.kernel;
   b->stream = plans[0]->stream;
   b->graph = nullptr;
   b->exec = nullptr;

@@ -710,6 +710,18 @@ struct Screen<float> {
   }
 };
 
+// Grid correction of pixel (p, q): 1 / (c psi(f_p) psi(f_q)) from the
+// plan's table, or 1 when the plan has none (uniform branch).  Imaging
+// multiplies the plane sum by it; degridding multiplies its input image by
+// it (the correction is real and diagonal, so it is its own adjoint).
+template <typename R>
+__device__ __forceinline__ cplx<R> corrected(const Geo& g, int p, int q,
+                                             cplx<R> v) {
+  if (g.corr == nullptr) return v;
+  const R c = (R)(g.corr[p] * g.corr[g.nu + q]);
+  return {v.re * c, v.im * c};
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_wcorrect(const cplx<R>* __restrict__ F,
                                                   cplx<R>* __restrict__ img,
@@ -726,7 +738,7 @@ __global__ __launch_bounds__(256) void k_wcorrect(const cplx<R>* __restrict__ F,
     const cplx<R> f = F[(size_t)k * npix + src];
     acc = cadd(acc, cmul(f, sc.next(g, k)));
   }
-  img[pix] = cadd(img[pix], acc);
+  img[pix] = cadd(img[pix], corrected(g, p, q, acc));
 }
 
 // Row transform of every plane + screen + plane sum into image row q.
@@ -837,7 +849,8 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
     for (int r = 0; r < RAD; ++r) {
       const int j = threadIdx.x + it * NT;
       if (NB % NT == 0 || j < NB)
-        out[j + r * NB] = cadd(old[it][r], acc[it][r]);
+        out[j + r * NB] =
+            cadd(old[it][r], corrected(g, j + r * NB, q, acc[it][r]));
     }
 }
 
@@ -874,6 +887,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_screen_row_bcast
         } else {
           x[it][r] = reinterpret_cast<const cplx<R>*>(img)[(size_t)q * N + p];
         }
+        x[it][r] = corrected(g, p, q, x[it][r]);
         sc[it][r].init(g, p, q, true);
       }
     }
@@ -901,6 +915,7 @@ __global__ __launch_bounds__(256) void k_screen_bcast(
   cplx<R> x = {(R)0, (R)0};
   if (img_real) x.re = reinterpret_cast<const R*>(img)[pix];
   else x = reinterpret_cast<const cplx<R>*>(img)[pix];
+  x = corrected(g, p, q, x);
   Screen<R> sc;
   sc.init(g, p, q, true);
   for (int k = 0; k < g.nw; ++k) {
@@ -920,6 +935,19 @@ __global__ __launch_bounds__(256) void k_fill_zero_u32(uint32_t* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t t = i; t < n; t += stride) p[t] = 0u;
+}
+
+// Grid-correction table: thread i < nu gives 1 / (c psi(f_i)) for the u
+// axis, thread nu + i gives 1 / psi(f_i) for the v axis.
+__global__ __launch_bounds__(256) void k_correction(Geo g, double* corr) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nu + g.nv) return;
+  const bool u = i < g.nu;
+  const int n = u ? g.nu : g.nv;
+  const int idx = u ? i : i - g.nu;
+  const double f = (double)(idx - n / 2) / (double)n;
+  const double psi = kernel_transform(g.kern, g.K, g.inv2s2, g.es_beta, f);
+  corr[i] = 1.0 / ((u ? g.cnorm : 1.0) * psi);
 }
 
 template <typename R>
@@ -1210,6 +1238,12 @@ void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st) {
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_fill_zero_u32, dim3((unsigned)blocks), dim3(256), 0, st,
                      p, n);
+}
+
+void launch_correction(const Geo& g, double* corr, hipStream_t st) {
+  const int n = g.nu + g.nv;
+  hipLaunchKernelGGL(k_correction, dim3((n + 255) / 256), dim3(256), 0, st,
+                     g, corr);
 }
 
 template <typename R>

@@ -49,24 +49,35 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// One-dimensional kernel factor g(d) = exp(-d^2 / (2 sigma^2)); FP32 uses
-// the hardware base-2 exponential (v_exp_f32) with a pre-scaled argument.
-// Arguments never approach the denormal range that would need rescaling:
-// the farthest tap of the widest kernel is at 2^-30 or above.
-__device__ __forceinline__ float gauss1(const Geo& g, float d) {
-  return __builtin_amdgcn_exp2f(-g.kappa * (d * d));
+// One-dimensional kernel factor phi(d) at offset d (cells) from the
+// visibility, for |d| <= K/2 (the taps of the K x K footprint).
+//   Gaussian: exp(-d^2 / (2 sigma^2)); FP32 takes the hardware base-2
+//     exponential (v_exp_f32) of a pre-scaled argument, never near its
+//     denormal range (the farthest tap of the widest kernel is >= 2^-30).
+//   ES: exp(beta (sqrt(1 - z^2) - 1)) = exp(-beta z^2 / (1 + sqrt(1 - z^2))),
+//     the second form free of cancellation near the centre; 1 - z^2 is
+//     clamped at 0 (rounding can take |z| a hair past 1 at the edge tap).
+template <int KT>
+__device__ __forceinline__ float kern1(const Geo& g, float d) {
+  if constexpr (KT == kKernelES) {
+    const float z = d * g.es_zs_f;
+    const float z2 = z * z;
+    const float t = 1.0f - z2 > 0.0f ? 1.0f - z2 : 0.0f;
+    return __builtin_amdgcn_exp2f(-g.es_beta2 * z2 / (1.0f + __builtin_sqrtf(t)));
+  } else {
+    return __builtin_amdgcn_exp2f(-g.kappa * (d * d));
+  }
 }
-__device__ __forceinline__ double gauss1(const Geo& g, double d) {
-  return exp(-g.inv2s2 * (d * d));
-}
-
-// Two-dimensional tap weight g(dx) g(dy) = exp(-(dx^2 + dy^2)/(2 sigma^2))
-// from the squared distance: one exponential per tap.
-__device__ __forceinline__ float gauss2(const Geo& g, float d2) {
-  return __builtin_amdgcn_exp2f(-g.kappa * d2);
-}
-__device__ __forceinline__ double gauss2(const Geo& g, double d2) {
-  return exp(-g.inv2s2 * d2);
+template <int KT>
+__device__ __forceinline__ double kern1(const Geo& g, double d) {
+  if constexpr (KT == kKernelES) {
+    const double z = d * g.es_zs;
+    const double z2 = z * z;
+    const double t = 1.0 - z2 > 0.0 ? 1.0 - z2 : 0.0;
+    return exp(-g.es_beta * z2 / (1.0 + sqrt(t)));
+  } else {
+    return exp(-g.inv2s2 * (d * d));
+  }
 }
 
 struct Item {
@@ -332,30 +343,27 @@ struct RowLanes {
   static constexpr int BS = RPW * NG;  // records per batch (<= 64)
 };
 
-// Kernel weights of one row of taps, exp(-(a - H - dx)^2 / (2 sigma^2)) for
-// a = 0 .. K-1, times the row weight gy.  FP32: one hardware exp2 per tap.
-// FP64: the ratio of neighbouring taps, q(a) = w(a+1) / w(a), itself
+// Kernel weights of one row of taps, phi(a - H - dx) for a = 0 .. K-1.
+// FP32, and the FP64 ES kernel: one kernel evaluation per tap.  FP64
+// Gaussian: the ratio of neighbouring taps, q(a) = w(a+1) / w(a), itself
 // changes by the constant factor d = exp(-1 / sigma^2), so a row costs two
 // exps and two products a tap (relative rounding a few ulps of FP64).  The
 // recurrence starts at the far-left tap, whose weight underflows (and the
 // first ratio overflows) once (h + 1/2)^2 / (2 sigma^2) nears the FP64
 // exponent range; such narrow kernels (`direct`, a uniform flag) take one
 // exp per tap instead.
-template <typename R, int K>
-struct RowWeights;
-template <int K>
-struct RowWeights<float, K> {
-  float dx;
-  float kappa;
-  __device__ __forceinline__ RowWeights(const Geo& g, float dx_, double)
-      : dx(dx_), kappa(g.kappa) {}
-  __device__ __forceinline__ float at(int a) {
-    const float ex = (float)(a - (K - 1) / 2) - dx;
-    return __builtin_amdgcn_exp2f(-kappa * (ex * ex));
+template <typename R, int K, int KT>
+struct RowWeights {
+  const Geo& g;
+  R dx;
+  __device__ __forceinline__ RowWeights(const Geo& g_, R dx_, double)
+      : g(g_), dx(dx_) {}
+  __device__ __forceinline__ R at(int a) {
+    return kern1<KT>(g, (R)(a - (K - 1) / 2) - dx);
   }
 };
 template <int K>
-struct RowWeights<double, K> {
+struct RowWeights<double, K, kKernelGauss> {
   double w, q, d, dx, inv2s2;
   bool direct;
   __device__ __forceinline__ RowWeights(const Geo& g, double dx_, double d_) {
@@ -382,7 +390,7 @@ struct RowWeights<double, K> {
 
 // Adds kernel row `row` of one record to the LDS tile (taps outside the
 // tile belong to a neighbouring tile and are skipped).
-template <typename R, int K>
+template <typename R, int K, int KT>
 __device__ __forceinline__ void add_row(const Geo& g, uint32_t cc, R dx, R dy,
                                         R vr, R vi, int row, int ox, int oy,
                                         int T, int pitch, double d,
@@ -392,11 +400,11 @@ __device__ __forceinline__ void add_row(const Geo& g, uint32_t cc, R dx, R dy,
   const int lj = cell_j(cc) - oy + row - H;
   if ((unsigned)lj >= (unsigned)T) return;
   const R ey = (R)(row - H) - dy;
-  const R gy = gauss2(g, ey * ey);
+  const R gy = kern1<KT>(g, ey);
   const R wr = gy * vr, wi = gy * vi;
   GridAcc<R>* pre = s_re + lj * pitch + ci;
   GridAcc<R>* pim = s_im + lj * pitch + ci;
-  RowWeights<R, K> rw(g, dx, d);
+  RowWeights<R, K, KT> rw(g, dx, d);
 #pragma unroll
   for (int a = 0; a < K; ++a) {
     const R gx = rw.at(a);
@@ -419,7 +427,7 @@ __device__ __forceinline__ uint32_t lane_value_u(uint32_t x, int src) {
 // an equal run of the item's list positions, BS at a time (one record per
 // lane), with the next BS in flight while the current ones are added a
 // group of RPW records at a time (lane values moved by lane permutes).
-template <typename R, int K>
+template <typename R, int K, int KT>
 __device__ __forceinline__ void accumulate_item(const GridJob<R>& j,
                                                 const GridItem<R>& x,
                                                 GridAcc<R>* s_re,
@@ -451,8 +459,8 @@ __device__ __forceinline__ void accumulate_item(const GridJob<R>& j,
       const R dx = lane_value(cur.dxy.re, src), dy = lane_value(cur.dxy.im, src);
       const R vr = lane_value(cur.val.re, src), vi = lane_value(cur.val.im, src);
       if (act && src < cnt)
-        add_row<R, K>(j.g, cc, dx, dy, vr, vi, row, ox, oy, T, pitch, d, s_re,
-                      s_im);
+        add_row<R, K, KT>(j.g, cc, dx, dy, vr, vi, row, ox, oy, T, pitch, d,
+                          s_re, s_im);
     }
     cur = nxt;
     b0 = b1;
@@ -496,7 +504,7 @@ __device__ __forceinline__ void clear_lds(A* s, uint32_t words) {
 // is loaded while the current one accumulates, and that item's first
 // records are requested before the current tile's global stores, which
 // then drain while it starts.  The barriers order LDS only.
-template <typename R, int K, class Locate>
+template <typename R, int K, int KT, class Locate>
 __device__ __forceinline__ void item_loop(GridAcc<R>* s_lds, uint32_t* queue,
                                           uint32_t* s_next,
                                           const GridJob<R>* job0,
@@ -519,7 +527,7 @@ __device__ __forceinline__ void item_loop(GridAcc<R>* s_lds, uint32_t* queue,
     const GridJob<R>& j = *job;
     GridAcc<R>* s_re = s_lds;
     GridAcc<R>* s_im = s_lds + j.g.T * j.pitch;
-    if (x.f1 > x.f0) accumulate_item<R, K>(j, x, s_re, s_im);
+    if (x.f1 > x.f0) accumulate_item<R, K, KT>(j, x, s_re, s_im);
     lds_barrier();  // LDS sums complete; s_next visible
     const GridItem<R> nx = item_from(*jn, dn, vn);
     const GridJob<R>* jnn = job0;
@@ -533,14 +541,14 @@ __device__ __forceinline__ void item_loop(GridAcc<R>* s_lds, uint32_t* queue,
   }
 }
 
-template <typename R, int K>
+template <typename R, int K, int KT>
 __global__ __launch_bounds__(kGridThreads) void k_grid_tiles(GridJob<R> j) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t s_next[2];
   GridAcc<R>* s_lds = reinterpret_cast<GridAcc<R>*>(smem);
   const uint32_t total = item_total(j.counters);
   clear_lds(s_lds, 2u * (uint32_t)(j.g.T * j.pitch));
-  item_loop<R, K>(s_lds, &j.counters[3], s_next, &j,
+  item_loop<R, K, KT>(s_lds, &j.counters[3], s_next, &j,
                   [&](uint32_t n, const GridJob<R>*&, uint32_t& li) {
                     li = n;
                     return n < total;
@@ -551,7 +559,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_tiles(GridJob<R> j) {
 // work items of every job (plan), job after job; the LDS tile is sized for
 // the largest tile of the batch (lds_words accumulators in all).  Jobs are
 // read in place (uniform loads), never copied.
-template <typename R, int K>
+template <typename R, int K, int KT>
 __global__ __launch_bounds__(kGridThreads) void k_grid_batch(
     const GridJob<R>* __restrict__ jobs, int njobs,
     uint32_t* __restrict__ queue, uint32_t lds_words) {
@@ -569,7 +577,7 @@ __global__ __launch_bounds__(kGridThreads) void k_grid_batch(
   }
   clear_lds(s_lds, lds_words);
   lds_barrier();
-  item_loop<R, K>(s_lds, queue, s_next, jobs,
+  item_loop<R, K, KT>(s_lds, queue, s_next, jobs,
                   [&](uint32_t n, const GridJob<R>*& jp, uint32_t& li) {
                     int p = 0;
                     const bool live = n < s_base[njobs];
@@ -660,7 +668,7 @@ __global__ __launch_bounds__(1024) void k_grid_merge(
   }
 }
 
-template <typename R, int K>
+template <typename R, int K, int KT>
 __global__ __launch_bounds__(256) void k_degrid_tiles(
     Geo g, const uint32_t* __restrict__ offsets,
     uint32_t* __restrict__ counters, const uint2* __restrict__ extra,
@@ -742,8 +750,8 @@ __global__ __launch_bounds__(256) void k_degrid_tiles(
         R gx[K], gy[K];
 #pragma unroll
         for (int a = 0; a < K; ++a) {
-          gx[a] = gauss1(g, (R)(a - H) - q.dx);
-          gy[a] = gauss1(g, (R)(a - H) - q.dy);
+          gx[a] = kern1<KT>(g, (R)(a - H) - q.dx);
+          gy[a] = kern1<KT>(g, (R)(a - H) - q.dy);
         }
         cplx<R> acc = {(R)0, (R)0};
 #pragma unroll
@@ -785,33 +793,33 @@ uint32_t persistent_groups(size_t lds_bytes, int cus, uint32_t max_items) {
   return (uint32_t)(n > 0 ? n : 1);
 }
 
-template <typename R, int K>
+template <typename R, int K, int KT>
 void grid_k(const GridJob<R>& j, uint32_t max_items, int cus,
             hipStream_t st) {
   const size_t lds = grid_lds_bytes(j.g.T, K, (int)sizeof(R));
-  hipLaunchKernelGGL((k_grid_tiles<R, K>),
+  hipLaunchKernelGGL((k_grid_tiles<R, K, KT>),
                      dim3(persistent_groups(lds, cus, max_items)),
                      dim3(kGridThreads), lds, st, j);
 }
 
-template <typename R, int K>
+template <typename R, int K, int KT>
 void grid_batch_k(const GridJob<R>* jobs, int njobs, size_t lds,
                   uint32_t* queue, uint32_t max_items, int cus,
                   hipStream_t st) {
-  hipLaunchKernelGGL((k_grid_batch<R, K>),
+  hipLaunchKernelGGL((k_grid_batch<R, K, KT>),
                      dim3(persistent_groups(lds, cus, max_items)),
                      dim3(kGridThreads), lds, st, jobs, njobs, queue,
                      (uint32_t)(lds / sizeof(GridAcc<R>)));
 }
 
-template <typename R, int K>
+template <typename R, int K, int KT>
 void degrid_k(const Geo& g, const uint32_t* offsets, uint32_t* counters,
               const uint2* extra, const uint32_t* busy, const void* planes,
               const void* records, uint32_t chunk,
               void* vis_out, uint32_t max_items, int cus, hipStream_t st) {
   const int W = g.T + (K - 1);
   const size_t lds = (size_t)W * W * sizeof(cplx<R>);
-  hipLaunchKernelGGL((k_degrid_tiles<R, K>),
+  hipLaunchKernelGGL((k_degrid_tiles<R, K, KT>),
                      dim3(max_items > 0 ? max_items : 1), dim3(256),
                      lds, st, g, offsets, counters, extra, busy,
                      (const cplx<R>*)planes, (const Record<R>*)records,
@@ -831,31 +839,41 @@ int grid_lds_pitch(int T, int K) {
   return T + K;
 }
 
-#define WS_K_SWITCH(KVAR, CALL)                                           \
+// Dispatch on the support (KK) and the kernel type (KT), both compile-time
+// specialisations of the gridding and degridding kernels.
+#define WS_KT_SWITCH(KK, KTVAR, CALL)                                     \
+  if ((KTVAR) == kKernelES) {                                             \
+    constexpr int KT = kKernelES;                                         \
+    CALL;                                                                 \
+  } else {                                                                \
+    constexpr int KT = kKernelGauss;                                      \
+    CALL;                                                                 \
+  }
+#define WS_K_SWITCH(KVAR, KTVAR, CALL)                                    \
   switch (KVAR) {                                                         \
-    case 1: { constexpr int KK = 1; CALL; } break;                        \
-    case 3: { constexpr int KK = 3; CALL; } break;                        \
-    case 5: { constexpr int KK = 5; CALL; } break;                        \
-    case 7: { constexpr int KK = 7; CALL; } break;                        \
-    case 9: { constexpr int KK = 9; CALL; } break;                        \
-    case 11: { constexpr int KK = 11; CALL; } break;                      \
-    case 13: { constexpr int KK = 13; CALL; } break;                      \
-    case 15: { constexpr int KK = 15; CALL; } break;                      \
+    case 1: { constexpr int KK = 1; WS_KT_SWITCH(KK, KTVAR, CALL) } break; \
+    case 3: { constexpr int KK = 3; WS_KT_SWITCH(KK, KTVAR, CALL) } break; \
+    case 5: { constexpr int KK = 5; WS_KT_SWITCH(KK, KTVAR, CALL) } break; \
+    case 7: { constexpr int KK = 7; WS_KT_SWITCH(KK, KTVAR, CALL) } break; \
+    case 9: { constexpr int KK = 9; WS_KT_SWITCH(KK, KTVAR, CALL) } break; \
+    case 11: { constexpr int KK = 11; WS_KT_SWITCH(KK, KTVAR, CALL) } break; \
+    case 13: { constexpr int KK = 13; WS_KT_SWITCH(KK, KTVAR, CALL) } break; \
+    case 15: { constexpr int KK = 15; WS_KT_SWITCH(KK, KTVAR, CALL) } break; \
     default: break;                                                       \
   }
 
 template <typename R>
 void launch_grid_tiles(const GridJob<R>& j, uint32_t max_items, int cus,
                        hipStream_t st) {
-  WS_K_SWITCH(j.g.K, (grid_k<R, KK>(j, max_items, cus, st)));
+  WS_K_SWITCH(j.g.K, j.g.kern, (grid_k<R, KK, KT>(j, max_items, cus, st)));
 }
 
 template <typename R>
-void launch_grid_batch(const GridJob<R>* jobs, int njobs, int K, size_t lds,
-                       uint32_t* queue, uint32_t max_items, int cus,
-                       hipStream_t st) {
-  WS_K_SWITCH(K, (grid_batch_k<R, KK>(jobs, njobs, lds, queue, max_items,
-                                      cus, st)));
+void launch_grid_batch(const GridJob<R>* jobs, int njobs, int K, int kern,
+                       size_t lds, uint32_t* queue, uint32_t max_items,
+                       int cus, hipStream_t st) {
+  WS_K_SWITCH(K, kern, (grid_batch_k<R, KK, KT>(jobs, njobs, lds, queue,
+                                                max_items, cus, st)));
 }
 
 void launch_item_desc(const Geo& g, const uint32_t* offsets,
@@ -905,12 +923,14 @@ void launch_degrid_tiles(const Geo& g, const uint32_t* offsets,
                          const void* records, uint32_t chunk,
                          void* vis_out, uint32_t max_items, int cus,
                          hipStream_t st) {
-  WS_K_SWITCH(g.K, (degrid_k<R, KK>(g, offsets, counters, extra, busy,
-                                    planes, records, chunk, vis_out,
-                                    max_items, cus, st)));
+  WS_K_SWITCH(g.K, g.kern, (degrid_k<R, KK, KT>(g, offsets, counters,
+                                                extra, busy, planes, records,
+                                                chunk, vis_out, max_items,
+                                                cus, st)));
 }
 
 #undef WS_K_SWITCH
+#undef WS_KT_SWITCH
 
 size_t degrid_lds_bytes(int T, int K, int elem_bytes) {
   const int W = T + K - 1;
@@ -920,8 +940,8 @@ size_t degrid_lds_bytes(int T, int K, int elem_bytes) {
 #define WS_INST(R)                                                          \
   template void launch_grid_tiles<R>(const GridJob<R>&, uint32_t, int,     \
                                      hipStream_t);                         \
-  template void launch_grid_batch<R>(const GridJob<R>*, int, int, size_t,  \
-                                     uint32_t*, uint32_t, int,             \
+  template void launch_grid_batch<R>(const GridJob<R>*, int, int, int,     \
+                                     size_t, uint32_t*, uint32_t, int,     \
                                      hipStream_t);                         \
   template void launch_zero_idle<R>(const Geo&, const uint32_t*,           \
                                     const uint32_t*, void*, hipStream_t);  \

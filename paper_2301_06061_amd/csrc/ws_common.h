@@ -59,12 +59,67 @@ struct Geo {
   double dl, dm;       // pixel size in direction cosines
   double inv2s2;       // 1 / (2 sigma^2), FP64
   float kappa;         // log2(e) / (2 sigma^2), FP32 (exp2 form)
-  double cnorm;        // 1 / (2 pi sigma^2)
+  double cnorm;        // kernel norm c: the 2-D kernel integrates to one
+  // Exponential-of-semicircle kernel phi(d) = exp(beta (sqrt(1 - z^2) - 1)),
+  // z = 2 d / K (used when kern == kKernelES).
+  int kern;            // kKernelGauss or kKernelES
+  double es_beta;      // beta
+  double es_zs;        // 2 / K
+  float es_beta2;      // beta log2(e) (FP32 exp2 form)
+  float es_zs_f;       // 2 / K in FP32
+  // Grid correction: null, or the device table of nu + nv FP64 factors
+  // whose product corr[p] corr[nu + q] is 1 / (c psi(f_p) psi(f_q)).
+  const double* corr;
   // Row order of a transformed stack: 0 = natural; otherwise the columns
   // went through a four-step transform of nv = perm_n1 * perm_n2 and row
   // k1 * perm_n2 + k2 holds column frequency k1 + perm_n1 * k2.
   int perm_n1, perm_n2;
 };
+
+// Gridding kernels (Sec. 2, the paragraph after Eq. 3: the paper's Gaussian,
+// and the exponential of a semicircle as the analytic stand-in for the
+// production kernels it names).
+constexpr int kKernelGauss = 0;
+constexpr int kKernelES = 1;
+
+// psi(f) = integral over |d| <= K/2 of phi(d) cos(2 pi f d) dd: the Fourier
+// transform of the truncated 1-D kernel at f cycles per cell, in FP64.
+// Tanh-sinh (double-exponential) quadrature over the half interval
+// [0, K/2] (the integrand is even): d = (K/4)(1 + tanh(s)),
+// s = (pi/2) sinh(t), t = j h; its node density grows double-exponentially
+// at both ends, which absorbs the square-root edge of the ES kernel.  The
+// distance of a node from the far end, K/2 - d = (K/2) / (1 + e^(2s)), is
+// formed directly so that 1 - z^2 = (1 - z)(1 + z) keeps full precision
+// next to the edge.  h = 1/32 over |t| <= 3.2 (205 nodes) converges to
+// FP64 rounding for every supported kernel.
+__host__ __device__ inline double kernel_transform(int kern, int K,
+                                                   double inv2s2, double beta,
+                                                   double f) {
+  const double a = 0.5 * (double)K;  // half-width of the support
+  const double h = 1.0 / 32.0;
+  const double pi = 3.14159265358979323846;
+  double sum = 0.0;
+  for (int j = -102; j <= 102; ++j) {
+    const double t = (double)j * h;
+    const double s = 0.5 * pi * sinh(t);
+    const double e = exp(2.0 * s);
+    const double far = a / (1.0 + e);     // K/2 - d
+    const double d = a - far;
+    const double ch = cosh(s);
+    const double wt = h * 0.5 * a * (0.5 * pi * cosh(t)) / (ch * ch);
+    double phi;
+    if (kern == kKernelES) {
+      const double omz = far / a;         // 1 - z
+      const double z = 1.0 - omz;
+      const double r = sqrt(omz * (1.0 + z) > 0.0 ? omz * (1.0 + z) : 0.0);
+      phi = exp(-beta * z * z / (1.0 + r));
+    } else {
+      phi = exp(-inv2s2 * d * d);
+    }
+    sum += wt * phi * cos(2.0 * pi * f * d);
+  }
+  return 2.0 * sum;
+}
 
 // Row of the stack that holds column frequency q.
 __host__ __device__ inline int stack_row(const Geo& g, int q) {

@@ -90,9 +90,9 @@ template <typename R>
 void launch_grid_tiles(const GridJob<R>& j, uint32_t max_items, int cus,
                        hipStream_t st);
 template <typename R>
-void launch_grid_batch(const GridJob<R>* jobs, int njobs, int K, size_t lds,
-                       uint32_t* queue, uint32_t max_items, int cus,
-                       hipStream_t st);
+void launch_grid_batch(const GridJob<R>* jobs, int njobs, int K, int kern,
+                       size_t lds, uint32_t* queue, uint32_t max_items,
+                       int cus, hipStream_t st);
 template <typename R>
 void launch_zero_idle(const Geo& g, const uint32_t* counters,
                       const uint32_t* idle, void* planes, hipStream_t st);
@@ -150,5 +150,9 @@ void launch_fill_zero(void* p, int64_t n, hipStream_t st);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
 template <typename R>
 void launch_twiddles(void* tw, int n, hipStream_t st);
+// Grid-correction table of a plan (g.corr must point at nu + nv doubles):
+// corr[p] = 1 / (c psi(f_p)), corr[nu + q] = 1 / psi(f_q), f = (index -
+// n/2) / n, psi the kernel's 1-D transform (kernel_transform).
+void launch_correction(const Geo& g, double* corr, hipStream_t st);
 
 }  // namespace ws

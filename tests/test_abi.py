@@ -128,3 +128,44 @@ def test_noalloc_refuses_before_touching_a_device():
     assert _abi.lib().ws_grid_image_noalloc(C.byref(bad), 10, None, None,
                                             None, None, None, None) == \
         _abi.WS_UNSUPPORTED_SIZE
+
+
+# ---- production kernel and grid correction (host-only parts) -------------
+
+@pytest.mark.parametrize("kernel", ["gauss", "es"])
+@pytest.mark.parametrize("support", [1, 3, 7, 9, 15])
+def test_kernel_transform_matches_oracle(kernel, support):
+    """The library's psi (tanh-sinh quadrature) and kernel norm c against
+    the oracle's (Gauss-Legendre after its own substitution), two
+    independent quadratures of the same integral."""
+    import numpy as np
+    from oracle import wstack as o
+    p = _p(support=support, kernel=kernel)
+    po = o.Params(512, 512, 8, math.radians(1), math.radians(1), -100.0,
+                  100.0, support, kernel=kernel)
+    f = np.linspace(0.0, 0.5, 41)
+    psi, c = ws.api.kernel_transform(p, f)
+    ref = o.kernel_ft(po, f)
+    # Relative to psi(0): where psi is small, both quadratures lose digits
+    # to the cancellation of the oscillating integrand.
+    assert np.abs(psi - ref).max() <= 1e-13 * ref[0]
+    assert c == pytest.approx(o.kernel_norm(po), rel=1e-13)
+
+
+def test_kernel_params_validated():
+    ws.validate(_p(kernel="es", beta=0.0, correct=True))
+    ws.validate(_p(kernel="es", beta=12.5))
+    for bad in (dict(kernel=2), dict(beta=float("nan")), dict(beta=1e9),
+                dict(correct=2)):
+        p = _p()
+        for k, v in bad.items():
+            setattr(p, k, v)
+        with pytest.raises(ws.WStackError) as e:
+            ws.validate(p)
+        assert e.value.status == _abi.WS_INVALID_ARG
+    # A broad truncated Gaussian has a transform that changes sign inside
+    # |f| <= 1/2: its correction is refused.
+    with pytest.raises(ws.WStackError) as e:
+        ws.validate(_p(support=7, sigma=6.0, correct=True))
+    assert e.value.status == _abi.WS_INVALID_ARG
+    ws.validate(_p(support=7, sigma=6.0, correct=False))

@@ -30,11 +30,18 @@ def test_noalloc_matches_plan_path_twice(precision):
     cases = [synth.random_case(71, n=512, nw=6, support=7, m=200_000,
                                law="core", precision=prec),
              synth.edge_case(72, n=256, nv=128, nw=4, support=9, m=3000,
-                             precision=prec)]
+                             precision=prec),
+             synth.random_case(73, n=128, nw=3, support=7, m=1000,
+                               law="core", precision=prec)]
+    # The third call: the ES kernel with grid correction (its table also
+    # lives in the scratch).
+    cases[2].kernel = "es"
+    cases[2].correct = True
     for wl in cases:
         params = api.make_params(wl.nu, wl.nv, wl.nw, wl.fov_l, wl.fov_m,
                                  wl.w_min, wl.w_max, wl.support, wl.sigma,
-                                 precision)
+                                 precision, kernel=wl.kernel,
+                                 correct=wl.correct)
         uvw = torch.from_numpy(wl.uvw).to(d)
         vis = torch.from_numpy(wl.vis).to(d)
         wt = torch.from_numpy(wl.weight).to(d)
