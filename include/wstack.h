@@ -202,6 +202,44 @@ ws_status ws_grid_image(ws_plan* plan, int64_t m, const double* uvw,
                         const void* vis, const float* weight, void* image,
                         int64_t* n_dropped_taps);
 
+/* Baseline-major gridding (Sec. 2, data structures: (u, v, w) per baseline
+ * and measurement time, several visibilities per baseline from the
+ * frequency channels and polarisations, a weight per measurement and
+ * polarisation; Sec. 3.4.2: one GPU thread per measurement convolves all
+ * of its frequencies and polarisations; Sec. 5: full multi-wavelength and
+ * polarisation support as future work).  The same gridding as
+ * ws_grid_visibilities over m = nrows * nchan visibilities, entry
+ * r * nchan + c for row r (one baseline at one time) and channel c:
+ *   uvw_m     device float64 [nrows][3], baseline coordinates in METRES;
+ *             the visibility of channel c sits at uvw_m[r] * (freq_hz[c] /
+ *             c0) wavelengths, c0 = 299792458 m/s (the scale formed first,
+ *             then one product per coordinate, in FP64);
+ *   freq_hz   device float64 [nchan], channel frequencies;
+ *   vis       device complex64 (FP32 path) or complex128 (FP64 path)
+ *             [nrows][nchan][npol], the npol correlations;
+ *   weight    device float32 [nrows][npol] or NULL (unit);
+ *   pol_coeff HOST float64 [npol][2] (re, im): coefficients a_p of the
+ *             gridded value sum_p a_p weight[r][p] vis[r][c][p], formed in
+ *             FP64 and rounded to the path precision (a Stokes parameter
+ *             from linear or circular correlations, e.g. I = (XX + YY)/2:
+ *             a = (1/2, 0, 0, 1/2)); copied before the call returns;
+ *   1 <= npol <= 4, nchan >= 1, 0 <= nrows * nchan <= max_vis.
+ * n_dropped_taps: as for ws_grid_visibilities. */
+ws_status ws_grid_rows(ws_plan* plan, int64_t nrows, int32_t nchan,
+                       int32_t npol, const double* uvw_m,
+                       const double* freq_hz, const void* vis,
+                       const float* weight, const double* pol_coeff,
+                       int64_t* n_dropped_taps);
+
+/* Baseline-major input through the one-call path: the image of
+ * ws_grid_image for the visibilities ws_grid_rows defines.  Arguments as
+ * for those two calls; the plan must be empty and is empty afterwards. */
+ws_status ws_grid_image_rows(ws_plan* plan, int64_t nrows, int32_t nchan,
+                             int32_t npol, const double* uvw_m,
+                             const double* freq_hz, const void* vis,
+                             const float* weight, const double* pol_coeff,
+                             void* image, int64_t* n_dropped_taps);
+
 /* Degridding (Sec. 5 future work): the exact adjoint of gridding, FFT(+1)
  * and w-correction.  vis_out[m] = w_m sum_taps c g g Q_k(m)[j][i] with
  * Q_k = FFT(-1)(conj(screen_k) * X).  image: device [nv][nu], complex in the

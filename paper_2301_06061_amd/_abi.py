@@ -59,6 +59,10 @@ _SIGS = {
     "ws_image_accumulate": (C.c_int32, [_P, _P]),
     "ws_grid_image": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P, _P]),
     "ws_tile_stats": (C.c_int32, [_P, _P]),
+    "ws_grid_rows": (C.c_int32, [_P, C.c_int64, C.c_int32, C.c_int32, _P,
+                                 _P, _P, _P, _P, _P]),
+    "ws_grid_image_rows": (C.c_int32, [_P, C.c_int64, C.c_int32, C.c_int32,
+                                       _P, _P, _P, _P, _P, _P, _P]),
     "ws_degrid": (C.c_int32, [_P, _P, C.c_int32, C.c_int64, _P, _P, _P]),
     "ws_grid_image_noalloc": (C.c_int32, [C.POINTER(Params), C.c_int64, _P,
                                           _P, _P, _P, _P, _P]),

@@ -206,6 +206,50 @@ class WStackPlan:
                   _ptr(weight), _ptr(image), _ptr(dropped))
         return image
 
+    def _rows_args(self, uvw_m, freq_hz, vis, weight, pol_coeff):
+        if vis.dim() != 3:
+            raise ValueError("vis must be [nrows, nchan, npol]")
+        nrows, nchan, npol = (int(x) for x in vis.shape)
+        self._check(uvw_m, torch.float64, (nrows, 3), "uvw_m")
+        self._check(freq_hz, torch.float64, (nchan,), "freq_hz")
+        self._check(vis, self.cdtype, None, "vis")
+        self._check(weight, torch.float32, (nrows, npol), "weight")
+        import numpy as np
+        coeff = np.ascontiguousarray(
+            np.asarray(pol_coeff, dtype=np.complex128).reshape(npol))
+        pc = np.ascontiguousarray(
+            np.stack([coeff.real, coeff.imag], axis=1), dtype=np.float64)
+        return nrows, nchan, npol, pc
+
+    def grid_rows(self, uvw_m, freq_hz, vis, weight, pol_coeff, dropped=None):
+        """Baseline-major gridding (additive): uvw_m [R, 3] metres, freq_hz
+        [C], vis [R, C, P], weight [R, P] or None, pol_coeff P complex
+        coefficients of the gridded combination (host values)."""
+        nrows, nchan, npol, pc = self._rows_args(uvw_m, freq_hz, vis, weight,
+                                                 pol_coeff)
+        self._check(dropped, torch.int64, (1,), "dropped")
+        self._bind()
+        _abi.call("ws_grid_rows", self._h, nrows, nchan, npol, _ptr(uvw_m),
+                  _ptr(freq_hz), _ptr(vis), _ptr(weight),
+                  pc.ctypes.data_as(C.c_void_p), _ptr(dropped))
+
+    def grid_image_rows(self, uvw_m, freq_hz, vis, weight, pol_coeff,
+                        image=None, dropped=None):
+        """Baseline-major input through the one-call path (the stack must
+        be empty); adds into ``image`` (a new zero image if None)."""
+        nrows, nchan, npol, pc = self._rows_args(uvw_m, freq_hz, vis, weight,
+                                                 pol_coeff)
+        if image is None:
+            image = self.new_image()
+        self._check(image, self.cdtype, (self.params.nv, self.params.nu),
+                    "image")
+        self._check(dropped, torch.int64, (1,), "dropped")
+        self._bind()
+        _abi.call("ws_grid_image_rows", self._h, nrows, nchan, npol,
+                  _ptr(uvw_m), _ptr(freq_hz), _ptr(vis), _ptr(weight),
+                  pc.ctypes.data_as(C.c_void_p), _ptr(image), _ptr(dropped))
+        return image
+
     def new_image(self):
         return torch.zeros((self.params.nv, self.params.nu), dtype=self.cdtype,
                            device=self.device)

@@ -1,13 +1,26 @@
 """Autotuner for the gridder's launch parameters.
 
-For a shape class - grid size, plane count, kernel support, precision and
-the visibility count rounded to a half decade - it times the gridding step
-(binning + tile accumulation + merge) on the caller's own data for every
-candidate (tile edge T, records per work item C) and keeps the fastest.
+For a shape class - grid size, plane count, kernel support and type,
+precision and the visibility count rounded to a half decade - it times the
+gridding step (binning + tile accumulation + merge) on the caller's own
+data for every candidate (tile edge T, records per work item C) and keeps
+the fastest.
 Results are cached in a JSON file keyed by GPU architecture and shape
 class ($WSTACK_AUTOTUNE_CACHE, default ~/.cache/wstack/autotune.json).
-The kernel support itself is not tuned: it changes the result, so each K
-has its own compiled kernel and its own cache entries.
+The kernel support and type are not tuned: they change the result, so
+each (K, kernel type) has its own compiled kernel and its own cache
+entries.
+
+Not among the candidates, and why:
+* lanes per visibility: the gridder's lane mapping (one kernel row per
+  lane, floor(64 / K) records per group) is a compile-time structure per
+  K, chosen by measurement against one tap per lane (K^2 lanes per record:
+  1.19 -> 1.06 ms FP32, 2.04 -> 1.32 ms FP64 on 1e7 visibilities); it is
+  not a launch parameter;
+* plane batch: every plan keeps its whole plane stack resident (288 GB of
+  HBM holds the largest workloads here: 137 GB for 16384^2 x 32 FP64), so
+  all planes of a channel are gridded in one launch and transformed in one
+  launch; there is no plane batch to choose.
 """
 from __future__ import annotations
 
@@ -38,9 +51,10 @@ def _arch() -> str:
         return "unknown"
 
 
-def shape_key(nu, nv, nw, support, precision, m) -> str:
+def shape_key(nu, nv, nw, support, precision, m, kernel="gauss") -> str:
     bucket = 0 if m <= 0 else round(2 * math.log10(m)) / 2
-    return f"{_arch()}|{nu}x{nv}x{nw}|K{support}|{precision}|m1e{bucket:g}"
+    return (f"{_arch()}|{nu}x{nv}x{nw}|K{support}{kernel}|{precision}|"
+            f"m1e{bucket:g}")
 
 
 def _load() -> dict:
@@ -96,7 +110,8 @@ def tune(wl, uvw, vis, weight=None, precision: str = "fp32",
     uvw, vis, weight are the device tensors that will be gridded.
     """
     m = int(uvw.shape[0])
-    key = shape_key(wl.nu, wl.nv, wl.nw, wl.support, precision, m)
+    kernel = getattr(wl, "kernel", "gauss")
+    key = shape_key(wl.nu, wl.nv, wl.nw, wl.support, precision, m, kernel)
     if use_cache:
         hit = lookup(key)
         if hit is not None:
@@ -109,7 +124,8 @@ def tune(wl, uvw, vis, weight=None, precision: str = "fp32",
         for c in chunks:
             plan = WStackPlan(wl.nu, wl.nv, wl.nw, wl.fov_l, wl.fov_m,
                               wl.w_min, wl.w_max, wl.support, wl.sigma,
-                              precision, max_vis=max(1, m), tile=t, chunk=c)
+                              precision, max_vis=max(1, m), tile=t, chunk=c,
+                              kernel=kernel, beta=getattr(wl, "beta", 0.0))
             ms = time_grid(plan, uvw, vis, weight, reps)
             plan.close()
             del plan

@@ -339,10 +339,19 @@ ws_status zero_planes(ws_plan* pl) {
 // the per-tile work items.  Returns the grid size bound for the item kernel.
 // For gridding, `strips` (cleared first when clear_strips) gets a mark for
 // every column strip that holds a tile with records.
+VisSource flat_source(const double* uvw, const void* vis,
+                      const float* weight) {
+  VisSource s{};
+  s.uvw = uvw;
+  s.vis = vis;
+  s.weight = weight;
+  s.rows = 0;
+  return s;
+}
+
 template <typename R>
-ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
-                      const void* vis, const float* weight, int degrid,
-                      int64_t* n_dropped, uint32_t* max_items,
+ws_status bin_records(ws_plan* pl, int64_t m, const VisSource& src,
+                      int degrid, int64_t* n_dropped, uint32_t* max_items,
                       uint32_t* strips = nullptr, bool clear_strips = false,
                       void* vis_out = nullptr) {
   const Layout& L = pl->L;
@@ -365,7 +374,7 @@ ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
       launch_zero_u32(strips, (int64_t)g.nw * g.tiles_u, st);
   }));
   WS_TRY(launch(pl, "bin_count", [&] {
-    launch_bin_count(g, uvw, m, copies, nkeys, keyrank,
+    launch_bin_count(g, src, m, copies, nkeys, keyrank,
                      reinterpret_cast<unsigned long long*>(n_dropped), st);
   }));
   WS_TRY(launch(pl, "scan_keys", [&] {
@@ -374,7 +383,7 @@ ws_status bin_records(ws_plan* pl, int64_t m, const double* uvw,
     launch_copy_offsets(copies, nkeys, counts, st);
   }));
   WS_TRY(launch(pl, "bin_scatter", [&] {
-    launch_bin_scatter<R>(g, uvw, vis, weight, m, keyrank, copies, nkeys,
+    launch_bin_scatter<R>(g, src, m, keyrank, copies, nkeys,
                           pl->work + L.o_rec, degrid, vis_out, st);
   }));
   WS_TRY(launch(pl, "tile_work", [&] {
@@ -437,12 +446,11 @@ ws_status merge_impl(ws_plan* pl, int acc) {
 // With `lazy` (a first call whose stack only the fused imaging path will
 // read), tiles without records are not zeroed.
 template <typename R>
-ws_status grid_impl(ws_plan* pl, int64_t m, const double* uvw, const void* vis,
-                    const float* weight, int64_t* n_dropped,
-                    bool lazy = false) {
+ws_status grid_impl(ws_plan* pl, int64_t m, const VisSource& src,
+                    int64_t* n_dropped, bool lazy = false) {
   uint32_t max_items = 0;
   const int acc = pl->state == kGridded ? 1 : 0;
-  WS_TRY(bin_records<R>(pl, m, uvw, vis, weight, 0, n_dropped, &max_items,
+  WS_TRY(bin_records<R>(pl, m, src, 0, n_dropped, &max_items,
                         pl->w<uint32_t>(pl->L.o_strips), !acc));
   const GridJob<R> j = make_job<R>(pl, acc);
   if (!acc && !lazy) {
@@ -581,8 +589,8 @@ ws_status degrid_impl(ws_plan* pl, const void* image, int image_is_real,
   WS_TRY(cols_impl<R>(pl, -1, &g));
   if (m == 0) return WS_OK;
   uint32_t max_items = 0;
-  WS_TRY(bin_records<R>(pl, m, uvw, nullptr, weight, 1, nullptr, &max_items,
-                        nullptr, false, vis_out));
+  WS_TRY(bin_records<R>(pl, m, flat_source(uvw, nullptr, weight), 1,
+                        nullptr, &max_items, nullptr, false, vis_out));
   WS_TRY(launch(pl, "degrid_tiles", [&] {
     launch_degrid_tiles<R>(g, pl->w<uint32_t>(L.o_counts),
                            pl->w<uint32_t>(L.o_counters),
@@ -611,6 +619,62 @@ ws_status check_plan(ws_plan* pl) {
   if (pl == nullptr) return fail(WS_INVALID_ARG, "plan is NULL");
   if (hipSetDevice(pl->device) != hipSuccess)
     return fail(WS_HIP_ERROR, "hipSetDevice(%d) failed", pl->device);
+  return WS_OK;
+}
+
+// Gridding and imaging of an empty plan in one pass over the stack (the
+// one-call path); the plan is empty afterwards.
+ws_status grid_image_impl(ws_plan* pl, int64_t m, const VisSource& src,
+                          void* image, int64_t* n_dropped) {
+  const bool lazy = lazy_ok(pl);
+  const bool f64 = pl->p.precision == WS_FP64;
+  ws_status st = f64 ? grid_impl<double>(pl, m, src, n_dropped, lazy)
+                     : grid_impl<float>(pl, m, src, n_dropped, lazy);
+  if (st == WS_OK)
+    st = f64 ? image_impl<double>(pl, image, lazy)
+             : image_impl<float>(pl, image, lazy);
+  pl->state = kEmpty;
+  return st;
+}
+
+// Checks of a baseline-major call and its source (pol_coeff is a host
+// array of npol (re, im) pairs).
+ws_status rows_source(ws_plan* pl, int64_t nrows, int32_t nchan,
+                      int32_t npol, const double* uvw_m,
+                      const double* freq_hz, const void* vis,
+                      const float* weight, const double* pol_coeff,
+                      VisSource* out, int64_t* m) {
+  if (nrows < 0 || nchan < 1 || npol < 1 || npol > kMaxPol)
+    return fail(WS_INVALID_ARG, "nrows=%lld, nchan=%d, npol=%d: need nrows "
+                ">= 0, nchan >= 1, 1 <= npol <= %d", (long long)nrows, nchan,
+                npol, kMaxPol);
+  if (nrows > pl->max_vis / nchan)
+    return fail(WS_WORKSPACE_TOO_SMALL,
+                "nrows * nchan = %lld * %d exceeds max_vis=%lld",
+                (long long)nrows, nchan, (long long)pl->max_vis);
+  if (pol_coeff == nullptr) return fail(WS_INVALID_ARG, "pol_coeff is NULL");
+  for (int p = 0; p < 2 * npol; ++p)
+    if (!std::isfinite(pol_coeff[p]))
+      return fail(WS_INVALID_ARG, "pol_coeff must be finite");
+  *m = nrows * nchan;
+  if (*m > 0 && (uvw_m == nullptr || freq_hz == nullptr || vis == nullptr))
+    return fail(WS_INVALID_ARG, "uvw_m, freq_hz or vis is NULL");
+  if (!aligned(uvw_m, 8) || !aligned(freq_hz, 8) || !aligned(weight, 4) ||
+      !aligned(vis, pl->L.elem))
+    return fail(WS_INVALID_ARG, "misaligned uvw_m, freq_hz, vis or weight");
+  VisSource s{};
+  s.uvw = uvw_m;
+  s.vis = vis;
+  s.weight = weight;
+  s.rows = 1;
+  s.nchan = nchan;
+  s.npol = npol;
+  s.freq = freq_hz;
+  for (int p = 0; p < npol; ++p) {
+    s.coef[p][0] = pol_coeff[2 * p];
+    s.coef[p][1] = pol_coeff[2 * p + 1];
+  }
+  *out = s;
   return WS_OK;
 }
 
@@ -657,7 +721,9 @@ ws_status batch_image_impl(ws_batch* b, const int64_t* m,
     pl->stream = b->stream;
     pl->state = kEmpty;
     uint32_t mi = 0;
-    WS_TRY(bin_records<R>(pl, m[i], uvw[i], vis[i], weight ? weight[i] : nullptr,
+    WS_TRY(bin_records<R>(pl, m[i],
+                          flat_source(uvw[i], vis[i],
+                                      weight ? weight[i] : nullptr),
                           0, nullptr, &mi, pl->w<uint32_t>(pl->L.o_strips),
                           true));
     items += mi;
@@ -864,9 +930,10 @@ ws_status ws_grid_visibilities(ws_plan* plan, int64_t m, const double* uvw,
   if (plan->state == kTransformed)
     return fail(WS_BAD_STATE,
                 "the stack holds transforms; call ws_plan_reset first");
+  const VisSource src = flat_source(uvw, vis, weight);
   if (plan->p.precision == WS_FP64)
-    return grid_impl<double>(plan, m, uvw, vis, weight, n_dropped_taps);
-  return grid_impl<float>(plan, m, uvw, vis, weight, n_dropped_taps);
+    return grid_impl<double>(plan, m, src, n_dropped_taps);
+  return grid_impl<float>(plan, m, src, n_dropped_taps);
 }
 
 ws_status ws_fft_planes(ws_plan* plan, int32_t direction) {
@@ -933,17 +1000,47 @@ ws_status ws_grid_image(ws_plan* plan, int64_t m, const double* uvw,
   if (plan->state != kEmpty)
     return fail(WS_BAD_STATE,
                 "the stack is not empty; call ws_plan_reset first");
-  const bool lazy = lazy_ok(plan);
-  const bool f64 = plan->p.precision == WS_FP64;
-  ws_status st = f64 ? grid_impl<double>(plan, m, uvw, vis, weight,
-                                         n_dropped_taps, lazy)
-                     : grid_impl<float>(plan, m, uvw, vis, weight,
-                                        n_dropped_taps, lazy);
-  if (st == WS_OK)
-    st = f64 ? image_impl<double>(plan, image, lazy)
-             : image_impl<float>(plan, image, lazy);
-  plan->state = kEmpty;
-  return st;
+  return grid_image_impl(plan, m, flat_source(uvw, vis, weight), image,
+                         n_dropped_taps);
+}
+
+ws_status ws_grid_rows(ws_plan* plan, int64_t nrows, int32_t nchan,
+                       int32_t npol, const double* uvw_m,
+                       const double* freq_hz, const void* vis,
+                       const float* weight, const double* pol_coeff,
+                       int64_t* n_dropped_taps) {
+  WS_TRY(check_plan(plan));
+  VisSource src;
+  int64_t m = 0;
+  WS_TRY(rows_source(plan, nrows, nchan, npol, uvw_m, freq_hz, vis, weight,
+                     pol_coeff, &src, &m));
+  if (!aligned(n_dropped_taps, 8))
+    return fail(WS_INVALID_ARG, "misaligned n_dropped_taps");
+  if (plan->state == kTransformed)
+    return fail(WS_BAD_STATE,
+                "the stack holds transforms; call ws_plan_reset first");
+  if (plan->p.precision == WS_FP64)
+    return grid_impl<double>(plan, m, src, n_dropped_taps);
+  return grid_impl<float>(plan, m, src, n_dropped_taps);
+}
+
+ws_status ws_grid_image_rows(ws_plan* plan, int64_t nrows, int32_t nchan,
+                             int32_t npol, const double* uvw_m,
+                             const double* freq_hz, const void* vis,
+                             const float* weight, const double* pol_coeff,
+                             void* image, int64_t* n_dropped_taps) {
+  WS_TRY(check_plan(plan));
+  VisSource src;
+  int64_t m = 0;
+  WS_TRY(rows_source(plan, nrows, nchan, npol, uvw_m, freq_hz, vis, weight,
+                     pol_coeff, &src, &m));
+  if (image == nullptr) return fail(WS_INVALID_ARG, "image is NULL");
+  if (!aligned(image, plan->L.elem) || !aligned(n_dropped_taps, 8))
+    return fail(WS_INVALID_ARG, "misaligned image or n_dropped_taps");
+  if (plan->state != kEmpty)
+    return fail(WS_BAD_STATE,
+                "the stack is not empty; call ws_plan_reset first");
+  return grid_image_impl(plan, m, src, image, n_dropped_taps);
 }
 
 ws_status ws_degrid(ws_plan* plan, const void* image, int32_t image_is_real,
@@ -997,16 +1094,8 @@ ws_status ws_grid_image_noalloc(const ws_params* params, int64_t m,
   if (!aligned(vis, L.elem) || !aligned(image, L.elem) ||
       !aligned(n_dropped_taps, 8))
     return fail(WS_INVALID_ARG, "misaligned vis, image or n_dropped_taps");
-  const bool lazy = lazy_ok(&pl);
-  const bool f64 = params->precision == WS_FP64;
-  ws_status st = f64 ? grid_impl<double>(&pl, m, uvw, vis, weight,
-                                         n_dropped_taps, lazy)
-                     : grid_impl<float>(&pl, m, uvw, vis, weight,
-                                        n_dropped_taps, lazy);
-  if (st == WS_OK)
-    st = f64 ? image_impl<double>(&pl, image, lazy)
-             : image_impl<float>(&pl, image, lazy);
-  return st;
+  return grid_image_impl(&pl, m, flat_source(uvw, vis, weight), image,
+                         n_dropped_taps);
 }
 
 ws_status ws_plan_reset(ws_plan* plan) {

@@ -27,8 +27,63 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t key) {
   return (key * 2654435761u) >> (32 - 13);  // 13 = log2(kHashSize)
 }
 
+// Speed of light (m/s): baseline-major uvw in metres becomes wavelengths
+// at frequency f by the factor f / c0.
+constexpr double kSpeedOfLight = 299792458.0;
+
+// Baseline coordinates of visibility i in wavelengths.  Baseline-major:
+// the scale f / c0 is one FP64 division, then one product per coordinate
+// (contraction off, so the position rounds as the separate operations).
+__device__ __forceinline__ void source_uvw(const VisSource& s, int64_t i,
+                                           double& u, double& v, double& w) {
+#pragma clang fp contract(off)
+  if (s.rows) {
+    const int64_t r = i / s.nchan;
+    const int c = (int)(i - r * s.nchan);
+    const double sc = s.freq[c] / kSpeedOfLight;
+    u = s.uvw[3 * r] * sc;
+    v = s.uvw[3 * r + 1] * sc;
+    w = s.uvw[3 * r + 2] * sc;
+  } else {
+    u = s.uvw[3 * i];
+    v = s.uvw[3 * i + 1];
+    w = s.uvw[3 * i + 2];
+  }
+}
+
+// Weighted value of visibility i (gridding).  Baseline-major: the
+// correlations of row r, channel c combined in FP64 with the coefficients
+// and the per-correlation weights, then rounded to the path precision.
+template <typename R>
+__device__ __forceinline__ cplx<R> source_value(const VisSource& s,
+                                                int64_t i) {
+  if (s.rows) {
+    const int64_t r = i / s.nchan;
+    const cplx<R>* v = static_cast<const cplx<R>*>(s.vis) + i * s.npol;
+    double re = 0.0, im = 0.0;
+    for (int p = 0; p < s.npol; ++p) {
+      const double wt = s.weight != nullptr
+                            ? (double)s.weight[r * s.npol + p] : 1.0;
+      const double ar = s.coef[p][0] * wt, ai = s.coef[p][1] * wt;
+      const cplx<R> x = v[p];
+      re += ar * (double)x.re - ai * (double)x.im;
+      im += ar * (double)x.im + ai * (double)x.re;
+    }
+    return {(R)re, (R)im};
+  }
+  const R wt = s.weight != nullptr ? (R)s.weight[i] : (R)1;
+  const cplx<R> vv = static_cast<const cplx<R>*>(s.vis)[i];
+  return {wt * vv.re, wt * vv.im};
+}
+
+// Weight of visibility i (degridding reads flat sources only).
+__device__ __forceinline__ float source_weight(const VisSource& s,
+                                               int64_t i) {
+  return s.weight != nullptr ? s.weight[i] : 1.0f;
+}
+
 __global__ __launch_bounds__(kCountThreads) void k_bin_count(
-    Geo g, const double* __restrict__ uvw, int64_t m,
+    Geo g, VisSource src, int64_t m,
     uint32_t* __restrict__ copies, uint32_t nkeys,
     uint2* __restrict__ keyrank, unsigned long long* __restrict__ dropped) {
   uint32_t* __restrict__ counts =
@@ -56,9 +111,7 @@ __global__ __launch_bounds__(kCountThreads) void k_bin_count(
   for (int e = 0; e < kCountPerThread; ++e) {
     int64_t gi = base + e * kCountThreads + tid;
     gi = gi < m ? gi : m - 1;
-    cu[e] = uvw[3 * gi];
-    cv[e] = uvw[3 * gi + 1];
-    cw[e] = uvw[3 * gi + 2];
+    source_uvw(src, gi, cu[e], cv[e], cw[e]);
   }
 #pragma unroll
   for (int e = 0; e < kCountPerThread; ++e) {
@@ -244,8 +297,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_bin_scatter(
-    Geo g, const double* __restrict__ uvw, const cplx<R>* __restrict__ vis,
-    const float* __restrict__ weight, int64_t m,
+    Geo g, VisSource src, int64_t m,
     const uint2* __restrict__ keyrank, const uint32_t* __restrict__ offsets,
     uint32_t nkeys, Record<R>* __restrict__ rec, int degrid,
     cplx<R>* __restrict__ vis_out) {
@@ -258,9 +310,10 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
     if (degrid) vis_out[gi] = cplx<R>{(R)0, (R)0};
     return;
   }
-  double x, y;
+  double x, y, u, v, w;
   int i0, j0, k;
-  place(g, uvw[3 * gi], uvw[3 * gi + 1], uvw[3 * gi + 2], x, y, i0, j0, k);
+  source_uvw(src, gi, u, v, w);
+  place(g, u, v, w, x, y, i0, j0, k);
   // The copy the counting workgroup of this visibility added into.
   const int64_t copy = (gi / kCountPerBlock) % kCountCopies;
   const uint32_t pos = offsets[copy * nkeys + kr.x] + kr.y;
@@ -268,13 +321,12 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
   // Fractional offsets from the nearest cell, subtracted in FP64 first.
   r.dx = (R)(x - (double)i0);
   r.dy = (R)(y - (double)j0);
-  const R wt = weight != nullptr ? (R)weight[gi] : (R)1;
   if (!degrid) {
-    const cplx<R> vv = vis[gi];
-    r.vr = wt * vv.re;
-    r.vi = wt * vv.im;
+    const cplx<R> vv = source_value<R>(src, gi);
+    r.vr = vv.re;
+    r.vi = vv.im;
   } else {
-    r.vr = wt;
+    r.vr = (R)source_weight(src, gi);
     r.vi = (R)0;
   }
   r.cell = pack_cell(i0, j0);
@@ -370,13 +422,13 @@ __global__ __launch_bounds__(256) void k_tile_work(
 
 }  // namespace
 
-void launch_bin_count(const Geo& g, const double* uvw, int64_t m,
+void launch_bin_count(const Geo& g, const VisSource& src, int64_t m,
                       uint32_t* copies, uint32_t nkeys, uint2* keyrank,
                       unsigned long long* dropped, hipStream_t st) {
   if (m == 0) return;
   const int64_t nb = (m + kCountPerBlock - 1) / kCountPerBlock;
   hipLaunchKernelGGL(k_bin_count, dim3((unsigned)nb), dim3(kCountThreads), 0,
-                     st, g, uvw, m, copies, nkeys, keyrank, dropped);
+                     st, g, src, m, copies, nkeys, keyrank, dropped);
 }
 
 void launch_fold_copies(const uint32_t* copies, uint32_t nkeys,
@@ -405,27 +457,25 @@ void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
 }
 
 template <typename R>
-void launch_bin_scatter(const Geo& g, const double* uvw, const void* vis,
-                        const float* weight, int64_t m, const uint2* keyrank,
-                        const uint32_t* offsets, uint32_t nkeys,
-                        void* records, int degrid, void* vis_out,
-                        hipStream_t st) {
+void launch_bin_scatter(const Geo& g, const VisSource& src, int64_t m,
+                        const uint2* keyrank, const uint32_t* offsets,
+                        uint32_t nkeys, void* records, int degrid,
+                        void* vis_out, hipStream_t st) {
   if (m == 0) return;
   const int64_t nb = (m + 255) / 256;
   hipLaunchKernelGGL(k_bin_scatter<R>, dim3((unsigned)nb), dim3(256), 0, st, g,
-                     uvw, (const cplx<R>*)vis, weight, m, keyrank, offsets,
-                     nkeys, (Record<R>*)records, degrid, (cplx<R>*)vis_out);
+                     src, m, keyrank, offsets, nkeys, (Record<R>*)records,
+                     degrid, (cplx<R>*)vis_out);
 }
 
-template void launch_bin_scatter<float>(const Geo&, const double*, const void*,
-                                        const float*, int64_t, const uint2*,
-                                        const uint32_t*, uint32_t, void*, int,
-                                        void*, hipStream_t);
-template void launch_bin_scatter<double>(const Geo&, const double*,
-                                         const void*, const float*, int64_t,
-                                         const uint2*, const uint32_t*,
-                                         uint32_t, void*, int, void*,
-                                         hipStream_t);
+template void launch_bin_scatter<float>(const Geo&, const VisSource&, int64_t,
+                                        const uint2*, const uint32_t*,
+                                        uint32_t, void*, int, void*,
+                                        hipStream_t);
+template void launch_bin_scatter<double>(const Geo&, const VisSource&,
+                                         int64_t, const uint2*,
+                                         const uint32_t*, uint32_t, void*,
+                                         int, void*, hipStream_t);
 
 void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t chunk, uint32_t* tile_chunks,

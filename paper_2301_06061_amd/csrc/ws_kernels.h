@@ -11,11 +11,31 @@
 
 namespace ws {
 
+// Where the binning kernels read visibility i (0 <= i < m) from.
+//   rows == 0 (flat): uvw[i] in wavelengths, vis[i], weight[i] (or unit);
+//     the gridded value is weight[i] vis[i].
+//   rows == 1 (baseline-major, Sec. 2 data structures / Sec. 3.4.2 thread
+//     loop): visibility i = r * nchan + c of row r (one baseline at one
+//     time) and channel c; uvw[r] in metres, scaled by f_c / c0 to
+//     wavelengths; vis[r][c][p] over npol correlations, weight[r][p] (or
+//     unit); the gridded value is sum_p coef_p weight[r][p] vis[r][c][p]
+//     (formed in FP64), e.g. a Stokes parameter from the correlations.
+constexpr int kMaxPol = 4;
+struct VisSource {
+  const double* uvw;
+  const void* vis;
+  const float* weight;
+  int rows;
+  int nchan, npol;
+  const double* freq;          // [nchan] Hz (rows only)
+  double coef[kMaxPol][2];     // (re, im) per correlation (rows only)
+};
+
 // binning (bin.hip)
 // Counts go to kCountCopies copies of nkeys words each (zeroed by the
 // caller); fold them into totals, scan the totals, then turn the copies
 // into per-copy offsets, which the scatter reads.
-void launch_bin_count(const Geo& g, const double* uvw, int64_t m,
+void launch_bin_count(const Geo& g, const VisSource& src, int64_t m,
                       uint32_t* copies, uint32_t nkeys, uint2* keyrank,
                       unsigned long long* dropped, hipStream_t st);
 void launch_fold_copies(const uint32_t* copies, uint32_t nkeys,
@@ -26,11 +46,10 @@ int64_t scan_sums_len(int64_t n);
 void launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
                            uint32_t* sums, hipStream_t st);
 template <typename R>
-void launch_bin_scatter(const Geo& g, const double* uvw, const void* vis,
-                        const float* weight, int64_t m, const uint2* keyrank,
-                        const uint32_t* offsets, uint32_t nkeys,
-                        void* records, int degrid, void* vis_out,
-                        hipStream_t st);
+void launch_bin_scatter(const Geo& g, const VisSource& src, int64_t m,
+                        const uint2* keyrank, const uint32_t* offsets,
+                        uint32_t nkeys, void* records, int degrid,
+                        void* vis_out, hipStream_t st);
 void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t chunk, uint32_t* tile_chunks,
                       uint32_t* tile_slot, uint32_t* counters,

@@ -16,5 +16,7 @@ from .workloads import (  # noqa: F401
     random_case,
     hermitian_pairs,
     edge_case,
+    rows_case,
+    RowsWorkload,
     CONFIGS,
 )

@@ -312,3 +312,55 @@ def edge_case(seed: int, n: int = 128, nv: int = None, nw: int = 4,
     return Workload(n, nv, nw, fov_l, fov_m, w_min, w_max, support, 0.0,
                     precision, np.ascontiguousarray(uvw), vis, wt,
                     name=f"edge{seed}")
+
+
+@dataclass
+class RowsWorkload:
+    """Baseline-major data (one row per baseline and time): uvw in metres
+    per row, channel frequencies, visibilities per (row, channel,
+    correlation), weights per (row, correlation).  ``geo`` is a Workload
+    holding the grid geometry (its uvw/vis are None)."""
+
+    geo: Workload
+    uvw_m: np.ndarray      # float64 [R, 3]
+    freq_hz: np.ndarray    # float64 [C]
+    vis: np.ndarray        # complex64 / complex128 [R, C, P]
+    weight: np.ndarray     # float32 [R, P]
+
+
+C0 = 299_792_458.0  # m/s
+
+
+def rows_case(seed: int, n: int = 128, nw: int = 4, support: int = 7,
+              nrows: int = 500, nchan: int = 8, npol: int = 4,
+              f_lo: float = 100e6, f_hi: float = 200e6, fov_deg: float = 2.0,
+              precision: int = 1, law: str = "core") -> RowsWorkload:
+    """Seeded baseline-major case: rows drawn like ``random_case`` in cells
+    at the highest channel frequency (so every channel's footprint stays on
+    the grid), converted to metres; channels spaced evenly in [f_lo, f_hi];
+    CN(0, 1) correlations; U[0.5, 1.5] weights.  The plane range covers the
+    w of every channel."""
+    fov = math.radians(fov_deg)
+    du = 1.0 / fov
+    rng = np.random.default_rng(seed)
+    half = n / 2 - _margin(support)
+    if law == "gauss":
+        uc, vc = _gauss_disk(rng, nrows, 0.25 * n / 2, half)
+        wmax = (n / 2) * du
+        w = rng.uniform(-wmax, wmax, nrows)
+    else:
+        uc, vc, r = _dense_core(rng, nrows, half)
+        wmax = (n / 2) * du
+        w = wmax * r / max(half, 1e-9) + rng.standard_normal(nrows) * 0.1 * wmax
+    freq = np.linspace(f_lo, f_hi, nchan) if nchan > 1 else np.array([f_hi])
+    to_m = C0 / freq.max()
+    uvw_m = np.stack([uc * du, vc * du, w], axis=1) * to_m
+    cdt = np.complex128 if precision == 1 else np.complex64
+    vis = _cn01(rng, nrows * nchan * npol, cdt).reshape(nrows, nchan, npol)
+    wt = rng.uniform(0.5, 1.5, (nrows, npol)).astype(np.float32)
+    w_lambda = uvw_m[:, 2][:, None] * (freq[None, :] / C0)
+    lo, hi = ((float(w_lambda.min()), float(w_lambda.max()))
+              if nrows > 0 and nw > 1 else (-1.0, 1.0))
+    geo = Workload(n, n, nw, fov, fov, lo, hi, support, 0.0, precision,
+                   name=f"rows{seed}")
+    return RowsWorkload(geo, uvw_m, freq, vis, wt)
