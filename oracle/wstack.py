@@ -510,3 +510,100 @@ def expand_rows(uvw_m, freq_hz, vis, weight, pol_coeff):
     for p in range(npol):
         comb += (coeff[p] * w[:, p])[:, None] * vis[:, :, p]
     return uvw, comb.reshape(nr * nc), None
+
+
+# ---------------------------------------------------------------------------
+# Imaging major cycle (Sec. 1: imaging is followed by deconvolution with the
+# CLEAN algorithm and its variants - Hogbom's image-plane loop, and the
+# major / minor cycle split of Clark and of Schwab, in which the model is
+# subtracted from the visibilities, not from the image, between minor
+# cycles).
+#
+# Readings (the paper cites these methods but does not restate them):
+# * the measurement operator predicts model visibilities with unit weights
+#   (degrid(model) with weight None); the weights enter when the residual
+#   visibilities are imaged (natural weighting, as for the dirty image);
+# * images are real: the real part of the w-stacked image (the input is
+#   taken to be Hermitian, so the imaginary part is rounding);
+# * dirty beam: b = Re(image of unit visibilities), normalised by its value
+#   at the centre pixel (N_v/2, N_u/2), beta; residual images are divided by
+#   the same beta, so that a point source of flux S shows a peak of ~S;
+# * minor cycle (Hogbom): the pixel of largest |D| (the first in row-major
+#   order on ties) gets gain * D there added to the model, and gain * D
+#   times b centred on that pixel (b[q - q* + N_v/2][p - p* + N_u/2], where
+#   that index lies on the grid; the rest of the beam is truncated) is
+#   subtracted from D; the cycle stops after niter components or when the
+#   peak falls below the threshold;
+# * major cycle: residual visibilities R = V - degrid(model), residual
+#   image D = Re(image(R, weights)) / beta, then a minor cycle, n_major
+#   times; the returned residual image is that of the final model.
+# ---------------------------------------------------------------------------
+
+def dirty_beam(p: Params, uvw, weight=None):
+    """(b, beta): the normalised dirty beam and its centre value."""
+    ones = np.ones(np.asarray(uvw).shape[0], dtype=np.complex128)
+    img = image(p, uvw, ones, weight).real
+    beta = float(img[p.nv // 2, p.nu // 2])
+    return img / beta, beta
+
+
+def hogbom(residual, beam, niter, gain, threshold=0.0, picks=None):
+    """Hogbom minor cycle on a real residual image (modified copy returned).
+
+    Returns (model, residual, components): ``components`` lists
+    (q, p, value) for each step, the value being the residual at the pixel
+    before the step.  With ``picks`` (a list of (q, p)), those pixels are
+    taken in turn instead of the argmax (to replay a sequence chosen in
+    another precision); the argmax is still what a free run would take.
+    """
+    d = np.array(residual, dtype=np.float64, copy=True)
+    b = np.asarray(beam, dtype=np.float64)
+    nv, nu = d.shape
+    model = np.zeros_like(d)
+    comps = []
+    steps = niter if picks is None else min(niter, len(picks))
+    for t in range(steps):
+        if picks is None:
+            flat = int(np.argmax(np.abs(d)))
+            q, pp = divmod(flat, nu)
+        else:
+            q, pp = picks[t]
+        a = float(d[q, pp])
+        if abs(a) < threshold:
+            break
+        comps.append((q, pp, a))
+        model[q, pp] += gain * a
+        # beam centred on (q, pp), truncated at the grid edges
+        q0, q1 = max(0, q - nv // 2), min(nv, q + nv // 2)
+        p0, p1 = max(0, pp - nu // 2), min(nu, pp + nu // 2)
+        d[q0:q1, p0:p1] -= gain * a * b[q0 - q + nv // 2:q1 - q + nv // 2,
+                                        p0 - pp + nu // 2:p1 - pp + nu // 2]
+    return model, d, comps
+
+
+def residual_image(p: Params, uvw, vis, weight, model, beta):
+    """Re(image(V - degrid(model), weights)) / beta."""
+    pred = degrid(p, model, uvw, None)
+    r = np.asarray(vis).astype(np.complex128) - pred
+    return image(p, uvw, r, weight).real / beta
+
+
+def major_cycle(p: Params, uvw, vis, weight, n_major, n_minor, gain,
+                threshold=0.0, picks=None):
+    """Cotton-Schwab major cycles with Hogbom minor cycles.
+
+    Returns (model, residual image of the final model, components per
+    major cycle, beam, beta).  ``picks``: per major cycle, a forced pixel
+    sequence (see ``hogbom``).
+    """
+    b, beta = dirty_beam(p, uvw, weight)
+    model = np.zeros((p.nv, p.nu))
+    history = []
+    for j in range(n_major):
+        d = residual_image(p, uvw, vis, weight, model, beta)
+        dm, _, comps = hogbom(d, b, n_minor, gain, threshold,
+                              None if picks is None else picks[j])
+        model = model + dm
+        history.append(comps)
+    return model, residual_image(p, uvw, vis, weight, model, beta), \
+        history, b, beta
