@@ -10,9 +10,11 @@ FP32 path; the FP64 path is timed on the same inputs for comparison.
 Further legs (on by default, each skippable): the large single image
 (1e8 visibilities, 16384^2 x 32, K = 9, FP32 and FP64), 64 batched channels
 (autotuned, replayed from a HIP graph), the differentiable operator
-(degrid forward + grid backward, 1e7 visibilities, 4096^2 x 32), and the
-headline step with its host-to-device input copies (pinned memory) and the
-image copy back inside the timing.
+(degrid forward + grid backward, 1e7 visibilities, 4096^2 x 32), the
+headline grid fed baseline-major rows (8 channels x 4 correlations ->
+Stokes I), an imaging major cycle on the config-5 sky, and the headline
+step with its host-to-device input copies (pinned memory) and the image
+copy back inside the timing.
 
 Prints one JSON line (the last line on stdout).  value = visibilities imaged
 per second (Mvis/s) over the timed steps of the headline workload.
@@ -388,6 +390,104 @@ def bench_batch(args, torch, ws, synth):
             "autotune_s": tune_s, "tuned_tile_chunk": choice}
 
 
+def bench_rows(args, torch, ws, synth):
+    """Baseline-major input: the headline grid and field as m / 8 rows
+    (baseline, time) x 8 channels (100-200 MHz) x 4 correlations combined
+    into Stokes I, through ws_grid_image_rows (FP32)."""
+    dev = torch.device("cuda", 0)
+    nrows = args.m // 8
+    t = time.perf_counter()
+    rw = synth.rows_case(0, n=4096, nw=32, support=7, nrows=nrows, nchan=8,
+                         npol=4, fov_deg=5.0, precision=0, law="core")
+    log(f"rows: {nrows} x 8 x 4 drawn in {time.perf_counter() - t:.1f} s")
+    plan = ws.WStackPlan.from_workload(rw.geo, max_vis=nrows * 8)
+    du = torch.from_numpy(rw.uvw_m).to(dev)
+    df = torch.from_numpy(rw.freq_hz).to(dev)
+    dv = torch.from_numpy(rw.vis).to(dev)
+    dw = torch.from_numpy(rw.weight).to(dev)
+    img = plan.new_image()
+    coef = [0.5, 0.0, 0.0, 0.5]  # Stokes I from linear feeds: (XX + YY) / 2
+
+    def step():
+        plan.reset()
+        img.zero_()
+        plan.grid_image_rows(du, df, dv, dw, coef, image=img)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 10))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    m = nrows * 8
+    log(f"rows (baseline-major) fp32: {sec * 1e3:.3f} ms/step")
+    in_bytes = int(rw.uvw_m.nbytes + rw.freq_hz.nbytes + rw.vis.nbytes +
+                   rw.weight.nbytes)
+    del plan, du, df, dv, dw, img
+    torch.cuda.empty_cache()
+    return {"workload": "4096^2 x 32 w-planes, K=7 Gaussian, 5 deg: "
+                        f"{nrows} rows x 8 channels x 4 correlations -> "
+                        "Stokes I, dense core",
+            "visibilities": m, "ms_per_step": sec * 1e3,
+            "mvis_per_s": m / sec / 1e6,
+            "input_bytes_per_vis": in_bytes / m}
+
+
+def bench_clean(args, torch, ws, synth):
+    """Imaging major cycle on the config-5 workload: the 1000-source sky's
+    visibilities (predicted by the degridder), dirty beam, then major
+    cycles of (residual image, Hogbom minor cycle), FP32."""
+    from paper_2301_06061_amd.clean import MajorCycle
+    dev = torch.device("cuda", 0)
+    wl, x = synth.config5(m=args.m)
+    plan = ws.WStackPlan.from_workload(wl)
+    uvw = torch.from_numpy(wl.uvw).to(dev)
+    wt = torch.from_numpy(wl.weight).to(dev)
+    vis = plan.degrid(torch.from_numpy(x).to(dev), uvw, None)
+    n_major, n_minor, gain = 2, 200, 0.1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mc = MajorCycle(plan, uvw, vis, wt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.set_profiling(True)
+    plan.kernel_times(reset=True)
+    mc.run(n_major, n_minor, gain)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    kt = plan.kernel_times(reset=True)
+    plan.set_profiling(False)
+    minor_ms = kt.get("clean_minor", (0.0, 1))[0] / n_major
+    npix = wl.nu * wl.nv
+    step_bytes = 3 * npix * 4  # read residual and beam, write residual
+    per_it = minor_ms / n_minor
+    found = int((mc.model.abs() > 0).sum().item())
+    log(f"clean: beam {1e3 * (t1 - t0):.1f} ms, {n_major} major cycles "
+        f"{1e3 * (t2 - t1):.1f} ms, minor {per_it * 1e3:.1f} us/iteration")
+    out = {"workload": "config-5 sky (1000 sources, 4096^2, 32 w-planes, "
+                       "K=7), 1e7 visibilities predicted by the degridder",
+           "beam_ms": 1e3 * (t1 - t0),
+           "major_cycles": n_major, "minor_per_cycle": n_minor,
+           "gain": gain,
+           "ms_total": 1e3 * (t2 - t1),
+           "ms_per_major_cycle": 1e3 * (t2 - t1) / n_major,
+           "minor_cycle_ms": minor_ms,
+           "minor_iteration_us": per_it * 1e3,
+           "minor_step_roofline": {
+               "bound": "hbm", "bytes_per_iteration": step_bytes,
+               "achieved": step_bytes / (per_it / 1e3) / 1e9,
+               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": step_bytes / (per_it / 1e3) / 1e9 / HBM_PEAK_GBS},
+           "model_pixels": found,
+           "kernels": {k: v[0] / max(v[1], 1) for k, v in kt.items()}}
+    del mc, plan, uvw, wt, vis
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_with_copies(args, torch, plan, wl, img):
     """The headline FP32 step with its input copies from pinned host memory
     (uvw, vis, weight) and the image copy back inside the timing, as the
@@ -443,6 +543,10 @@ def main(argv=None):
                     help="skip the differentiable operator")
     ap.add_argument("--no-copies", action="store_true",
                     help="skip the copy-inclusive headline step")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the baseline-major input leg")
+    ap.add_argument("--no-clean", action="store_true",
+                    help="skip the imaging major cycle leg")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline workload (no further legs, no "
                          "CPU baseline)")
@@ -459,6 +563,7 @@ def main(argv=None):
     if args.headline_only:
         args.no_cpu_baseline = args.no_large = args.no_batch = True
         args.no_degrid = args.no_copies = True
+        args.no_rows = args.no_clean = True
 
     import synth
     t = time.perf_counter()
@@ -547,6 +652,10 @@ def main(argv=None):
     torch.cuda.empty_cache()
     if not args.no_degrid:
         extra["degrid_config5"] = bench_degrid(args, torch, ws, synth)
+    if not args.no_rows:
+        extra["rows_config2"] = bench_rows(args, torch, ws, synth)
+    if not args.no_clean:
+        extra["clean_config5"] = bench_clean(args, torch, ws, synth)
     if not args.no_batch:
         extra["batch_config4"] = bench_batch(args, torch, ws, synth)
     if not args.no_large:

@@ -252,6 +252,55 @@ ws_status ws_degrid(ws_plan* plan, const void* image, int32_t image_is_real,
                     int64_t m, const double* uvw, const float* weight,
                     void* vis_out);
 
+/* ---- imaging major cycle --------------------------------------------------
+ * Deconvolution follows imaging in the processing chain of Sec. 1: CLEAN
+ * (Hogbom's image-plane loop) inside the major / minor cycle split of Clark
+ * and Schwab, where the model is subtracted from the visibilities between
+ * minor cycles.  These calls run one such cycle on the plan's kernels;
+ * images here are REAL (float32 on the FP32 path, float64 on the FP64
+ * path), [nv][nu]; the visibilities should be Hermitian-paired so that the
+ * images they give are real (the imaginary parts are dropped).  A caller
+ * loops: ws_dirty_beam once, then per major cycle ws_residual_image and
+ * ws_clean_minor (the Python driver is paper_2301_06061_amd.clean). */
+
+/* Dirty beam: beam = Re(I(1)) / beta, I(1) the image (ws_grid_image) of unit
+ * visibilities with the given weights, beta its value at the centre pixel
+ * (nv/2, nu/2), written to the device double *beta.  image_scratch: device
+ * complex [nv][nu] of the plan precision, overwritten.  The plan must be
+ * empty and is empty afterwards. */
+ws_status ws_dirty_beam(ws_plan* plan, int64_t m, const double* uvw,
+                        const float* weight, void* image_scratch, void* beam,
+                        double* beta);
+
+/* Residual image of a model: residual = Re(I(V - A model)) / beta, with A
+ * model = ws_degrid(model, unit weights) (the prediction of the sky model's
+ * visibilities) and I the image with the given weights (ws_grid_image).
+ * model: device real [nv][nu]; beta: device double (from ws_dirty_beam);
+ * vis_scratch: device complex [m] (receives V - A model); image_scratch:
+ * device complex [nv][nu]; residual: device real [nv][nu], overwritten.
+ * The plan is empty afterwards. */
+ws_status ws_residual_image(ws_plan* plan, int64_t m, const double* uvw,
+                            const void* vis, const float* weight,
+                            const void* model, const double* beta,
+                            void* vis_scratch, void* image_scratch,
+                            void* residual);
+
+/* Hogbom minor cycle on device real images: up to niter steps, each taking
+ * the pixel of largest |residual| (the lowest index q * nu + p on ties;
+ * non-finite pixels are never taken), stopping before a peak below
+ * threshold; a step adds gain * peak to model at that pixel and subtracts
+ * gain * peak times the beam centred there (beam[q - q* + nv/2][p - p* +
+ * nu/2] where that index lies on the grid) from the residual.  beam is
+ * normalised (1 at its centre); residual and model are updated in place.
+ * picks: device int32 [niter] receiving the pixel index of each step, or
+ * NULL; n_done: device int32 receiving the number of steps, or NULL.
+ * 0 < gain <= 1, threshold >= 0.  All decisions stay on the device (no
+ * host synchronisation inside the cycle); the state lives in the plan's
+ * workspace, so the plan's other calls must not run concurrently. */
+ws_status ws_clean_minor(ws_plan* plan, void* residual, const void* beam,
+                         void* model, int32_t niter, double gain,
+                         double threshold, int32_t* picks, int32_t* n_done);
+
 /* ---- allocation-free imaging ---------------------------------------------
  * For callers that cannot allocate device memory at all: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The

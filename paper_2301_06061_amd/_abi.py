@@ -63,6 +63,11 @@ _SIGS = {
                                  _P, _P, _P, _P, _P]),
     "ws_grid_image_rows": (C.c_int32, [_P, C.c_int64, C.c_int32, C.c_int32,
                                        _P, _P, _P, _P, _P, _P, _P]),
+    "ws_dirty_beam": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P, _P]),
+    "ws_residual_image": (C.c_int32, [_P, C.c_int64, _P, _P, _P, _P, _P, _P,
+                                      _P, _P]),
+    "ws_clean_minor": (C.c_int32, [_P, _P, _P, _P, C.c_int32, C.c_double,
+                                   C.c_double, _P, _P]),
     "ws_degrid": (C.c_int32, [_P, _P, C.c_int32, C.c_int64, _P, _P, _P]),
     "ws_grid_image_noalloc": (C.c_int32, [C.POINTER(Params), C.c_int64, _P,
                                           _P, _P, _P, _P, _P]),

@@ -22,7 +22,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwstack.so")
 ARCH = "gfx950"
 
-SOURCES = ["abi.cpp", "bin.hip", "grid.hip", "fft.hip"]
+SOURCES = ["abi.cpp", "bin.hip", "grid.hip", "fft.hip", "clean.hip"]
 
 
 def hipcc() -> str:

@@ -61,7 +61,7 @@ struct Layout {
   // workspace offsets
   size_t o_tw_u, o_tw_v, o_corr, o_counts, o_sums, o_keyrank, o_rec, o_chunks,
       o_slot, o_counters, o_split, o_extra, o_busy, o_idle, o_copies, o_desc,
-      o_strips, o_partials, o_scratch, total;
+      o_strips, o_partials, o_scratch, o_clean, total;
 };
 
 ws_status check_params(const ws_params* p) {
@@ -212,6 +212,8 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   // when columns use the four-step transform.
   L->o_scratch = take(p->nv > kOnePassCols
                           ? (size_t)p->nu * p->nv * L->elem : (size_t)0);
+  // Minor-cycle state and its per-block argmax slots.
+  L->o_clean = take(sizeof(CleanState) + kCleanMaxSlots * sizeof(CleanSlot));
   L->total = o;
   return WS_OK;
 }
@@ -1096,6 +1098,117 @@ ws_status ws_grid_image_noalloc(const ws_params* params, int64_t m,
     return fail(WS_INVALID_ARG, "misaligned vis, image or n_dropped_taps");
   return grid_image_impl(&pl, m, flat_source(uvw, vis, weight), image,
                          n_dropped_taps);
+}
+
+ws_status ws_dirty_beam(ws_plan* plan, int64_t m, const double* uvw,
+                        const float* weight, void* image_scratch, void* beam,
+                        double* beta) {
+  WS_TRY(check_plan(plan));
+  WS_TRY(check_vis_args(plan, m, uvw, weight));
+  if (image_scratch == nullptr || beam == nullptr || beta == nullptr)
+    return fail(WS_INVALID_ARG, "image_scratch, beam or beta is NULL");
+  if (!aligned(image_scratch, plan->L.elem) ||
+      !aligned(beam, plan->L.elem / 2) || !aligned(beta, 8))
+    return fail(WS_INVALID_ARG, "misaligned image_scratch, beam or beta");
+  if (plan->state != kEmpty)
+    return fail(WS_BAD_STATE,
+                "the stack is not empty; call ws_plan_reset first");
+  const bool f64 = plan->p.precision == WS_FP64;
+  const int64_t npix = (int64_t)plan->p.nu * plan->p.nv;
+  WS_TRY(launch(plan, "fill_zero", [&] {
+    if (f64) launch_fill_zero<double>(image_scratch, npix, plan->stream);
+    else launch_fill_zero<float>(image_scratch, npix, plan->stream);
+  }));
+  WS_TRY(grid_image_impl(plan, m, flat_source(uvw, nullptr, weight),
+                         image_scratch, nullptr));
+  return launch(plan, "beam_normalise", [&] {
+    if (f64)
+      launch_beam_normalise<double>(image_scratch, beam, beta, plan->p.nu,
+                                    plan->p.nv, plan->stream);
+    else
+      launch_beam_normalise<float>(image_scratch, beam, beta, plan->p.nu,
+                                   plan->p.nv, plan->stream);
+  });
+}
+
+ws_status ws_residual_image(ws_plan* plan, int64_t m, const double* uvw,
+                            const void* vis, const float* weight,
+                            const void* model, const double* beta,
+                            void* vis_scratch, void* image_scratch,
+                            void* residual) {
+  WS_TRY(check_plan(plan));
+  WS_TRY(check_vis_args(plan, m, uvw, weight));
+  if (model == nullptr || beta == nullptr || image_scratch == nullptr ||
+      residual == nullptr || (m > 0 && (vis == nullptr ||
+                                        vis_scratch == nullptr)))
+    return fail(WS_INVALID_ARG, "a buffer argument is NULL");
+  const size_t e = plan->L.elem;
+  if (!aligned(vis, e) || !aligned(vis_scratch, e) ||
+      !aligned(image_scratch, e) || !aligned(model, e / 2) ||
+      !aligned(residual, e / 2) || !aligned(beta, 8))
+    return fail(WS_INVALID_ARG, "misaligned buffer argument");
+  const bool f64 = plan->p.precision == WS_FP64;
+  const int64_t npix = (int64_t)plan->p.nu * plan->p.nv;
+  // Predicted visibilities of the model (unit weights), then R = V - pred.
+  ws_status st = f64 ? degrid_impl<double>(plan, model, 1, m, uvw, nullptr,
+                                           vis_scratch)
+                     : degrid_impl<float>(plan, model, 1, m, uvw, nullptr,
+                                          vis_scratch);
+  plan->state = kEmpty;
+  WS_TRY(st);
+  WS_TRY(launch(plan, "residual_vis", [&] {
+    if (f64) launch_residual_vis<double>(vis, vis_scratch, m, plan->stream);
+    else launch_residual_vis<float>(vis, vis_scratch, m, plan->stream);
+  }));
+  WS_TRY(launch(plan, "fill_zero", [&] {
+    if (f64) launch_fill_zero<double>(image_scratch, npix, plan->stream);
+    else launch_fill_zero<float>(image_scratch, npix, plan->stream);
+  }));
+  WS_TRY(grid_image_impl(plan, m, flat_source(uvw, vis_scratch, weight),
+                         image_scratch, nullptr));
+  return launch(plan, "real_scale", [&] {
+    if (f64)
+      launch_real_scale<double>(image_scratch, residual, beta, npix,
+                                plan->stream);
+    else
+      launch_real_scale<float>(image_scratch, residual, beta, npix,
+                               plan->stream);
+  });
+}
+
+ws_status ws_clean_minor(ws_plan* plan, void* residual, const void* beam,
+                         void* model, int32_t niter, double gain,
+                         double threshold, int32_t* picks, int32_t* n_done) {
+  WS_TRY(check_plan(plan));
+  if (residual == nullptr || beam == nullptr || model == nullptr)
+    return fail(WS_INVALID_ARG, "residual, beam or model is NULL");
+  if (niter < 0) return fail(WS_INVALID_ARG, "niter=%d < 0", niter);
+  if (!(gain > 0.0 && gain <= 1.0))
+    return fail(WS_INVALID_ARG, "gain must lie in (0, 1]");
+  if (!(threshold >= 0.0) || !std::isfinite(threshold))
+    return fail(WS_INVALID_ARG, "threshold must be finite and >= 0");
+  const size_t e = plan->L.elem / 2;
+  if (!aligned(residual, e) || !aligned(beam, e) || !aligned(model, e) ||
+      !aligned(picks, 4) || !aligned(n_done, 4))
+    return fail(WS_INVALID_ARG, "misaligned buffer argument");
+  const int64_t npix = (int64_t)plan->p.nu * plan->p.nv;
+  int64_t ns = (npix + 2047) / 2048;  // ~8 pixels per thread and block
+  if (ns > kCleanMaxSlots) ns = kCleanMaxSlots;
+  if (ns < 1) ns = 1;
+  CleanState* state = plan->w<CleanState>(plan->L.o_clean);
+  CleanSlot* slots = reinterpret_cast<CleanSlot*>(
+      plan->work + plan->L.o_clean + sizeof(CleanState));
+  return launch(plan, "clean_minor", [&] {
+    if (plan->p.precision == WS_FP64)
+      launch_clean_minor<double>(residual, beam, model, plan->p.nu,
+                                 plan->p.nv, niter, gain, threshold, state,
+                                 slots, (int)ns, picks, n_done,
+                                 plan->stream);
+    else
+      launch_clean_minor<float>(residual, beam, model, plan->p.nu,
+                                plan->p.nv, niter, gain, threshold, state,
+                                slots, (int)ns, picks, n_done, plan->stream);
+  });
 }
 
 ws_status ws_plan_reset(ws_plan* plan) {

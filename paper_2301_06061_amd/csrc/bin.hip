@@ -72,6 +72,7 @@ __device__ __forceinline__ cplx<R> source_value(const VisSource& s,
     return {(R)re, (R)im};
   }
   const R wt = s.weight != nullptr ? (R)s.weight[i] : (R)1;
+  if (s.vis == nullptr) return {wt, (R)0};  // unit visibilities
   const cplx<R> vv = static_cast<const cplx<R>*>(s.vis)[i];
   return {wt * vv.re, wt * vv.im};
 }

@@ -13,7 +13,8 @@ namespace ws {
 
 // Where the binning kernels read visibility i (0 <= i < m) from.
 //   rows == 0 (flat): uvw[i] in wavelengths, vis[i], weight[i] (or unit);
-//     the gridded value is weight[i] vis[i].
+//     the gridded value is weight[i] vis[i] (vis == null: unit
+//     visibilities, the value is weight[i]).
 //   rows == 1 (baseline-major, Sec. 2 data structures / Sec. 3.4.2 thread
 //     loop): visibility i = r * nchan + c of row r (one baseline at one
 //     time) and channel c; uvw[r] in metres, scaled by f_c / c0 to
@@ -169,6 +170,36 @@ void launch_fill_zero(void* p, int64_t n, hipStream_t st);
 void launch_zero_u32(uint32_t* p, int64_t n, hipStream_t st);
 template <typename R>
 void launch_twiddles(void* tw, int n, hipStream_t st);
+// Imaging major cycle (clean.hip).  Device state of one Hogbom minor
+// cycle and the per-block argmax slots it reduces.
+struct CleanState {
+  int32_t stopped;    // threshold reached (or nothing finite to take)
+  int32_t pending;    // a component awaits subtraction
+  int32_t count;      // components taken
+  int32_t pad;
+  int64_t pend_idx;   // its pixel, q * nu + p
+  double pend_amp;    // gain * peak
+};
+struct CleanSlot {
+  double mag, val;
+  int64_t idx;
+};
+constexpr int kCleanMaxSlots = 1024;
+template <typename R>
+void launch_beam_normalise(const void* img, void* beam, double* beta, int nu,
+                           int nv, hipStream_t st);
+template <typename R>
+void launch_residual_vis(const void* vis, void* pred, int64_t m,
+                         hipStream_t st);
+template <typename R>
+void launch_real_scale(const void* img, void* out, const double* beta,
+                       int64_t n, hipStream_t st);
+template <typename R>
+void launch_clean_minor(void* d, const void* beam, void* model, int nu,
+                        int nv, int niter, double gain, double threshold,
+                        CleanState* state, CleanSlot* slots, int nslots,
+                        int32_t* picks, int32_t* n_done, hipStream_t st);
+
 // Grid-correction table of a plan (g.corr must point at nu + nv doubles):
 // corr[p] = 1 / (c psi(f_p)), corr[nu + q] = 1 / psi(f_q), f = (index -
 // n/2) / n, psi the kernel's 1-D transform (kernel_transform).
