@@ -104,7 +104,20 @@ typedef int32_t ws_status;
  *            the image); degridding multiplies its input image by the same
  *            real factor, which keeps it the exact adjoint.  Refused
  *            (WS_INVALID_ARG) when psi is not positive for |f| <= 1/2.
- *            0: no correction (the dirty image of Eq. 2 as gridded). */
+ *            0: no correction (the dirty image of Eq. 2 as gridded).
+ *   binning  how visibilities are grouped by (plane, tile, edge region)
+ *            before gridding (the records and their order per key are the
+ *            same): WS_BINNING_PARTITION - two-level partition by (plane,
+ *            tile rows), then by (tile column, region), with per-workgroup
+ *            histograms and no global atomics; WS_BINNING_HASHED - one
+ *            counting sort with LDS-hashed counts and global atomics;
+ *            WS_BINNING_AUTO - the partition whenever its histograms fit
+ *            (at most 16384 buckets of at most 16384 keys), else hashed.
+ *            Requesting WS_BINNING_PARTITION where it does not fit is
+ *            WS_UNSUPPORTED_SIZE. */
+#define WS_BINNING_AUTO 0
+#define WS_BINNING_PARTITION 1
+#define WS_BINNING_HASHED 2
 typedef struct ws_params {
   int32_t nu, nv, nw;
   double fov_l, fov_m;
@@ -117,6 +130,7 @@ typedef struct ws_params {
   int32_t kernel;
   double beta;
   int32_t correct;
+  int32_t binning;
 } ws_params;
 
 typedef struct ws_plan ws_plan;

@@ -23,6 +23,9 @@ WS_FP32 = 0
 WS_FP64 = 1
 WS_KERNEL_GAUSS = 0
 WS_KERNEL_ES = 1
+WS_BINNING_AUTO = 0
+WS_BINNING_PARTITION = 1
+WS_BINNING_HASHED = 2
 WS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
@@ -40,6 +43,7 @@ class Params(C.Structure):
         ("support", C.c_int32), ("sigma", C.c_double),
         ("precision", C.c_int32), ("tile", C.c_int32), ("chunk", C.c_int32),
         ("kernel", C.c_int32), ("beta", C.c_double), ("correct", C.c_int32),
+        ("binning", C.c_int32),
     ]
 
 

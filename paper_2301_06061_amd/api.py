@@ -18,15 +18,19 @@ _PREC = {"fp32": _abi.WS_FP32, "fp64": _abi.WS_FP64,
          0: _abi.WS_FP32, 1: _abi.WS_FP64}
 _KERN = {"gauss": _abi.WS_KERNEL_GAUSS, "es": _abi.WS_KERNEL_ES,
          0: _abi.WS_KERNEL_GAUSS, 1: _abi.WS_KERNEL_ES}
+_BIN = {"auto": _abi.WS_BINNING_AUTO, "partition": _abi.WS_BINNING_PARTITION,
+        "hashed": _abi.WS_BINNING_HASHED, 0: 0, 1: 1, 2: 2}
 
 
 def make_params(nu, nv, nw, fov_l, fov_m, w_min, w_max, support=7,
                 sigma=0.0, precision="fp32", tile=0, chunk=0,
-                kernel="gauss", beta=0.0, correct=False) -> _abi.Params:
+                kernel="gauss", beta=0.0, correct=False,
+                binning="auto") -> _abi.Params:
     return _abi.Params(int(nu), int(nv), int(nw), float(fov_l), float(fov_m),
                        float(w_min), float(w_max), int(support), float(sigma),
                        _PREC[precision], int(tile), int(chunk),
-                       _KERN[kernel], float(beta), int(bool(correct)))
+                       _KERN[kernel], float(beta), int(bool(correct)),
+                       _BIN[binning])
 
 
 def kernel_transform(params: _abi.Params, f):
@@ -102,10 +106,10 @@ class WStackPlan:
     def __init__(self, nu, nv, nw, fov_l, fov_m, w_min, w_max, support=7,
                  sigma=0.0, precision="fp32", max_vis=1 << 20, tile=0,
                  chunk=0, device=None, kernel="gauss", beta=0.0,
-                 correct=False):
+                 correct=False, binning="auto"):
         self.params = make_params(nu, nv, nw, fov_l, fov_m, w_min, w_max,
                                   support, sigma, precision, tile, chunk,
-                                  kernel, beta, correct)
+                                  kernel, beta, correct, binning)
         self.fp64 = self.params.precision == _abi.WS_FP64
         self.cdtype = torch.complex128 if self.fp64 else torch.complex64
         self.rdtype = torch.float64 if self.fp64 else torch.float32

@@ -44,6 +44,10 @@ constexpr int kFusedRows = 4096;
 constexpr int kMinN = 16;
 constexpr int kMaxSupport = 15;
 constexpr int64_t kMaxVis = (int64_t(1) << 31) - 1;
+// Partition binning: level-1 histogram of at most this many buckets, and
+// buckets of at most this many keys (64 KB of LDS each).
+constexpr int kPartMaxBuckets = 16384;
+constexpr int kPartMaxSpan = 16384;
 
 enum PlaneState { kEmpty = 0, kGridded = 1, kTransformed = 2 };
 
@@ -58,10 +62,15 @@ struct Layout {
   uint32_t max_slots;
   uint32_t max_extra;
   size_t planes_bytes;
+  // binning: WS_BINNING_PARTITION or WS_BINNING_HASHED (resolved)
+  int binning;
+  uint32_t part_buckets, part_span;  // partition: buckets and keys each
   // workspace offsets
   size_t o_tw_u, o_tw_v, o_corr, o_counts, o_sums, o_keyrank, o_rec, o_chunks,
       o_slot, o_counters, o_split, o_extra, o_busy, o_idle, o_copies, o_desc,
-      o_strips, o_partials, o_scratch, o_clean, total;
+      o_strips, o_partials, o_scratch, o_clean, o_p_hist1, o_p_hist1x,
+      o_p_btot, o_p_bounds, o_p_seg, o_p_rec1, o_p_keys, o_p_chunk0, o_p_rank2,
+      o_p_hist2, o_p_hist2x, total;
 };
 
 ws_status check_params(const ws_params* p) {
@@ -97,6 +106,10 @@ ws_status check_params(const ws_params* p) {
     return fail(WS_INVALID_ARG, "beta must be finite and <= 200");
   if (p->correct != 0 && p->correct != 1)
     return fail(WS_INVALID_ARG, "correct=%d: use 0 or 1", p->correct);
+  if (p->binning != WS_BINNING_AUTO && p->binning != WS_BINNING_PARTITION &&
+      p->binning != WS_BINNING_HASHED)
+    return fail(WS_INVALID_ARG, "binning=%d: use WS_BINNING_AUTO, "
+                "WS_BINNING_PARTITION or WS_BINNING_HASHED", p->binning);
   if (p->precision != WS_FP32 && p->precision != WS_FP64)
     return fail(WS_INVALID_ARG, "precision=%d: use WS_FP32 or WS_FP64",
                 p->precision);
@@ -165,6 +178,26 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   if (L->nkeys >= (int64_t)0xFFFFFFF0ll)
     return fail(WS_UNSUPPORTED_SIZE, "too many bins (%lld)",
                 (long long)L->nkeys);
+  // Partition buckets: a plane and G tile rows (G a power of two dividing
+  // tiles_v), the fewest rows that keep the level-1 histogram within 64 KB
+  // of LDS; the level-2 histogram (the keys of one bucket) must fit too.
+  {
+    int64_t G = 1;
+    while (p->nw * (tv / G) > kPartMaxBuckets && G < tv) G *= 2;
+    const int64_t buckets = p->nw * (tv / G);
+    const int64_t span = G * tu * kRegions;
+    const bool fits = buckets <= kPartMaxBuckets && span <= kPartMaxSpan;
+    if (p->binning == WS_BINNING_PARTITION && !fits)
+      return fail(WS_UNSUPPORTED_SIZE,
+                  "partition binning: %lld buckets of %lld keys exceed the "
+                  "LDS histograms (<= %d buckets, <= %d keys)",
+                  (long long)buckets, (long long)span, kPartMaxBuckets,
+                  kPartMaxSpan);
+    L->binning = (p->binning == WS_BINNING_HASHED || !fits)
+                     ? WS_BINNING_HASHED : WS_BINNING_PARTITION;
+    L->part_buckets = (uint32_t)buckets;
+    L->part_span = (uint32_t)span;
+  }
   int64_t slots = 2 * max_vis / L->chunk + 64;
   if (slots > 4096) slots = 4096;
   L->max_slots = (uint32_t)slots;
@@ -188,9 +221,34 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   L->o_corr = take((size_t)(p->nu + p->nv) * 8);
   // Key counts, scanned in place into key offsets (+ the total).
   L->o_counts = take((size_t)(L->nkeys + 1) * 4);
-  // kCountCopies copies of the key counts, turned into per-copy offsets.
-  L->o_copies = take((size_t)kCountCopies * L->nkeys * 4);
+  const bool part = L->binning == WS_BINNING_PARTITION;
+  // kCountCopies copies of the key counts, turned into per-copy offsets
+  // (hashed binning only).
+  L->o_copies = take(part ? 0 : (size_t)kCountCopies * L->nkeys * 4);
+  const int64_t pblocks = partition_blocks(max_vis, L->elem);
+  const int64_t pscan = (int64_t)L->part_buckets * pblocks;
   L->o_sums = take((size_t)(scan_sums_len(nscan) + 1) * 4);
+  // Partition: level-1 histograms (block-major, then bucket-major and
+  // scanned), records and keys in bucket order, chunk starts, level-2
+  // ranks and histograms.
+  L->o_p_hist1 = take(part ? (size_t)pscan * 4 : 0);
+  L->o_p_hist1x = take(part ? (size_t)pscan * 4 : 0);
+  L->o_p_btot = take(part ? (size_t)pblocks * 4 : 0);
+  L->o_p_bounds = take(part ? (size_t)(L->part_buckets + 1) * 4 : 0);
+  L->o_p_seg = take(part ? (size_t)64 * L->part_buckets * 4 : 0);
+  L->o_p_rec1 = take(part ? (size_t)max_vis *
+                                (L->elem == 16 ? sizeof(Record<double>)
+                                               : sizeof(Record<float>))
+                          : 0);
+  L->o_p_keys = take(part ? (size_t)max_vis * 4 : 0);
+  L->o_p_chunk0 = take(part ? (size_t)(L->part_buckets + 1) * 4 : 0);
+  L->o_p_rank2 = take(part ? (size_t)max_vis * 4 : 0);
+  const size_t h2 = part ? (size_t)partition_chunks(max_vis, L->part_buckets,
+                                                     L->elem) *
+                               L->part_span * 4
+                         : 0;
+  L->o_p_hist2 = take(h2);
+  L->o_p_hist2x = take(h2);
   L->o_keyrank = take((size_t)max_vis * 8);
   L->o_rec = take((size_t)max_vis *
                   (L->elem == 16 ? sizeof(Record<double>)
@@ -369,25 +427,62 @@ ws_status bin_records(ws_plan* pl, int64_t m, const VisSource& src,
   const uint32_t chunk = degrid ? L.chunk_degrid : L.chunk;
   uint32_t* copies = pl->w<uint32_t>(L.o_copies);
   const uint32_t nkeys = (uint32_t)L.nkeys;
+  const bool part = L.binning == WS_BINNING_PARTITION;
   WS_TRY(launch(pl, "zero_counts", [&] {
-    launch_zero_u32(copies, kCountCopies * L.nkeys, st);
+    if (!part) launch_zero_u32(copies, kCountCopies * L.nkeys, st);
     launch_zero_u32(counters, 16, st);
     if (strips != nullptr && clear_strips)
       launch_zero_u32(strips, (int64_t)g.nw * g.tiles_u, st);
   }));
-  WS_TRY(launch(pl, "bin_count", [&] {
-    launch_bin_count(g, src, m, copies, nkeys, keyrank,
-                     reinterpret_cast<unsigned long long*>(n_dropped), st);
-  }));
-  WS_TRY(launch(pl, "scan_keys", [&] {
-    launch_fold_copies(copies, nkeys, counts, st);
-    launch_exclusive_scan(counts, counts, L.nkeys, sums, st);
-    launch_copy_offsets(copies, nkeys, counts, st);
-  }));
-  WS_TRY(launch(pl, "bin_scatter", [&] {
-    launch_bin_scatter<R>(g, src, m, keyrank, copies, nkeys,
-                          pl->work + L.o_rec, degrid, vis_out, st);
-  }));
+  if (part) {
+    PartWork w;
+    w.nbuckets = L.part_buckets;
+    w.span = L.part_span;
+    w.keyrank = keyrank;
+    w.hist1 = pl->w<uint32_t>(L.o_p_hist1);
+    w.hist1x = pl->w<uint32_t>(L.o_p_hist1x);
+    w.btot = pl->w<uint32_t>(L.o_p_btot);
+    w.hist2x = pl->w<uint32_t>(L.o_p_hist2x);
+    w.bounds = pl->w<uint32_t>(L.o_p_bounds);
+    w.seg = pl->w<uint32_t>(L.o_p_seg);
+    w.sums = sums;
+    w.rec1 = pl->work + L.o_p_rec1;
+    w.keys = pl->w<uint32_t>(L.o_p_keys);
+    w.chunk0 = pl->w<uint32_t>(L.o_p_chunk0);
+    w.rank2 = pl->w<uint32_t>(L.o_p_rank2);
+    w.hist2 = pl->w<uint32_t>(L.o_p_hist2);
+    w.offsets = counts;
+    w.rec = pl->work + L.o_rec;
+    auto* drop = reinterpret_cast<unsigned long long*>(n_dropped);
+    WS_TRY(launch(pl, "part_count1", [&] {
+      launch_part_count1<R>(g, src, m, w, drop, st);
+    }));
+    WS_TRY(launch(pl, "part_scan1", [&] { launch_part_scan1<R>(m, w, st); }));
+    WS_TRY(launch(pl, "part_scatter1", [&] {
+      launch_part_scatter1<R>(g, src, m, w, degrid, vis_out, st);
+    }));
+    WS_TRY(launch(pl, "part_count2", [&] {
+      launch_part_count2<R>(m, w, st);
+    }));
+    WS_TRY(launch(pl, "part_scan2", [&] { launch_part_scan2<R>(m, w, st); }));
+    WS_TRY(launch(pl, "part_scatter2", [&] {
+      launch_part_scatter2<R>(m, w, st);
+    }));
+  } else {
+    WS_TRY(launch(pl, "bin_count", [&] {
+      launch_bin_count(g, src, m, copies, nkeys, keyrank,
+                       reinterpret_cast<unsigned long long*>(n_dropped), st);
+    }));
+    WS_TRY(launch(pl, "scan_keys", [&] {
+      launch_fold_copies(copies, nkeys, counts, st);
+      launch_exclusive_scan(counts, counts, L.nkeys, sums, st);
+      launch_copy_offsets(copies, nkeys, counts, st);
+    }));
+    WS_TRY(launch(pl, "bin_scatter", [&] {
+      launch_bin_scatter<R>(g, src, m, keyrank, copies, nkeys,
+                            pl->work + L.o_rec, degrid, vis_out, st);
+    }));
+  }
   WS_TRY(launch(pl, "tile_work", [&] {
     launch_tile_work(g, counts, degrid, chunk, chunks, slot, counters, split,
                      L.max_slots, pl->w<uint2>(L.o_extra), L.max_extra,

@@ -421,7 +421,460 @@ __global__ __launch_bounds__(256) void k_tile_work(
   tile_chunks[t] = work == 0 ? 0u : nch;
 }
 
+// ---- two-level partition (no global atomics) ------------------------------
+//
+// Level 1 sorts the visibilities into coarse buckets (a plane and G rows of
+// tiles: all the keys of one bucket are contiguous in key order), level 2
+// sorts each bucket by its fine keys (tile column and region).  Both
+// levels count in dense LDS histograms and publish one histogram per
+// workgroup, so offsets come from scans, never from global atomics.  Both
+// scatters first place their workgroup's records in LDS in output order
+// (bucket by bucket, or key by key), then write them out as contiguous runs.
+//
+//   part_count1   placement, key, coarse bucket and the rank within the
+//                 workgroup's bucket (LDS atomic); the workgroup's bucket
+//                 histogram and its exclusive scan, block-major
+//   col_*         bucket-major exclusive scan of the block-major
+//                 histograms in place: offset of (bucket, block), and the
+//                 bucket bounds
+//   part_chunks   records per bucket -> chunks of one workgroup each
+//   (scan)        first chunk of every bucket
+//   part_scatter1 records built from the inputs, staged in LDS in bucket
+//                 order, written to their bucket offsets, with their keys
+//                 in a separate array (level 2 reads only the keys to
+//                 count; the record's spare word carries the key through
+//                 the staging)
+//   part_count2   per chunk: fine key ranks (LDS atomic), the chunk's
+//                 fine-key histogram and its exclusive scan
+//   part_scan2    per bucket: chunk-major running sums of every fine key,
+//                 the bucket's key offsets (the gridder's offsets table)
+//   part_scatter2 records staged in LDS in key order, written to their
+//                 key offsets
+//
+// Workgroups of level 1 and chunks of level 2 hold part_block<R>()
+// visibilities: as many records as fit the LDS staging area.
+
+constexpr int kPartThreads = 1024;
+constexpr int kPartSegs = 64;  // block segments of the level-1 scan
+
+// In-place exclusive scan of n LDS counters (each thread a contiguous run);
+// returns the total.  Called by every thread of the workgroup.
+__device__ __forceinline__ uint32_t lds_exclusive_scan(uint32_t* s, uint32_t n,
+                                                       uint32_t* s_tmp) {
+  const uint32_t per = (n + blockDim.x - 1) / blockDim.x;
+  const uint32_t f0 = threadIdx.x * per;
+  const uint32_t f1 = min(f0 + per, n);
+  uint32_t acc = 0;
+  for (uint32_t f = f0; f < f1; ++f) acc += s[f];
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(acc, s_tmp, &total);
+  for (uint32_t f = f0; f < f1; ++f) {
+    const uint32_t v = s[f];
+    s[f] = run;
+    run += v;
+  }
+  __syncthreads();
+  return total;
+}
+
+template <int V>
+__global__ __launch_bounds__(kPartThreads) void k_part_count1(
+    Geo g, VisSource src, int64_t m, uint32_t span, uint32_t nbuckets,
+    uint2* __restrict__ keyrank, uint32_t* __restrict__ hist1,
+    uint32_t* __restrict__ hist1x, uint32_t* __restrict__ btot,
+    unsigned long long* __restrict__ dropped) {
+  constexpr int PER = V / kPartThreads;
+  extern __shared__ uint32_t s_h[];  // nbuckets counters
+  __shared__ unsigned long long s_drop;
+  __shared__ uint32_t s_tmp[kPartThreads / 64];
+  const int tid = threadIdx.x;
+  for (uint32_t c = tid; c < nbuckets; c += kPartThreads) s_h[c] = 0u;
+  if (tid == 0) s_drop = 0;
+  __syncthreads();
+  unsigned long long my_drop = 0;
+  const int64_t base = (int64_t)blockIdx.x * V;
+  double cu[PER], cv[PER], cw[PER];
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    int64_t gi = base + (int64_t)e * kPartThreads + tid;
+    gi = gi < m ? gi : m - 1;
+    source_uvw(src, gi, cu[e], cv[e], cw[e]);
+  }
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int64_t gi = base + (int64_t)e * kPartThreads + tid;
+    if (gi >= m) continue;
+    double x, y;
+    int i0, j0, k;
+    uint2 kr = make_uint2(kNoKey, 0u);
+    if (place(g, cu[e], cv[e], cw[e], x, y, i0, j0, k)) {
+      my_drop += (unsigned long long)(g.K * g.K - taps_on_grid(g, i0, j0));
+      const uint32_t key = bin_key(g, i0, j0, k);
+      kr.x = key;
+      kr.y = atomicAdd(&s_h[key / span], 1u);
+    } else {
+      my_drop += (unsigned long long)(g.K * g.K);
+    }
+    keyrank[gi] = kr;
+  }
+  if (dropped != nullptr && my_drop != 0) atomicAdd(&s_drop, my_drop);
+  __syncthreads();
+  const size_t row = (size_t)blockIdx.x * nbuckets;
+  for (uint32_t c = tid; c < nbuckets; c += kPartThreads)
+    hist1[row + c] = s_h[c];
+  __syncthreads();
+  const uint32_t total = lds_exclusive_scan(s_h, nbuckets, s_tmp);
+  for (uint32_t c = tid; c < nbuckets; c += kPartThreads)
+    hist1x[row + c] = s_h[c];
+  if (tid == 0) {
+    btot[blockIdx.x] = total;
+    if (dropped != nullptr && s_drop != 0) atomicAdd(dropped, s_drop);
+  }
+}
+
+// Bucket-major exclusive scan of the block-major level-1 histograms
+// (hist[b][c], b < nb blocks, c < nc buckets) without a transpose: the
+// blocks are cut into nseg segments; col_sum totals each (segment,
+// bucket), col_seg scans those over the segments and leaves each bucket's
+// total, and col_apply turns the histograms into offsets in place:
+//   hist[b][c] <- bounds[c] + sum over b' < b of hist[b'][c],
+// bounds[c] the exclusive scan of the bucket totals (computed between
+// col_seg and col_apply).
+__global__ __launch_bounds__(256) void k_col_sum(
+    const uint32_t* __restrict__ hist, uint32_t nb, uint32_t nc,
+    uint32_t seglen, uint32_t* __restrict__ seg) {
+  const uint32_t c = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t s = blockIdx.y;
+  if (c >= nc) return;
+  const uint32_t b0 = s * seglen, b1 = min(b0 + seglen, nb);
+  uint32_t acc = 0;
+  for (uint32_t b = b0; b < b1; ++b) acc += hist[(size_t)b * nc + c];
+  seg[(size_t)s * nc + c] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_col_seg(uint32_t* __restrict__ seg,
+                                                 uint32_t nseg, uint32_t nc,
+                                                 uint32_t* __restrict__ tot) {
+  const uint32_t c = blockIdx.x * 256u + threadIdx.x;
+  if (c >= nc) return;
+  uint32_t run = 0;
+  for (uint32_t s = 0; s < nseg; ++s) {
+    const uint32_t v = seg[(size_t)s * nc + c];
+    seg[(size_t)s * nc + c] = run;
+    run += v;
+  }
+  tot[c] = run;
+}
+
+__global__ __launch_bounds__(256) void k_col_apply(
+    uint32_t* __restrict__ hist, uint32_t nb, uint32_t nc, uint32_t seglen,
+    const uint32_t* __restrict__ seg, const uint32_t* __restrict__ bounds) {
+  const uint32_t c = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t s = blockIdx.y;
+  if (c >= nc) return;
+  const uint32_t b0 = s * seglen, b1 = min(b0 + seglen, nb);
+  uint32_t run = bounds[c] + seg[(size_t)s * nc + c];
+  for (uint32_t b = b0; b < b1; ++b) {
+    uint32_t* p = hist + (size_t)b * nc + c;
+    const uint32_t v = *p;
+    *p = run;
+    run += v;
+  }
+}
+
+// offs1: the scanned (bucket, block) offsets, block-major (one row per
+// workgroup); hist1x: the workgroup's own exclusive bucket offsets.
+template <typename R, int V>
+__global__ __launch_bounds__(kPartThreads) void k_part_scatter1(
+    Geo g, VisSource src, int64_t m, const uint2* __restrict__ keyrank,
+    const uint32_t* __restrict__ offs1, const uint32_t* __restrict__ hist1x,
+    const uint32_t* __restrict__ btot, uint32_t span, uint32_t nbuckets,
+    Record<R>* __restrict__ rec, uint32_t* __restrict__ keys, int degrid,
+    cplx<R>* __restrict__ vis_out) {
+  constexpr int PER = V / kPartThreads;
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  Record<R>* s_rec = reinterpret_cast<Record<R>*>(s_raw);  // V records
+  const uint32_t b = blockIdx.x;
+  const int64_t base = (int64_t)b * V;
+  const uint32_t* ex = hist1x + (size_t)b * nbuckets;
+  const uint32_t* off = offs1 + (size_t)b * nbuckets;
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int64_t gi = base + (int64_t)e * kPartThreads + threadIdx.x;
+    if (gi >= m) continue;
+    const uint2 kr = keyrank[gi];
+    if (kr.x == kNoKey) {
+      if (degrid) vis_out[gi] = cplx<R>{(R)0, (R)0};
+      continue;
+    }
+    double x, y, u, v, w;
+    int i0, j0, k;
+    source_uvw(src, gi, u, v, w);
+    place(g, u, v, w, x, y, i0, j0, k);
+    Record<R> r;
+    r.dx = (R)(x - (double)i0);
+    r.dy = (R)(y - (double)j0);
+    if (!degrid) {
+      const cplx<R> vv = source_value<R>(src, gi);
+      r.vr = vv.re;
+      r.vi = vv.im;
+    } else {
+      r.vr = (R)source_weight(src, gi);
+      r.vi = (R)0;
+    }
+    r.cell = pack_cell(i0, j0);
+    r.idx = (uint32_t)gi;
+    r.pad0 = kr.x;  // the key, for the write-out and level 2
+    r.pad1 = 0u;
+    s_rec[ex[kr.x / span] + kr.y] = r;
+  }
+  __syncthreads();
+  const uint32_t n = btot[b];
+  for (uint32_t i = threadIdx.x; i < n; i += kPartThreads) {
+    const Record<R> r = s_rec[i];
+    const uint32_t c = r.pad0 / span;
+    const uint32_t pos = off[c] + (i - ex[c]);
+    rec[pos] = r;
+    keys[pos] = r.pad0;
+  }
+}
+
+// Chunks per bucket (bucket c holds records bounds[c] .. bounds[c + 1]).
+__global__ __launch_bounds__(256) void k_part_chunks(
+    const uint32_t* __restrict__ bounds, uint32_t nbuckets, uint32_t chunk,
+    uint32_t* __restrict__ nchunks) {
+  const uint32_t c = blockIdx.x * 256u + threadIdx.x;
+  if (c >= nbuckets) return;
+  nchunks[c] = (bounds[c + 1] - bounds[c] + chunk - 1) / chunk;
+}
+
+// Bucket of chunk ch: the last c with chunk0[c] <= ch (chunk0 exclusive
+// scan of the chunk counts, chunk0[nbuckets] = total), i.e. the bucket
+// that owns the chunk even when empty buckets share its chunk0 value.
+__device__ __forceinline__ uint32_t chunk_bucket(const uint32_t* chunk0,
+                                                 uint32_t nbuckets,
+                                                 uint32_t ch) {
+  uint32_t lo = 0, hi = nbuckets;  // chunk0[lo] <= ch < chunk0[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (chunk0[mid] <= ch) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int V>
+__global__ __launch_bounds__(kPartThreads) void k_part_count2(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ bounds,
+    const uint32_t* __restrict__ chunk0, uint32_t nbuckets, uint32_t span,
+    uint32_t* __restrict__ rank2, uint32_t* __restrict__ hist2,
+    uint32_t* __restrict__ hist2x) {
+  extern __shared__ uint32_t s_h[];  // span counters
+  __shared__ uint32_t s_tmp[kPartThreads / 64];
+  const uint32_t ch = blockIdx.x;
+  if (ch >= chunk0[nbuckets]) return;
+  const uint32_t c = chunk_bucket(chunk0, nbuckets, ch);
+  const uint32_t start = bounds[c] + (ch - chunk0[c]) * V;
+  const uint32_t end = min(start + (uint32_t)V, bounds[c + 1]);
+  for (uint32_t f = threadIdx.x; f < span; f += kPartThreads) s_h[f] = 0u;
+  __syncthreads();
+  const uint32_t kb = c * span;
+  for (uint32_t r = start + threadIdx.x; r < end; r += kPartThreads)
+    rank2[r] = atomicAdd(&s_h[keys[r] - kb], 1u);
+  __syncthreads();
+  const size_t row = (size_t)ch * span;
+  for (uint32_t f = threadIdx.x; f < span; f += kPartThreads)
+    hist2[row + f] = s_h[f];
+  __syncthreads();
+  lds_exclusive_scan(s_h, span, s_tmp);
+  for (uint32_t f = threadIdx.x; f < span; f += kPartThreads)
+    hist2x[row + f] = s_h[f];
+}
+
+// One workgroup per bucket: hist2 of its chunks becomes the offset of
+// every (chunk, fine key) share, and offsets[] of its keys is written.
+__global__ __launch_bounds__(kPartThreads) void k_part_scan2(
+    const uint32_t* __restrict__ bounds, const uint32_t* __restrict__ chunk0,
+    uint32_t nbuckets, uint32_t span, uint32_t* __restrict__ hist2,
+    uint32_t* __restrict__ offsets) {
+  extern __shared__ uint32_t s_tot[];  // span totals
+  __shared__ uint32_t s_tmp[kPartThreads / 64];
+  const uint32_t c = blockIdx.x;
+  const uint32_t base = bounds[c];
+  const uint32_t q0 = chunk0[c], q1 = chunk0[c + 1];
+  for (uint32_t f = threadIdx.x; f < span; f += kPartThreads) {
+    uint32_t run = 0;
+    for (uint32_t q = q0; q < q1; ++q) {
+      uint32_t* p = hist2 + (size_t)q * span + f;
+      const uint32_t v = *p;
+      *p = run;
+      run += v;
+    }
+    s_tot[f] = run;
+  }
+  __syncthreads();
+  lds_exclusive_scan(s_tot, span, s_tmp);
+  for (uint32_t f = threadIdx.x; f < span; f += kPartThreads) {
+    const uint32_t o = base + s_tot[f];
+    offsets[(size_t)c * span + f] = o;
+    for (uint32_t q = q0; q < q1; ++q) hist2[(size_t)q * span + f] += o;
+  }
+  if (c + 1 == nbuckets && threadIdx.x == 0)
+    offsets[(size_t)nbuckets * span] = bounds[nbuckets];
+}
+
+template <typename R, int V>
+__global__ __launch_bounds__(kPartThreads) void k_part_scatter2(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ bounds,
+    const uint32_t* __restrict__ chunk0, uint32_t nbuckets, uint32_t span,
+    const uint32_t* __restrict__ rank2, const uint32_t* __restrict__ hist2,
+    const uint32_t* __restrict__ hist2x,
+    const Record<R>* __restrict__ rec1, Record<R>* __restrict__ rec) {
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  Record<R>* s_rec = reinterpret_cast<Record<R>*>(s_raw);  // V records
+  const uint32_t ch = blockIdx.x;
+  if (ch >= chunk0[nbuckets]) return;
+  const uint32_t c = chunk_bucket(chunk0, nbuckets, ch);
+  const uint32_t start = bounds[c] + (ch - chunk0[c]) * V;
+  const uint32_t end = min(start + (uint32_t)V, bounds[c + 1]);
+  const uint32_t* off = hist2 + (size_t)ch * span;
+  const uint32_t* ex = hist2x + (size_t)ch * span;
+  const uint32_t kb = c * span;
+  for (uint32_t r = start + threadIdx.x; r < end; r += kPartThreads)
+    s_rec[ex[keys[r] - kb] + rank2[r]] = rec1[r];
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < end - start; i += kPartThreads) {
+    const Record<R> r = s_rec[i];
+    const uint32_t f = r.pad0 - kb;
+    rec[off[f] + (i - ex[f])] = r;
+  }
+}
+
 }  // namespace
+
+// Two-level partition of m visibilities (see the kernels above), in the
+// phases the library times separately.
+namespace {
+template <typename R>
+constexpr int part_block() {
+  // LDS staging of one workgroup: 4096 32-byte (FP32) or 2048 48-byte
+  // (FP64) records.
+  return sizeof(R) == 4 ? 4096 : 2048;
+}
+int part_block_of(int elem) { return elem == 8 ? 4096 : 2048; }
+uint32_t part_nb1(int64_t m, int V) {
+  const int64_t nb = (m + V - 1) / V;
+  return (uint32_t)(nb > 0 ? nb : 1);
+}
+uint32_t part_max_chunks(int64_t m, uint32_t nbuckets, int V) {
+  return (uint32_t)((m + V - 1) / V) + nbuckets;
+}
+}  // namespace
+
+template <typename R>
+void launch_part_count1(const Geo& g, const VisSource& src, int64_t m,
+                        const PartWork& w, unsigned long long* dropped,
+                        hipStream_t st) {
+  if (m == 0) return;
+  constexpr int V = part_block<R>();
+  hipLaunchKernelGGL(k_part_count1<V>, dim3(part_nb1(m, V)),
+                     dim3(kPartThreads), (size_t)w.nbuckets * 4, st, g, src, m,
+                     w.span, w.nbuckets, w.keyrank, w.hist1, w.hist1x, w.btot,
+                     dropped);
+}
+
+template <typename R>
+void launch_part_scan1(int64_t m, const PartWork& w, hipStream_t st) {
+  constexpr int V = part_block<R>();
+  const uint32_t C = w.nbuckets;
+  const dim3 cg((C + 255) / 256);
+  if (m > 0) {
+    const uint32_t nb1 = part_nb1(m, V);
+    const uint32_t nseg = nb1 < (uint32_t)kPartSegs ? nb1 : (uint32_t)kPartSegs;
+    const uint32_t seglen = (nb1 + nseg - 1) / nseg;
+    hipLaunchKernelGGL(k_col_sum, dim3(cg.x, nseg), dim3(256), 0, st,
+                       w.hist1, nb1, C, seglen, w.seg);
+    hipLaunchKernelGGL(k_col_seg, cg, dim3(256), 0, st, w.seg, nseg, C,
+                       w.bounds);
+    launch_exclusive_scan(w.bounds, w.bounds, (int64_t)C, w.sums, st);
+    hipLaunchKernelGGL(k_col_apply, dim3(cg.x, nseg), dim3(256), 0, st,
+                       w.hist1, nb1, C, seglen, w.seg, w.bounds);
+  } else {
+    launch_zero_u32(w.bounds, (int64_t)C + 1, st);
+  }
+  hipLaunchKernelGGL(k_part_chunks, cg, dim3(256), 0, st, w.bounds, C,
+                     (uint32_t)V, w.chunk0);
+  launch_exclusive_scan(w.chunk0, w.chunk0, (int64_t)C, w.sums, st);
+}
+
+template <typename R>
+void launch_part_scatter1(const Geo& g, const VisSource& src, int64_t m,
+                          const PartWork& w, int degrid, void* vis_out,
+                          hipStream_t st) {
+  if (m == 0) return;
+  constexpr int V = part_block<R>();
+  hipLaunchKernelGGL((k_part_scatter1<R, V>), dim3(part_nb1(m, V)),
+                     dim3(kPartThreads), (size_t)V * sizeof(Record<R>), st, g,
+                     src, m, w.keyrank, w.hist1, w.hist1x, w.btot, w.span,
+                     w.nbuckets, (Record<R>*)w.rec1, w.keys, degrid,
+                     (cplx<R>*)vis_out);
+}
+
+template <typename R>
+void launch_part_count2(int64_t m, const PartWork& w, hipStream_t st) {
+  if (m == 0) return;
+  constexpr int V = part_block<R>();
+  hipLaunchKernelGGL(k_part_count2<V>,
+                     dim3(part_max_chunks(m, w.nbuckets, V)),
+                     dim3(kPartThreads), (size_t)w.span * 4, st, w.keys,
+                     w.bounds, w.chunk0, w.nbuckets, w.span, w.rank2, w.hist2,
+                     w.hist2x);
+}
+
+template <typename R>
+void launch_part_scan2(int64_t, const PartWork& w, hipStream_t st) {
+  hipLaunchKernelGGL(k_part_scan2, dim3(w.nbuckets), dim3(kPartThreads),
+                     (size_t)w.span * 4, st, w.bounds, w.chunk0, w.nbuckets,
+                     w.span, w.hist2, w.offsets);
+}
+
+template <typename R>
+void launch_part_scatter2(int64_t m, const PartWork& w, hipStream_t st) {
+  if (m == 0) return;
+  constexpr int V = part_block<R>();
+  hipLaunchKernelGGL((k_part_scatter2<R, V>),
+                     dim3(part_max_chunks(m, w.nbuckets, V)),
+                     dim3(kPartThreads), (size_t)V * sizeof(Record<R>), st,
+                     w.keys, w.bounds, w.chunk0, w.nbuckets, w.span, w.rank2,
+                     w.hist2, w.hist2x, (const Record<R>*)w.rec1,
+                     (Record<R>*)w.rec);
+}
+
+#define WS_INST(R)                                                           \
+  template void launch_part_count1<R>(const Geo&, const VisSource&, int64_t, \
+                                      const PartWork&, unsigned long long*, \
+                                      hipStream_t);                         \
+  template void launch_part_scan1<R>(int64_t, const PartWork&, hipStream_t); \
+  template void launch_part_scatter1<R>(const Geo&, const VisSource&,       \
+                                        int64_t, const PartWork&, int,      \
+                                        void*, hipStream_t);                \
+  template void launch_part_count2<R>(int64_t, const PartWork&,             \
+                                      hipStream_t);                         \
+  template void launch_part_scan2<R>(int64_t, const PartWork&, hipStream_t); \
+  template void launch_part_scatter2<R>(int64_t, const PartWork&,           \
+                                        hipStream_t);
+WS_INST(float)
+WS_INST(double)
+#undef WS_INST
+
+int64_t partition_blocks(int64_t max_vis, int elem) {
+  const int V = part_block_of(elem);
+  return (max_vis + V - 1) / V;
+}
+int64_t partition_chunks(int64_t max_vis, int64_t nbuckets, int elem) {
+  const int V = part_block_of(elem);
+  return (max_vis + V - 1) / V + nbuckets;
+}
 
 void launch_bin_count(const Geo& g, const VisSource& src, int64_t m,
                       uint32_t* copies, uint32_t nkeys, uint2* keyrank,

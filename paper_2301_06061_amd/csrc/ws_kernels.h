@@ -39,6 +39,52 @@ struct VisSource {
 void launch_bin_count(const Geo& g, const VisSource& src, int64_t m,
                       uint32_t* copies, uint32_t nkeys, uint2* keyrank,
                       unsigned long long* dropped, hipStream_t st);
+// Two-level partition (bin.hip): the same records and key offsets as the
+// counting sort above, with no global atomics.  Buckets hold `span` keys
+// each (a plane and a group of tile rows; nbuckets * span = all keys).
+struct PartWork {
+  uint32_t nbuckets, span;
+  uint2* keyrank;      // [max_vis] key and rank in the workgroup's bucket
+  uint32_t* hist1;     // [blocks][nbuckets] level-1 histograms, then
+                       // the scanned (bucket, block) offsets in place
+  uint32_t* hist1x;    // [blocks][nbuckets] each workgroup's exclusive scan
+  uint32_t* btot;      // [blocks] records each workgroup placed
+  uint32_t* bounds;    // [nbuckets + 1] first record of every bucket
+  uint32_t* seg;       // [64][nbuckets] segment sums of the level-1 scan
+  uint32_t* sums;      // scan scratch
+  void* rec1;          // [max_vis] records in bucket order
+  uint32_t* keys;      // [max_vis] their keys
+  uint32_t* chunk0;    // [nbuckets + 1] first level-2 chunk of each bucket
+  uint32_t* rank2;     // [max_vis] rank within (chunk, key)
+  uint32_t* hist2;     // [chunks][span] level-2 histograms -> offsets
+  uint32_t* hist2x;    // [chunks][span] each chunk's exclusive scan
+  uint32_t* offsets;   // [nkeys + 1] record offset of every key
+  void* rec;           // [max_vis] final records in key order
+};
+// Phases, in order: level-1 counts; the bucket-major scan and the
+// level-2 chunks; the level-1 scatter; level-2 counts; level-2 scan (writes
+// the key offsets); the level-2 scatter (writes the final records).
+template <typename R>
+void launch_part_count1(const Geo& g, const VisSource& src, int64_t m,
+                        const PartWork& w, unsigned long long* dropped,
+                        hipStream_t st);
+template <typename R>
+void launch_part_scan1(int64_t m, const PartWork& w, hipStream_t st);
+template <typename R>
+void launch_part_scatter1(const Geo& g, const VisSource& src, int64_t m,
+                          const PartWork& w, int degrid, void* vis_out,
+                          hipStream_t st);
+template <typename R>
+void launch_part_count2(int64_t m, const PartWork& w, hipStream_t st);
+template <typename R>
+void launch_part_scan2(int64_t m, const PartWork& w, hipStream_t st);
+template <typename R>
+void launch_part_scatter2(int64_t m, const PartWork& w, hipStream_t st);
+// Workgroups of level 1 and chunks of level 2 for max_vis visibilities
+// (elem: bytes of a complex value, 8 or 16).
+int64_t partition_blocks(int64_t max_vis, int elem);
+int64_t partition_chunks(int64_t max_vis, int64_t nbuckets, int elem);
+
 void launch_fold_copies(const uint32_t* copies, uint32_t nkeys,
                         uint32_t* totals, hipStream_t st);
 void launch_copy_offsets(uint32_t* copies, uint32_t nkeys,
