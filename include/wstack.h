@@ -81,7 +81,9 @@ typedef int32_t ws_status;
 #define WS_KERNEL_ES 1
 
 /* Imaging geometry and kernel.
- *   nu, nv   grid size, each a power of two in [16, 16384]
+ *   nu, nv   grid size, each a power of two in [16, 32768] (65536 would
+ *            overflow the 16-bit cell fields of the binned records, and a
+ *            single FP32 plane of it is 34 GB)
  *   nw       number of w-planes, >= 1
  *   fov_l, fov_m  full field of view in radians, > 0, with
  *            (fov_l/2)^2 + (fov_m/2)^2 < 1

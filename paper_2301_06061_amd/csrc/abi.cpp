@@ -35,7 +35,9 @@ bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-constexpr int kMaxN = 16384;
+// Grid edge limit: the record packs each cell index in 16 bits (with a
+// bias of 64), and a 32768^2 FP32 plane is already 8.6 GB.
+constexpr int kMaxN = 32768;
 // Largest column length transformed in one pass (whole column blocks in
 // LDS); longer columns use the four-step transform.
 constexpr int kOnePassCols = 4096;
@@ -68,7 +70,7 @@ struct Layout {
   // workspace offsets
   size_t o_tw_u, o_tw_v, o_corr, o_counts, o_sums, o_keyrank, o_rec, o_chunks,
       o_slot, o_counters, o_split, o_extra, o_busy, o_idle, o_copies, o_desc,
-      o_strips, o_partials, o_scratch, o_clean, o_p_hist1, o_p_hist1x,
+      o_strips, o_partials, o_scratch, o_rowscratch, o_clean, o_p_hist1, o_p_hist1x,
       o_p_btot, o_p_bounds, o_p_seg, o_p_rec1, o_p_keys, o_p_chunk0, o_p_rank2,
       o_p_hist2, o_p_hist2x, total;
 };
@@ -126,8 +128,7 @@ ws_status check_params(const ws_params* p) {
   }
   if (!fft_supported(p->nu, p->precision == WS_FP64 ? 16 : 8))
     return fail(WS_UNSUPPORTED_SIZE,
-                "nu=%d: a row must fit one workgroup's LDS (FP32 <= 16384, "
-                "FP64 <= 8192)", p->nu);
+                "nu=%d: a quarter row must fit one workgroup's LDS", p->nu);
   if (p->chunk < 0 || p->chunk > (1 << 24))
     return fail(WS_INVALID_ARG, "chunk=%d out of range", p->chunk);
   const int64_t cells = (int64_t)p->nu * p->nv;
@@ -270,6 +271,9 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   // when columns use the four-step transform.
   L->o_scratch = take(p->nv > kOnePassCols
                           ? (size_t)p->nu * p->nv * L->elem : (size_t)0);
+  // Scratch rows of the 4-way split row transform (rows too long for two
+  // half-length LDS transforms).
+  L->o_rowscratch = take(fft_row_scratch_bytes(p->nu, L->elem));
   // Minor-cycle state and its per-block argmax slots.
   L->o_clean = take(sizeof(CleanState) + kCleanMaxSlots * sizeof(CleanSlot));
   L->total = o;
@@ -605,7 +609,8 @@ ws_status rows_impl(ws_plan* pl, int sign) {
   bool ok = true;
   WS_TRY(launch(pl, "fft_rows", [&] {
     ok = launch_fft_rows<R>(pl->planes, p.nu, (int64_t)p.nw * p.nv,
-                            pl->work + pl->L.o_tw_u, sign, pl->stream);
+                            pl->work + pl->L.o_tw_u, sign,
+                            pl->work + pl->L.o_rowscratch, pl->stream);
   }));
   if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no row FFT for nu=%d", p.nu);
   return WS_OK;

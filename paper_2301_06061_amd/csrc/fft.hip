@@ -363,6 +363,64 @@ __global__ __launch_bounds__(NT) void k_fft_rows_split(
   fft_line<R, LOGH, 1, NT>(lds, ld_diff, st_odd, twl, s);
 }
 
+// Rows too long even for two half-length LDS transforms (FP64 at 32768):
+// F-way decimation in frequency with F = 4.  With x' = (-1)^n x and
+// NF = N / F,
+//   X[F k + r] = DFT_NF( W_N^(s r n) sum_m x'[n + m NF] W_F^(s m r) )[k],
+// so output class r is one length-NF transform of a combination of the F
+// samples x'[n + m NF]; output F k + r carries the centring sign (-1)^r.
+// Pass r re-reads the row (F samples per point) instead of keeping the
+// other classes in registers (at FP64 they would need ~200 registers a
+// thread), and writes its outputs to the workgroup's row of `scratch`
+// (every class reads the whole row, so nothing can be written in place
+// before the last class); the finished row is then copied back.
+// Persistent: workgroup b transforms rows b, b + G, ... (G = grid size),
+// with scratch rows [G][N].  Only for grids wider than the fused kernels
+// handle.
+template <typename R, int LOGF, int NT, int F>
+__global__ __launch_bounds__(NT) void k_fft_rows_splitF(
+    cplx<R>* data, int64_t nrows, const cplx<R>* __restrict__ tw, R s,
+    cplx<R>* __restrict__ scratch) {
+  constexpr int NF = 1 << LOGF;
+  constexpr int N = F * NF;
+  __shared__ cplx<R> lds[lds_line<NF>(1)];
+  __shared__ cplx<R> s_lo[kTwLo], s_hi[(NF + kTwLo - 1) / kTwLo];
+  const Twiddles<R> twl = load_twiddles_sub(s_lo, s_hi, tw, NF, N);
+  __syncthreads();
+  cplx<R>* tmp = scratch + (size_t)blockIdx.x * N;
+  for (int64_t row = blockIdx.x; row < nrows; row += gridDim.x) {
+    cplx<R>* line = data + row * N;
+    for (int r = 0; r < F; ++r) {
+      auto ld = [&](int e, int, int, int) {
+        cplx<R> acc = {(R)0, (R)0};
+#pragma unroll
+        for (int m = 0; m < F; ++m) {
+          const int idx = e + m * NF;
+          const cplx<R> x = checker(line[idx], idx);
+          acc = cadd(acc,
+                     cmul(x, twiddle_full(tw, (m * r * NF) & (N - 1), s)));
+        }
+        return cmul(acc, twiddle_full(tw, (r * e) & (N - 1), s));
+      };
+      const R sg = (r & 1) ? (R)-1 : (R)1;
+      auto st = [&](int e, int, int, int, cplx<R> v) {
+        tmp[F * e + r] = cplx<R>{sg * v.re, sg * v.im};
+      };
+      fft_line<R, LOGF, 1, NT>(lds, ld, st, twl, s);
+      __syncthreads();
+    }
+    // Scratch row complete (global writes of this workgroup, ordered by
+    // the barrier's release / acquire at workgroup scope): copy it back.
+    __threadfence_block();
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += NT) line[i] = tmp[i];
+    __syncthreads();
+  }
+}
+
+// Workgroups of k_fft_rows_splitF (and scratch rows it needs).
+constexpr int kSplitRowGroups = 256;
+
 // Which rows of a column block hold data, from the per-tile record
 // counts of gridding (0 = a tile without records, whose cells a fused
 // grid-and-image call leaves unwritten and the transform takes as zero).
@@ -973,7 +1031,7 @@ constexpr bool line_fits() {
 
 template <typename R, int LOGN>
 bool rows_t(cplx<R>* data, int64_t nrows, const cplx<R>* tw, R s,
-            hipStream_t st) {
+            cplx<R>* scratch, hipStream_t st) {
   if constexpr (line_fits<R, LOGN>()) {
     constexpr int NT = row_threads(LOGN);
     hipLaunchKernelGGL((k_fft_rows<R, LOGN, NT>), dim3((unsigned)nrows),
@@ -984,6 +1042,14 @@ bool rows_t(cplx<R>* data, int64_t nrows, const cplx<R>* tw, R s,
     hipLaunchKernelGGL((k_fft_rows_split<R, LOGN - 1, NT>),
                        dim3((unsigned)nrows), dim3(NT), 0, st, data, nrows,
                        tw, s);
+    return true;
+  } else if constexpr (line_fits<R, LOGN - 2>()) {
+    if (scratch == nullptr) return false;
+    constexpr int NT = row_threads(LOGN - 2);
+    const int64_t g = nrows < kSplitRowGroups ? nrows : kSplitRowGroups;
+    hipLaunchKernelGGL((k_fft_rows_splitF<R, LOGN - 2, NT, 4>),
+                       dim3((unsigned)(g > 0 ? g : 1)), dim3(NT), 0, st, data,
+                       nrows, tw, s, scratch);
     return true;
   } else {
     return false;
@@ -1131,24 +1197,36 @@ bool screen_bcast_t(const void* img, int img_real, cplx<R>* planes,
     case 12: { constexpr int LG = 12; CALL; } break;                       \
     case 13: { constexpr int LG = 13; CALL; } break;                       \
     case 14: { constexpr int LG = 14; CALL; } break;                       \
+    case 15: { constexpr int LG = 15; CALL; } break;                       \
     default: return false;                                                 \
   }
 
 }  // namespace
 
 bool fft_supported(int n, int elem_bytes) {
-  // Half a row must fit one workgroup's LDS (150 KiB with padding).
-  return n >= 16 && n <= 16384 && (n & (n - 1)) == 0 &&
-         (size_t)(n / 2 + n / 16) * elem_bytes <= 150 * 1024;
+  // A quarter row must fit one workgroup's LDS (150 KiB with padding).
+  return n >= 16 && n <= 32768 && (n & (n - 1)) == 0 &&
+         (size_t)(n / 4 + n / 128) * elem_bytes <= 150 * 1024;
+}
+
+bool fft_row_needs_scratch(int n, int elem_bytes) {
+  // Rows longer than two half-length LDS transforms take the 4-way split.
+  return (size_t)(n / 2 + n / 64) * elem_bytes > 150 * 1024;
+}
+
+size_t fft_row_scratch_bytes(int n, int elem_bytes) {
+  return fft_row_needs_scratch(n, elem_bytes)
+             ? (size_t)kSplitRowGroups * n * elem_bytes : 0;
 }
 
 template <typename R>
 bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw, int sign,
-                     hipStream_t st) {
+                     void* scratch, hipStream_t st) {
   const int lg = ilog2(n);
   bool ok = false;
   WS_LOGN_SWITCH(lg, (ok = rows_t<R, LG>((cplx<R>*)data, nrows,
-                                         (const cplx<R>*)tw, (R)sign, st)));
+                                         (const cplx<R>*)tw, (R)sign,
+                                         (cplx<R>*)scratch, st)));
   return ok;
 }
 
@@ -1254,6 +1332,7 @@ void launch_twiddles(void* tw, int n, hipStream_t st) {
 
 #define WS_INST(R)                                                            \
   template bool launch_fft_rows<R>(void*, int, int64_t, const void*, int,    \
+                                   void*,                                  \
                                    hipStream_t);                             \
   template bool launch_fft_cols<R>(void*, int, int, int, const void*, int,   \
                                    const uint32_t*, int, const uint32_t*,    \

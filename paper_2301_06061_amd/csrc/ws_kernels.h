@@ -181,9 +181,12 @@ void launch_degrid_tiles(const Geo& g, const uint32_t* offsets,
 
 // FFT and screen (fft.hip)
 bool fft_supported(int n, int elem_bytes);
+// Rows too long for two half-length LDS transforms take a 4-way split
+// that writes through a scratch area of this many bytes (0 otherwise).
+size_t fft_row_scratch_bytes(int n, int elem_bytes);
 template <typename R>
 bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw,
-                     int sign, hipStream_t st);
+                     int sign, void* scratch, hipStream_t st);
 // Column transforms; with `strips` non-null, the blocks of column strips
 // (strip_w columns of one plane) whose mark is zero are skipped; with
 // `tiles` non-null (per-tile record counts, tile edge strip_w), rows of

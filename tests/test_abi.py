@@ -65,7 +65,8 @@ def test_workspace_grows_with_max_vis():
 @pytest.mark.parametrize("kw,status", [
     (dict(nu=500), _abi.WS_UNSUPPORTED_SIZE),
     (dict(nv=8), _abi.WS_UNSUPPORTED_SIZE),
-    (dict(nu=32768), _abi.WS_UNSUPPORTED_SIZE),
+    (dict(nu=65536), _abi.WS_UNSUPPORTED_SIZE),
+    (dict(nv=65536), _abi.WS_UNSUPPORTED_SIZE),
     (dict(nw=0), _abi.WS_INVALID_ARG),
     (dict(support=6), _abi.WS_UNSUPPORTED_SIZE),
     (dict(support=17), _abi.WS_UNSUPPORTED_SIZE),
@@ -91,6 +92,22 @@ def test_valid_edge_params_accepted():
     ws.validate(_p(nu=4096, nv=16, support=1, tile=16))
     ws.validate(_p(nu=16384, nv=16384, precision="fp32"))
     ws.validate(_p(nu=16384, nv=16384, precision="fp64"))
+    ws.validate(_p(nu=32768, nv=32768, precision="fp32"))
+    ws.validate(_p(nu=32768, nv=32768, precision="fp64"))
+
+
+def test_widest_rows_reserve_split_scratch():
+    """FP64 rows of 32768 exceed two half-length LDS transforms: their
+    plans reserve the 4-way split's scratch rows (256 rows of the grid
+    width); FP32 rows of the same width do not need them."""
+    _, w64 = ws.workspace_bytes(_p(nu=32768, nv=16, nw=1, precision="fp64",
+                                   tile=16), 1000)
+    _, w64n = ws.workspace_bytes(_p(nu=16384, nv=16, nw=1, precision="fp64",
+                                    tile=16), 1000)
+    assert w64 - w64n >= 256 * 32768 * 16
+    _, w32 = ws.workspace_bytes(_p(nu=32768, nv=16, nw=1, precision="fp32",
+                                   tile=16), 1000)
+    assert w32 < 256 * 32768 * 8
 
 
 def test_max_vis_bounds():

@@ -102,11 +102,13 @@ def test_grid_matches_oracle(precision, ci):
 @pytest.mark.parametrize("shape", [(16, 16, 1), (64, 32, 3), (512, 512, 2),
                                    (32, 4096, 1), (4096, 16, 1),
                                    (16, 8192, 2), (32, 16384, 1),
-                                   (8192, 16, 1), (16384, 16, 1)])
+                                   (8192, 16, 1), (16384, 16, 1),
+                                   (32768, 16, 1), (16, 32768, 1)])
 @pytest.mark.parametrize("direction", [1, -1])
 def test_fft_planes_matches_oracle(precision, shape, direction):
-    """One-pass and four-step columns; rows in LDS, or split in two halves
-    when a row exceeds LDS (FP64 at 16384)."""
+    """One-pass and four-step columns; rows in LDS, split in two halves
+    when a row exceeds LDS (FP64 at 16384, FP32 at 32768), or in four
+    quarters through scratch rows (FP64 at 32768)."""
     nu, nv, nw = shape
     rng = np.random.default_rng(nu + nv + nw)
     cdt = np.complex128 if precision == "fp64" else np.complex64
@@ -154,7 +156,10 @@ LARGE = [dict(n=16, nv=8192, nw=2, support=7, m=2000, law="core",
          dict(n=32, nv=16384, nw=3, support=9, m=2000, law="gauss",
               fov_deg=0.005),
          dict(n=8192, nv=16, nw=2, support=5, m=2000, law="core"),
-         dict(n=16384, nv=16, nw=2, support=7, m=1000, law="gauss")]
+         dict(n=16384, nv=16, nw=2, support=7, m=1000, law="gauss"),
+         dict(n=32768, nv=16, nw=2, support=7, m=1000, law="gauss"),
+         dict(n=16, nv=32768, nw=2, support=5, m=1000, law="core",
+              fov_deg=0.005)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
