@@ -717,54 +717,31 @@ __device__ __forceinline__ double n_minus_one(const Geo& g, int p, int q) {
 }
 
 // Screen phasor exp(+-2 pi i w_k (n - 1)) of pixel (p, q), handed out plane
-// by plane (k = 0, 1, ... in order).  The phase w_k (n - 1) is formed and
-// reduced to [-1/2, 1/2] turn in FP64 on both paths.  The FP64 path seeds
-// an FP64 phasor with sincospi and advances it by an FP64 complex multiply
-// per plane; the FP32 path evaluates each plane's phasor directly from
-// the reduced phase with the hardware sine and cosine, whose argument is
-// in turns (measured maximum error 1.3e-7 over [-1/2, 1/2] turn, the order
-// of the FP32 transform's own), which keeps two registers of state per
-// pixel instead of eight and costs two instructions.
+// by plane (k = 0, 1, ... in order, each once).  The phases w_0 (n - 1) and
+// dw (n - 1) are formed and reduced to [-1/2, 1/2] turn in FP64 on both
+// paths, and the phasor of plane 0 and the step between planes are taken
+// from them with FP64 sincospi; each further plane's phasor is the
+// previous one times the step (the planes are equispaced in w).  The FP64
+// path advances an FP64 phasor; the FP32 path rounds the seed and step to
+// FP32 and advances in FP32 (4 registers of state per pixel): its phase
+// error grows by about one FP32 rounding per plane (~2e-6 rad after 32
+// planes) and never sees the large unreduced argument.  `odd` adds half a
+// turn to the seed: the output centring sign of odd pixels.
 template <typename R>
-struct Screen;
-
-template <>
-struct Screen<double> {
-  cplx<double> ph, step;
-  // `odd`: the phasor also carries the output centring sign -1.
+struct Screen {
+  cplx<R> ph, step;
   __device__ __forceinline__ void init(const Geo& g, int p, int q, bool conj,
                                        bool odd = false) {
     const double nm1 = n_minus_one(g, p, q);
-    ph = turns_phasor(g.w0 * nm1 + (odd ? 0.5 : 0.0));
-    step = turns_phasor(g.dw * nm1);
-    if (conj) {
-      ph.im = -ph.im;
-      step.im = -step.im;
-    }
+    const cplx<double> a = turns_phasor(fma(g.w0, nm1, odd ? 0.5 : 0.0));
+    const cplx<double> b = turns_phasor(g.dw * nm1);
+    ph = {(R)a.re, (R)(conj ? -a.im : a.im)};
+    step = {(R)b.re, (R)(conj ? -b.im : b.im)};
   }
-  __device__ __forceinline__ cplx<double> next(const Geo&, int,
-                                               double = 0.0) {
-    const cplx<double> w = ph;
+  __device__ __forceinline__ cplx<R> next(const Geo&, int) {
+    const cplx<R> w = ph;
     ph = cmul(ph, step);
     return w;
-  }
-};
-
-template <>
-struct Screen<float> {
-  double nm1;  // negated for the conjugate screen
-  __device__ __forceinline__ void init(const Geo& g, int p, int q, bool conj,
-                                       bool = false) {
-    nm1 = n_minus_one(g, p, q);
-    if (conj) nm1 = -nm1;
-  }
-  // `half` = 1/2 adds the output centring sign -1 as half a turn, inside
-  // the FP64 phase (a fused multiply-add, so it costs nothing).
-  __device__ __forceinline__ cplx<float> next(const Geo& g, int k,
-                                              double half = 0.0) {
-    const double a = fma(g.w0 + (double)k * g.dw, nm1, half);
-    const float f = (float)(a - rint(a));
-    return {__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f)};
   }
 };
 
@@ -818,7 +795,6 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
   const TableTwiddles<R> twl{s_tab};
   static_assert(NT % 2 == 0 && NB % 2 == 0, "output parity per thread");
   const bool odd = (threadIdx.x & 1) != 0;
-  const double half = odd ? 0.5 : 0.0;
   cplx<R> acc[IT][RAD];
   Screen<R> sc[IT][RAD];
 #pragma unroll
@@ -876,7 +852,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
     if (!kPrefetch) fetch(k, on, cur);
     auto ld = [&](int, int, int it, int r) { return cur[it][r]; };
     auto st = [&](int, int, int it, int r, cplx<R> v) {
-      const auto w = sc[it][r].next(g, k, half);
+      const auto w = sc[it][r].next(g, k);
       acc[it][r] = cadd(acc[it][r], cmul(v, cplx<R>{(R)w.re, (R)w.im}));
     };
     fft_line<R, LOGN, 1, NT>(lds, ld, st, twl, (R)1);
