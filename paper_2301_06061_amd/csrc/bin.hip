@@ -437,8 +437,8 @@ __global__ __launch_bounds__(256) void k_tile_work(
 //   col_*         bucket-major exclusive scan of the block-major
 //                 histograms in place: offset of (bucket, block), and the
 //                 bucket bounds
-//   part_chunks   records per bucket -> chunks of one workgroup each
-//   (scan)        first chunk of every bucket
+//   part_bounds   one workgroup: bucket bounds and the first level-2 chunk
+//                 of every bucket (chunks of one staging area each)
 //   part_scatter1 records built from the inputs, staged in LDS in bucket
 //                 order, written to their bucket offsets, with their keys
 //                 in a separate array (level 2 reads only the keys to
@@ -574,7 +574,19 @@ __global__ __launch_bounds__(256) void k_col_apply(
   if (c >= nc) return;
   const uint32_t b0 = s * seglen, b1 = min(b0 + seglen, nb);
   uint32_t run = bounds[c] + seg[(size_t)s * nc + c];
-  for (uint32_t b = b0; b < b1; ++b) {
+  // Eight loads in flight before the eight stores.
+  uint32_t b = b0;
+  for (; b + 8 <= b1; b += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = hist[(size_t)(b + u) * nc + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      hist[(size_t)(b + u) * nc + c] = run;
+      run += v[u];
+    }
+  }
+  for (; b < b1; ++b) {
     uint32_t* p = hist + (size_t)b * nc + c;
     const uint32_t v = *p;
     *p = run;
@@ -639,13 +651,41 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter1(
   }
 }
 
-// Chunks per bucket (bucket c holds records bounds[c] .. bounds[c + 1]).
-__global__ __launch_bounds__(256) void k_part_chunks(
-    const uint32_t* __restrict__ bounds, uint32_t nbuckets, uint32_t chunk,
-    uint32_t* __restrict__ nchunks) {
-  const uint32_t c = blockIdx.x * 256u + threadIdx.x;
-  if (c >= nbuckets) return;
-  nchunks[c] = (bounds[c + 1] - bounds[c] + chunk - 1) / chunk;
+// One workgroup: bucket totals (in bounds[], from col_seg) -> bucket bounds
+// (exclusive scan, bounds[nbuckets] = total), then chunks per bucket ->
+// first chunk of every bucket (chunk0[nbuckets] = total chunks).  Each
+// thread takes a contiguous run of buckets (nbuckets <= 16384).
+__global__ __launch_bounds__(kPartThreads) void k_part_bounds(
+    uint32_t* __restrict__ bounds, uint32_t nbuckets, uint32_t chunk,
+    uint32_t* __restrict__ chunk0) {
+  __shared__ uint32_t s_tmp[kPartThreads / 64];
+  const uint32_t per = (nbuckets + kPartThreads - 1) / kPartThreads;
+  const uint32_t c0 = threadIdx.x * per;
+  const uint32_t c1 = min(c0 + per, nbuckets);
+  uint32_t tot[16];
+  uint32_t acc = 0;
+  for (uint32_t c = c0; c < c1; ++c) {
+    tot[c - c0] = bounds[c];
+    acc += tot[c - c0];
+  }
+  uint32_t total;
+  uint32_t run = block_exclusive_scan(acc, s_tmp, &total);
+  uint32_t nch = 0;
+  for (uint32_t c = c0; c < c1; ++c) {
+    bounds[c] = run;
+    run += tot[c - c0];
+    nch += (tot[c - c0] + chunk - 1) / chunk;
+  }
+  uint32_t ntotal;
+  uint32_t crun = block_exclusive_scan(nch, s_tmp, &ntotal);
+  for (uint32_t c = c0; c < c1; ++c) {
+    chunk0[c] = crun;
+    crun += (tot[c - c0] + chunk - 1) / chunk;
+  }
+  if (threadIdx.x == 0) {
+    bounds[nbuckets] = total;
+    chunk0[nbuckets] = ntotal;
+  }
 }
 
 // Bucket of chunk ch: the last c with chunk0[c] <= ch (chunk0 exclusive
@@ -704,7 +744,18 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scan2(
   const uint32_t q0 = chunk0[c], q1 = chunk0[c + 1];
   for (uint32_t f = threadIdx.x; f < span; f += kPartThreads) {
     uint32_t run = 0;
-    for (uint32_t q = q0; q < q1; ++q) {
+    uint32_t q = q0;
+    for (; q + 8 <= q1; q += 8) {  // eight loads in flight, then the stores
+      uint32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = hist2[(size_t)(q + u) * span + f];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        hist2[(size_t)(q + u) * span + f] = run;
+        run += v[u];
+      }
+    }
+    for (; q < q1; ++q) {
       uint32_t* p = hist2 + (size_t)q * span + f;
       const uint32_t v = *p;
       *p = run;
@@ -796,15 +847,18 @@ void launch_part_scan1(int64_t m, const PartWork& w, hipStream_t st) {
                        w.hist1, nb1, C, seglen, w.seg);
     hipLaunchKernelGGL(k_col_seg, cg, dim3(256), 0, st, w.seg, nseg, C,
                        w.bounds);
-    launch_exclusive_scan(w.bounds, w.bounds, (int64_t)C, w.sums, st);
-    hipLaunchKernelGGL(k_col_apply, dim3(cg.x, nseg), dim3(256), 0, st,
-                       w.hist1, nb1, C, seglen, w.seg, w.bounds);
   } else {
     launch_zero_u32(w.bounds, (int64_t)C + 1, st);
   }
-  hipLaunchKernelGGL(k_part_chunks, cg, dim3(256), 0, st, w.bounds, C,
-                     (uint32_t)V, w.chunk0);
-  launch_exclusive_scan(w.chunk0, w.chunk0, (int64_t)C, w.sums, st);
+  hipLaunchKernelGGL(k_part_bounds, dim3(1), dim3(kPartThreads), 0, st,
+                     w.bounds, C, (uint32_t)V, w.chunk0);
+  if (m > 0) {
+    const uint32_t nb1 = part_nb1(m, V);
+    const uint32_t nseg = nb1 < (uint32_t)kPartSegs ? nb1 : (uint32_t)kPartSegs;
+    const uint32_t seglen = (nb1 + nseg - 1) / nseg;
+    hipLaunchKernelGGL(k_col_apply, dim3(cg.x, nseg), dim3(256), 0, st,
+                       w.hist1, nb1, C, seglen, w.seg, w.bounds);
+  }
 }
 
 template <typename R>
