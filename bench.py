@@ -65,7 +65,12 @@ def algorithmic_bytes(name, wl, elem, m, st=None):
                       partials written and read back by the merge;
       bin_count:      uvw read (24 B) + key/rank written (8 B) per vis;
       bin_scatter:    uvw, vis, weight, key/rank and the key offset read,
-                      one record written per visibility.
+                      one record written per visibility;
+      part_count1:    uvw read + key/rank written per vis (as bin_count);
+      part_scatter1:  key/rank, uvw, vis, weight read, one record and its
+                      4-byte key written per visibility;
+      part_count2:    key read + rank written (4 + 4 B) per vis;
+      part_scatter2:  record, key and rank read, record written per vis.
     """
     cells = wl.nu * wl.nv * wl.nw
     img = wl.nu * wl.nv
@@ -88,6 +93,10 @@ def algorithmic_bytes(name, wl, elem, m, st=None):
         }
     full["bin_count"] = m * (24 + 8)
     full["bin_scatter"] = m * (24 + elem + 4 + 8 + 4 + rec)
+    full["part_count1"] = m * (24 + 8)
+    full["part_scatter1"] = m * (8 + 24 + elem + 4 + rec + 4)
+    full["part_count2"] = m * (4 + 4)
+    full["part_scatter2"] = m * (rec + 4 + 4 + rec)
     return full.get(name)
 
 
