@@ -534,6 +534,61 @@ def bench_with_copies(args, torch, plan, wl, img):
             "d2h_bytes": int(h_img.nbytes)}
 
 
+def fft_references(planes: int = 32, n: int = 4096) -> dict:
+    """Reference rates for the two transform passes on the headline stack
+    (planes x n x n complex64, dense).  First the access-pattern probe (a
+    separate program; its source states the patterns): the HBM rate of
+    moving column blocks with 64- or 128-byte row segments, strided or
+    contiguous on each side, and of the row pass's reads.  Then torch.fft
+    (the vendor FFT library) along columns and along rows, and plain copies
+    whose reads are row segments of 32, 64 or 128 bytes at a stride of one
+    row, written contiguously.  Rates are bytes read + written per
+    second."""
+    import subprocess
+    exe = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                       "paper_2301_06061_amd", "probes", "access_patterns")
+    probe = {"error": "not built (run __graft_entry__.build())"}
+    if os.path.exists(exe):
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+        try:
+            probe = json.loads(r.stdout.strip().splitlines()[-1])
+        except (ValueError, IndexError):
+            probe = {"error": f"rc {r.returncode}: {r.stderr[-300:]}"}
+    import torch
+    dev = torch.device("cuda", 0)
+    x = torch.randn(planes, n, n, dtype=torch.complex64, device=dev)
+    gb = 2.0 * x.numel() * 8 / 1e9
+
+    def t(f, reps=5):
+        f()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            f()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = {"stack": f"{planes} x {n} x {n} complex64 ({gb / 2:.2f} GB)",
+           "access_patterns": probe}
+    for name, f in [("torch_fft_columns", lambda: torch.fft.fft(x, dim=1)),
+                    ("torch_fft_rows", lambda: torch.fft.fft(x, dim=2)),
+                    ("torch_fft2", lambda: torch.fft.fft2(x)),
+                    ("copy_contiguous", lambda: x.clone())]:
+        ms = t(f)
+        out[name] = {"ms": round(ms, 3), "tb_s": round(gb / ms, 2)}
+    y = torch.empty_like(x)
+    for w in (4, 8, 16):
+        src = x.view(planes, n, n // w, w).permute(0, 2, 1, 3)
+        dst = y.view(planes, n // w, n, w)
+        ms = t(lambda: dst.copy_(src))
+        out[f"copy_{w * 8}B_row_segments"] = {"ms": round(ms, 3),
+                                               "tb_s": round(gb / ms, 2)}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -559,6 +614,12 @@ def main(argv=None):
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline workload (no further legs, no "
                          "CPU baseline)")
+    ap.add_argument("--fft-references", action="store_true",
+                    help="only time references for the transform passes on "
+                         "the headline stack shape and print them: the "
+                         "access-pattern probe (paper_2301_06061_amd/probes,"
+                         " built by build()) and torch.fft along columns "
+                         "and rows")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run one plain elementwise kernel that reads "
                          "1 GiB and writes 1 GiB (a reference for HBM byte "
@@ -569,6 +630,9 @@ def main(argv=None):
                           "(the imaging path has no multi-GPU mode); "
                           "--gpus must be 1"}))
         return 2
+    if args.fft_references:
+        print(json.dumps(fft_references()))
+        return 0
     if args.headline_only:
         args.no_cpu_baseline = args.no_large = args.no_batch = True
         args.no_degrid = args.no_copies = True

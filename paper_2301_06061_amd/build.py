@@ -4,7 +4,10 @@ Usage: python -m paper_2301_06061_amd.build [--jobs N]
 
 Every HIP source is compiled with hipcc for gfx950 only; object files go to
 ``paper_2301_06061_amd/_build`` and the shared library to
-``paper_2301_06061_amd/libwstack.so``.  This always recompiles.
+``paper_2301_06061_amd/libwstack.so``.  The memory access-pattern probe that
+``bench.py --access-probes`` runs (a separate program, not part of the
+library) is built next to its source in ``probes/``.  This always
+recompiles.
 """
 from __future__ import annotations
 
@@ -23,6 +26,8 @@ LIB = os.path.join(HERE, "libwstack.so")
 ARCH = "gfx950"
 
 SOURCES = ["abi.cpp", "bin.hip", "grid.hip", "fft.hip", "clean.hip"]
+PROBES = os.path.join(HERE, "probes")
+PROBE_SOURCES = ["access_patterns.hip"]
 
 
 def hipcc() -> str:
@@ -55,10 +60,21 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _compile_probe(src: str) -> str:
+    exe = os.path.join(PROBES, os.path.splitext(src)[0])
+    cmd = [hipcc()] + _flags() + [os.path.join(PROBES, src), "-o", exe]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"compiling probe {src} failed:\n{res.stderr}")
+    return exe
+
+
 def build(jobs: int = 4, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        probes = ex.map(_compile_probe, PROBE_SOURCES)
         objs = list(ex.map(_compile, SOURCES))
+        list(probes)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] \
         + objs
