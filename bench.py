@@ -43,7 +43,7 @@ def log(*a):
 
 def record_bytes(elem):
     """Bytes of one binned record (FP32 path: elem 8; FP64: 16)."""
-    return 32 if elem == 8 else 48
+    return 24 if elem == 8 else 40
 
 
 def algorithmic_bytes(name, wl, elem, m, st=None):
@@ -100,10 +100,20 @@ def algorithmic_bytes(name, wl, elem, m, st=None):
     return full.get(name)
 
 
+# Headers every kernel source includes: a change there changes the kernels.
+_KERNEL_HEADERS = ("ws_common.h", "ws_kernels.h")
+
+
 def source_digest(path):
+    """Digest of a kernel's source file together with the shared kernel
+    headers (record layout, geometry, launch declarations)."""
     import hashlib
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2301_06061_amd", "csrc")
+    for p in (path,) + tuple(os.path.join(csrc, n) for n in _KERNEL_HEADERS):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def pmc_traffic(kernel):

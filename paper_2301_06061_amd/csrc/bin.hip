@@ -332,7 +332,6 @@ __global__ __launch_bounds__(256) void k_bin_scatter(
   }
   r.cell = pack_cell(i0, j0);
   r.idx = (uint32_t)gi;
-  r.pad0 = r.pad1 = 0u;
   rec[pos] = r;
 }
 
@@ -606,6 +605,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter1(
   constexpr int PER = V / kPartThreads;
   extern __shared__ __align__(16) unsigned char s_raw[];
   Record<R>* s_rec = reinterpret_cast<Record<R>*>(s_raw);  // V records
+  uint32_t* s_key = reinterpret_cast<uint32_t*>(s_rec + V);  // their keys
   const uint32_t b = blockIdx.x;
   const int64_t base = (int64_t)b * V;
   const uint32_t* ex = hist1x + (size_t)b * nbuckets;
@@ -636,18 +636,18 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter1(
     }
     r.cell = pack_cell(i0, j0);
     r.idx = (uint32_t)gi;
-    r.pad0 = kr.x;  // the key, for the write-out and level 2
-    r.pad1 = 0u;
-    s_rec[ex[kr.x / span] + kr.y] = r;
+    const uint32_t slot = ex[kr.x / span] + kr.y;
+    s_rec[slot] = r;
+    s_key[slot] = kr.x;  // for the write-out and level 2
   }
   __syncthreads();
   const uint32_t n = btot[b];
   for (uint32_t i = threadIdx.x; i < n; i += kPartThreads) {
-    const Record<R> r = s_rec[i];
-    const uint32_t c = r.pad0 / span;
+    const uint32_t key = s_key[i];
+    const uint32_t c = key / span;
     const uint32_t pos = off[c] + (i - ex[c]);
-    rec[pos] = r;
-    keys[pos] = r.pad0;
+    rec[pos] = s_rec[i];
+    keys[pos] = key;
   }
 }
 
@@ -783,6 +783,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter2(
     const Record<R>* __restrict__ rec1, Record<R>* __restrict__ rec) {
   extern __shared__ __align__(16) unsigned char s_raw[];
   Record<R>* s_rec = reinterpret_cast<Record<R>*>(s_raw);  // V records
+  uint32_t* s_fine = reinterpret_cast<uint32_t*>(s_rec + V);  // fine keys
   const uint32_t ch = blockIdx.x;
   if (ch >= chunk0[nbuckets]) return;
   const uint32_t c = chunk_bucket(chunk0, nbuckets, ch);
@@ -791,13 +792,16 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter2(
   const uint32_t* off = hist2 + (size_t)ch * span;
   const uint32_t* ex = hist2x + (size_t)ch * span;
   const uint32_t kb = c * span;
-  for (uint32_t r = start + threadIdx.x; r < end; r += kPartThreads)
-    s_rec[ex[keys[r] - kb] + rank2[r]] = rec1[r];
+  for (uint32_t r = start + threadIdx.x; r < end; r += kPartThreads) {
+    const uint32_t f = keys[r] - kb;
+    const uint32_t slot = ex[f] + rank2[r];
+    s_rec[slot] = rec1[r];
+    s_fine[slot] = f;
+  }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < end - start; i += kPartThreads) {
-    const Record<R> r = s_rec[i];
-    const uint32_t f = r.pad0 - kb;
-    rec[off[f] + (i - ex[f])] = r;
+    const uint32_t f = s_fine[i];
+    rec[off[f] + (i - ex[f])] = s_rec[i];
   }
 }
 
@@ -808,8 +812,8 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter2(
 namespace {
 template <typename R>
 constexpr int part_block() {
-  // LDS staging of one workgroup: 4096 32-byte (FP32) or 2048 48-byte
-  // (FP64) records.
+  // LDS staging of one workgroup: 4096 24-byte (FP32) or 2048 40-byte
+  // (FP64) records and their keys.
   return sizeof(R) == 4 ? 4096 : 2048;
 }
 int part_block_of(int elem) { return elem == 8 ? 4096 : 2048; }
@@ -868,9 +872,9 @@ void launch_part_scatter1(const Geo& g, const VisSource& src, int64_t m,
   if (m == 0) return;
   constexpr int V = part_block<R>();
   hipLaunchKernelGGL((k_part_scatter1<R, V>), dim3(part_nb1(m, V)),
-                     dim3(kPartThreads), (size_t)V * sizeof(Record<R>), st, g,
-                     src, m, w.keyrank, w.hist1, w.hist1x, w.btot, w.span,
-                     w.nbuckets, (Record<R>*)w.rec1, w.keys, degrid,
+                     dim3(kPartThreads), (size_t)V * (sizeof(Record<R>) + 4),
+                     st, g, src, m, w.keyrank, w.hist1, w.hist1x, w.btot,
+                     w.span, w.nbuckets, (Record<R>*)w.rec1, w.keys, degrid,
                      (cplx<R>*)vis_out);
 }
 
@@ -898,8 +902,8 @@ void launch_part_scatter2(int64_t m, const PartWork& w, hipStream_t st) {
   constexpr int V = part_block<R>();
   hipLaunchKernelGGL((k_part_scatter2<R, V>),
                      dim3(part_max_chunks(m, w.nbuckets, V)),
-                     dim3(kPartThreads), (size_t)V * sizeof(Record<R>), st,
-                     w.keys, w.bounds, w.chunk0, w.nbuckets, w.span, w.rank2,
+                     dim3(kPartThreads), (size_t)V * (sizeof(Record<R>) + 4),
+                     st, w.keys, w.bounds, w.chunk0, w.nbuckets, w.span, w.rank2,
                      w.hist2, w.hist2x, (const Record<R>*)w.rec1,
                      (Record<R>*)w.rec);
 }

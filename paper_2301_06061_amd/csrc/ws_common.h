@@ -208,17 +208,20 @@ __host__ __device__ inline uint32_t bin_key(const Geo& g, int i0, int j0,
 }
 
 // One binned visibility, stored whole (array of structures) so that the
-// scatter of a visibility into its bin is a single 32- or 48-byte write
-// and the gridder reads a batch of records with wide loads.
+// scatter of a visibility into its bin is one 24-byte (FP32) or 40-byte
+// (FP64) write and the gridder reads a record with three 8-byte loads
+// (FP32); no padding rides in the binning and gridding streams.
 //   dx, dy  offset of the exact position from the nearest cell
 //   vr, vi  weighted visibility (gridding) or weight and 0 (degridding)
 //   cell    packed nearest cell (pack_cell)
 //   idx     input index of the visibility (degridding)
 template <typename R>
-struct alignas(16) Record {
+struct alignas(8) Record {
   R dx, dy, vr, vi;
-  uint32_t cell, idx, pad0, pad1;
+  uint32_t cell, idx;
 };
+static_assert(sizeof(Record<float>) == 24 && sizeof(Record<double>) == 40,
+              "records carry no padding");
 
 __host__ __device__ inline uint32_t pack_cell(int i0, int j0) {
   return (uint32_t)(i0 + kCellBias) | ((uint32_t)(j0 + kCellBias) << 16);

@@ -18,10 +18,10 @@ def test_algorithmic_bytes_of_the_column_pass_and_gridding():
     # read the stack once, read and write the image once
     assert bench.algorithmic_bytes("row_screen_sum", _W, 8, 10**7) == (
         cells * 8 + 2 * 4096 * 4096 * 8)
-    # every cell written once plus one 32-byte record (48 for FP64) read
-    assert bench.algorithmic_bytes("grid", _W, 8, 10**7) == cells * 8 + 32e7
+    # every cell written once plus one 24-byte record (40 for FP64) read
+    assert bench.algorithmic_bytes("grid", _W, 8, 10**7) == cells * 8 + 24e7
     assert bench.algorithmic_bytes("grid", _W, 16, 10**7) == (
-        cells * 16 + 48e7)
+        cells * 16 + 40e7)
     assert bench.algorithmic_bytes("no_such_kernel", _W, 8, 1) is None
 
 
@@ -32,6 +32,11 @@ def test_traffic_needs_the_recorded_source(tmp_path, monkeypatch):
     src_dir.mkdir()
     src = src_dir / "k.hip"
     src.write_text("kernel source\n")
+    csrc = root / "paper_2301_06061_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for name in ("ws_common.h", "ws_kernels.h"):
+        (csrc / name).write_text(f"// {name}\n")
+    monkeypatch.setattr(bench, "ROOT", str(root))
     digest = bench.source_digest(str(src))
     (root / "profiles" / "k_config2_fp32_pmc.txt").write_text(
         "# header line: not a value\n"
@@ -41,8 +46,12 @@ def test_traffic_needs_the_recorded_source(tmp_path, monkeypatch):
         "write_kib_per_launch: 50.0\n"
         "fetch_scale: 2.0\n"
         "write_scale: 1.0\n")
-    monkeypatch.setattr(bench, "ROOT", str(root))
     assert bench.pmc_traffic("k") == 100.0 * 1024 * 2.0 + 50.0 * 1024 * 1.0
+    # a change to a shared kernel header changes the kernels too
+    (csrc / "ws_common.h").write_text("// record layout changed\n")
+    assert bench.pmc_traffic("k") is None
+    (csrc / "ws_common.h").write_text("// ws_common.h\n")
+    assert bench.pmc_traffic("k") is not None
     src.write_text("kernel source, changed\n")
     assert bench.pmc_traffic("k") is None
     assert bench.pmc_traffic("missing") is None
@@ -73,11 +82,11 @@ def test_algorithmic_bytes_from_tile_statistics():
     assert bench.algorithmic_bytes("row_screen_sum", _W, 8, 10**7, st) == (
         10 * strip_b + 2 * 4096 * 4096 * 8)
     assert bench.algorithmic_bytes("grid", _W, 8, 10**7, st) == (
-        100 * tile_b + 12345 * 32 + 2 * 10 * tile_b)
+        100 * tile_b + 12345 * 24 + 2 * 10 * tile_b)
     # binning is charged per visibility either way
     assert bench.algorithmic_bytes("bin_count", _W, 8, 10, st) == 10 * 32
     assert bench.algorithmic_bytes("bin_scatter", _W, 8, 10, st) == (
-        10 * (24 + 8 + 4 + 8 + 4 + 32))
+        10 * (24 + 8 + 4 + 8 + 4 + 24))
 
 
 def test_gpu_count_other_than_one_is_refused(capsys):
