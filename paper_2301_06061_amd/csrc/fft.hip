@@ -745,6 +745,18 @@ struct Screen {
   }
 };
 
+// The plane sum sum_k F_k ph_0 step^k by Horner's rule, planes taken last
+// to first: acc <- acc * step + F_k, and ph_0 * acc once at the end.  The
+// same products as handing out ph_k (the contribution of plane k is
+// multiplied by the step k times either way), in four fused multiply-adds
+// per sample and plane instead of eight.
+template <typename R>
+__device__ __forceinline__ cplx<R> horner_step(cplx<R> acc, cplx<R> step,
+                                               cplx<R> f) {
+  return {fma(acc.re, step.re, fma(-acc.im, step.im, f.re)),
+          fma(acc.re, step.im, fma(acc.im, step.re, f.im))};
+}
+
 // Grid correction of pixel (p, q): 1 / (c psi(f_p) psi(f_q)) from the
 // plan's table, or 1 when the plan has none (uniform branch).  Imaging
 // multiplies the plane sum by it; degridding multiplies its input image by
@@ -769,11 +781,9 @@ __global__ __launch_bounds__(256) void k_wcorrect(const cplx<R>* __restrict__ F,
   sc.init(g, p, q, false);
   cplx<R> acc = {(R)0, (R)0};
   const int64_t src = (int64_t)stack_row(g, q) * g.nu + p;
-  for (int k = 0; k < g.nw; ++k) {
-    const cplx<R> f = F[(size_t)k * npix + src];
-    acc = cadd(acc, cmul(f, sc.next(g, k)));
-  }
-  img[pix] = cadd(img[pix], corrected(g, p, q, acc));
+  for (int k = g.nw - 1; k >= 0; --k)
+    acc = horner_step(acc, sc.step, F[(size_t)k * npix + src]);
+  img[pix] = cadd(img[pix], corrected(g, p, q, cmul(sc.ph, acc)));
 }
 
 // Row transform of every plane + screen + plane sum into image row q.
@@ -806,8 +816,8 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
       if (NB % NT == 0 || threadIdx.x + it * NT < NB)
         sc[it][r].init(g, p, q, false, odd);
     }
-  // Row q of plane k + 1 can be loaded into registers while plane k is
-  // being transformed, so the HBM reads overlap the LDS stages.
+  // Row q of the next plane (k - 1) can be loaded into registers while
+  // plane k is being transformed, so the HBM reads overlap the LDS stages.
   using F0 = Stage<R, LOGN, 1, NT, 0>;
   constexpr int IT0 = F0::IT, RAD0 = F0::RAD, NB0 = F0::NB;
   // FP32: two workgroups per CU (register-capped) overlap each other's
@@ -817,7 +827,7 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
   // Column-strip marks (non-null; used when T is 64, so that the 64
   // samples one wavefront loads lie in one strip): samples of strips that
   // hold no data are not read, since gridding left those columns zero and
-  // the column transform kept them so.  The marks of plane k + 1 are
+  // the column transform kept them so.  The marks of the next plane are
   // loaded (uniform loads, issued together) while plane k is transformed.
   const bool skip = g.T == 64 && NB0 % 64 == 0;
   auto marks = [&](int k, uint32_t (&on)[IT0][RAD0]) {
@@ -843,17 +853,17 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
                                        : cplx<R>{(R)0, (R)0};
       }
   };
+  // Planes last to first (Horner's rule for the screen, horner_step).
   uint32_t on[IT0][RAD0], on_next[IT0][RAD0];
-  marks(0, on);
-  if (kPrefetch) fetch(0, on, cur);
-  for (int k = 0; k < g.nw; ++k) {
-    marks(k + 1, on_next);
-    if (kPrefetch && k + 1 < g.nw) fetch(k + 1, on_next, nxt);
+  marks(g.nw - 1, on);
+  if (kPrefetch) fetch(g.nw - 1, on, cur);
+  for (int k = g.nw - 1; k >= 0; --k) {
+    marks(k > 0 ? k - 1 : 0, on_next);
+    if (kPrefetch && k > 0) fetch(k - 1, on_next, nxt);
     if (!kPrefetch) fetch(k, on, cur);
     auto ld = [&](int, int, int it, int r) { return cur[it][r]; };
     auto st = [&](int, int, int it, int r, cplx<R> v) {
-      const auto w = sc[it][r].next(g, k);
-      acc[it][r] = cadd(acc[it][r], cmul(v, cplx<R>{(R)w.re, (R)w.im}));
+      acc[it][r] = horner_step(acc[it][r], sc[it][r].step, v);
     };
     fft_line<R, LOGN, 1, NT>(lds, ld, st, twl, (R)1);
     if (kPrefetch) {
@@ -883,8 +893,9 @@ __global__ __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 1) void k_row_screen_sum(
     for (int r = 0; r < RAD; ++r) {
       const int j = threadIdx.x + it * NT;
       if (NB % NT == 0 || j < NB)
-        out[j + r * NB] =
-            cadd(old[it][r], corrected(g, j + r * NB, q, acc[it][r]));
+        out[j + r * NB] = cadd(
+            old[it][r],
+            corrected(g, j + r * NB, q, cmul(sc[it][r].ph, acc[it][r])));
     }
 }
 
