@@ -375,16 +375,39 @@ __global__ __launch_bounds__(256) void k_tile_work(
         work += offsets[hi[s]] - offsets[lo[s]];
     }
   }
+  // Busy tiles are listed per wavefront (the gridder takes items in list
+  // order, and wavefront-sized runs of neighbouring tiles measured best);
+  // idle tiles and the total record reads (diagnostics) need no order and
+  // take one atomic per workgroup, which keeps same-address atomics, the
+  // cost of this kernel, few.
   const uint32_t ib = wave_append(&counters[4], live && work > 0);
-  const uint32_t ii = wave_append(&counters[5], live && work == 0);
-  // Total record reads of the gridding items (diagnostics): one 64-bit
-  // atomic per wavefront.
+  __shared__ uint32_t s_idle[4];
+  __shared__ unsigned long long s_reads[4];
+  __shared__ uint32_t s_base;
+  static_assert(4 * 64 == 256, "four wavefronts");
+  const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+  const unsigned long long imask = __ballot(live && work == 0);
   unsigned long long wsum = work;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1)
     wsum += (unsigned long long)__shfl_xor((long long)wsum, o, 64);
-  if ((threadIdx.x & 63) == 0 && wsum != 0)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&counters[6]), wsum);
+  if (lane == 0) {
+    s_idle[wave] = (uint32_t)__popcll(imask);
+    s_reads[wave] = wsum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t n = s_idle[0] + s_idle[1] + s_idle[2] + s_idle[3];
+    const unsigned long long reads =
+        s_reads[0] + s_reads[1] + s_reads[2] + s_reads[3];
+    s_base = n != 0 ? atomicAdd(&counters[5], n) : 0u;
+    if (reads != 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&counters[6]), reads);
+  }
+  __syncthreads();
+  uint32_t ii = s_base;
+  for (int w = 0; w < wave; ++w) ii += s_idle[w];
+  ii += (uint32_t)__popcll(imask & ((1ull << lane) - 1ull));
   if (!live) return;
   if (work > 0) busy[ib] = (uint32_t)t;
   else idle[ii] = (uint32_t)t;
