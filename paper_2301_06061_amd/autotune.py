@@ -2,9 +2,13 @@
 
 For a shape class - grid size, plane count, kernel support and type,
 precision and the visibility count rounded to a half decade - it times the
-gridding step (binning + tile accumulation + merge) on the caller's own
-data for every candidate (tile edge T, records per work item C) and keeps
-the fastest.
+one-call imaging step a batch runs per channel (binning, tile accumulation,
+merge, column FFT and fused rows + screen + plane sum, ws_grid_image) on
+the caller's own data for every candidate (tile edge T, records per work
+item C) and keeps the fastest.  The whole step, not the gridding alone:
+the tile edge also decides whether the imaging may leave tiles without
+records unwritten and skip them (64-cell tiles), which a gridding-only
+timing does not see.
 Results are cached in a JSON file keyed by GPU architecture and shape
 class ($WSTACK_AUTOTUNE_CACHE, default ~/.cache/wstack/autotune.json).
 The kernel support and type are not tuned: they change the result, so
@@ -83,17 +87,23 @@ def _valid_tile(t, wl) -> bool:
     return t <= min(wl.nu, wl.nv) and t > wl.support - 1
 
 
-def time_grid(plan: WStackPlan, uvw, vis, weight, reps: int = 3) -> float:
-    """Median milliseconds of one gridding call (after one warm-up)."""
-    plan.reset()
-    plan.grid(uvw, vis, weight)
+def time_step(plan: WStackPlan, uvw, vis, weight, reps: int = 3) -> float:
+    """Median milliseconds of one one-call grid-and-image step into a zeroed
+    image (after one warm-up)."""
+    img = plan.new_image()
+
+    def step():
+        plan.reset()
+        img.zero_()
+        plan.grid_image(uvw, vis, weight, image=img)
+
+    step()
     times = []
     for _ in range(reps):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
-        plan.reset()
         a.record()
-        plan.grid(uvw, vis, weight)
+        step()
         b.record()
         b.synchronize()
         times.append(a.elapsed_time(b))
@@ -126,7 +136,7 @@ def tune(wl, uvw, vis, weight=None, precision: str = "fp32",
                               wl.w_min, wl.w_max, wl.support, wl.sigma,
                               precision, max_vis=max(1, m), tile=t, chunk=c,
                               kernel=kernel, beta=getattr(wl, "beta", 0.0))
-            ms = time_grid(plan, uvw, vis, weight, reps)
+            ms = time_step(plan, uvw, vis, weight, reps)
             plan.close()
             del plan
             trials[f"T{t}_C{c}"] = ms

@@ -510,6 +510,8 @@ ws_status bin_records(ws_plan* pl, int64_t m, const VisSource& src,
   return WS_OK;
 }
 
+bool lazy_ok(const ws_plan* pl);
+
 template <typename R>
 GridJob<R> make_job(ws_plan* pl, int accumulate) {
   const Layout& L = pl->L;
@@ -529,6 +531,7 @@ GridJob<R> make_job(ws_plan* pl, int accumulate) {
   j.planes = static_cast<cplx<R>*>(pl->planes);
   j.partials = pl->w<cplx<R>>(L.o_partials);
   j.accumulate = accumulate;
+  j.zero_idle = lazy_ok(pl) ? 0 : 1;
   return j;
 }
 
@@ -833,11 +836,13 @@ ws_status batch_image_impl(ws_batch* b, const int64_t* m,
   ws_plan* p0 = b->plans[0];
   uint32_t* queue = reinterpret_cast<uint32_t*>(b->work + batch_jobs_bytes(b->n));
   WS_TRY(launch(p0, "zero_counts", [&] { launch_zero_u32(queue, 1, b->stream); }));
-  // As in ws_grid_image: when every plan's imaging reads by tile counts
-  // and strip marks, tiles without records are never written.
-  bool lazy = true;
-  for (int i = 0; i < b->n; ++i) lazy = lazy && lazy_ok(b->plans[i]);
-  if (!lazy) {
+  // As in ws_grid_image, plan by plan: where the imaging reads by tile
+  // counts and strip marks, tiles without records are never written; the
+  // other plans' idle tiles get their zeros (the batched zeroing kernel
+  // skips the jobs that need none).
+  bool all_lazy = true;
+  for (int i = 0; i < b->n; ++i) all_lazy = all_lazy && lazy_ok(b->plans[i]);
+  if (!all_lazy) {
     uint64_t tiles = 0;
     for (int i = 0; i < b->n; ++i) tiles += (uint64_t)b->plans[i]->g.ntiles;
     WS_TRY(launch(p0, "zero_idle", [&] {
@@ -854,7 +859,7 @@ ws_status batch_image_impl(ws_batch* b, const int64_t* m,
     ws_plan* pl = b->plans[i];
     WS_TRY(merge_impl<R>(pl, 0));
     pl->state = kGridded;
-    ws_status st = image_impl<R>(pl, images[i], lazy);
+    ws_status st = image_impl<R>(pl, images[i], lazy_ok(pl));
     pl->state = kEmpty;
     WS_TRY(st);
   }

@@ -621,7 +621,7 @@ __global__ __launch_bounds__(256) void k_zero_idle_batch(
     b -= (uint32_t)jobs[p].g.ntiles;
     ++p;
   }
-  if (p >= njobs || b >= jobs[p].counters[5]) return;
+  if (p >= njobs || !jobs[p].zero_idle || b >= jobs[p].counters[5]) return;
   zero_idle_tile(jobs[p].g, jobs[p].idle, b, jobs[p].planes);
 }
 

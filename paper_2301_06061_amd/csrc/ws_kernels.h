@@ -142,6 +142,7 @@ struct GridJob {
   cplx<R>* planes;
   cplx<R>* partials;
   int accumulate;
+  int zero_idle;              // batch: this job's idle tiles need zeros
 };
 
 // Descriptors of the gridding work items (after launch_tile_work), one

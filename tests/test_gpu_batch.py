@@ -95,9 +95,35 @@ def test_batch_graph_replays_match_oracle(precision, tol):
     b.close()
 
 
+def test_batch_mixes_lazy_and_zeroed_plans():
+    """Plans whose imaging reads by tile counts (tile edge 64, 512 columns
+    or more: tiles without records stay unwritten) next to plans whose
+    idle tiles must be zeroed (tile edge 32, or narrower grids), in one
+    batch: every image against the oracle, on two runs in a row (the
+    second run meets the first run's stack contents) and a graph replay."""
+    shapes = [(512, 2, 2000, 64), (512, 2, 2000, 32), (256, 2, 1000, 0),
+              (1024, 3, 3000, 64)]
+    wls = [synth.random_case(40 + i, n=n, nw=nw, support=7, m=m, law="core",
+                             precision=0)
+           for i, (n, nw, m, _) in enumerate(shapes)]
+    uvw, vis, wt = _dev(wls)
+    b = BatchedImager(wls, uvw, vis, wt, precision="fp32",
+                      params=[(t, 0) for (_, _, _, t) in shapes])
+    refs = [o.image(o.Params.of(w), w.uvw, w.vis, w.weight) for w in wls]
+    for run in range(2):
+        got = [t.cpu().numpy() for t in b.run()]
+        for i in range(len(wls)):
+            assert _err(got[i], refs[i], False) <= 1e-5, (run, i)
+    b.capture()
+    got = [t.cpu().numpy() for t in b.replay()]
+    for i in range(len(wls)):
+        assert _err(got[i], refs[i], False) <= 1e-5, ("replay", i)
+    b.close()
+
+
 def test_autotuner_cache_round_trip_and_tuned_batch(tmp_path, monkeypatch):
-    """tune() times every valid (tile, chunk) candidate on the caller's
-    data, stores the winner per shape class, answers the second time from
+    """tune() times the one-call step of every valid (tile, chunk) candidate
+    on the caller's data, stores the winner per shape class, answers the second time from
     the cache without timing anything, and the batch built from the tuned
     parameters matches the oracle."""
     from paper_2301_06061_amd import autotune
@@ -124,7 +150,7 @@ def test_autotuner_cache_round_trip_and_tuned_batch(tmp_path, monkeypatch):
         assert len(e["trials"]) == len(valid) * len(autotune.CHUNKS)
         assert e["ms"] == min(e["trials"].values())
     # second round: answered from the cache, nothing timed
-    monkeypatch.setattr(autotune, "time_grid",
+    monkeypatch.setattr(autotune, "time_step",
                         lambda *a, **k: pytest.fail("timed despite cache"))
     for i, wl in enumerate(wls):
         assert autotune.tune(wl, uvw[i], vis[i], wt[i], "fp32") == picks[i]
