@@ -19,6 +19,8 @@
 // step, with every decision kept in device memory: the host never waits
 // inside the cycle.  A step reads the residual and the beam and writes the
 // residual once (HBM-bound; the search rides along with the subtraction).
+#include <type_traits>
+
 #include "ws_kernels.h"
 
 namespace ws {
@@ -97,39 +99,66 @@ __global__ __launch_bounds__(256) void k_real_scale(
 }
 
 // Subtract the pending component (if any) and find this block's largest
-// |D|.  Pixels are taken in a grid-stride loop, so the blocks cover the
-// image evenly; the beam index of pixel (p, q) for a component at
+// |D|.  Pixels are taken V at a time (one 16-byte load of D when the
+// buffers allow it, else V = 1) in a grid-stride loop, so the blocks cover
+// the image evenly; the beam index of pixel (p, q) for a component at
 // (p*, q*) is (q - q* + nv/2, p - p* + nu/2), skipped where it leaves the
-// beam.  `search` = 0 for the final subtraction after the last pick.
-template <typename R>
+// beam.  nu is a power of two (2^lognu), so a group of V pixels lies in
+// one row.  Within a thread the pixels come in increasing index, so a
+// strictly larger |D| is the only way to replace the candidate (ties keep
+// the lower index); the comparisons run in the path precision, which
+// orders |D| exactly as FP64 would.  `search` = 0 for the final
+// subtraction after the last pick.
+template <typename R, int V>
 __global__ __launch_bounds__(kCleanThreads) void k_clean_step(
-    R* __restrict__ d, const R* __restrict__ beam, int nu, int nv,
+    R* __restrict__ d, const R* __restrict__ beam, int nu, int nv, int lognu,
     const CleanState* __restrict__ st, CleanSlot* __restrict__ slots,
     int search) {
   __shared__ Cand s_c[kCleanThreads / 64];
+  using Vec = typename std::conditional<
+      V == 1, R,
+      typename std::conditional<sizeof(R) == 4, float4, double2>::type>::type;
+  static_assert(V * sizeof(R) == sizeof(Vec), "V values per load");
   const int64_t n = (int64_t)nu * nv;
   const bool sub = st->pending != 0;
   const int64_t pidx = st->pend_idx;
-  const int pq = (int)(pidx / nu), pp = (int)(pidx - (int64_t)pq * nu);
+  const int pq = (int)(pidx >> lognu), pp = (int)(pidx & (nu - 1));
   const R amp = (R)st->pend_amp;
-  Cand best{-1.0, 0.0, (int64_t)n};
-  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  R bmag = (R)-1, bval = (R)0;
+  int64_t bidx = n;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * V;
   for (int64_t i = i0; i < n; i += stride) {
-    R v = d[i];
+    Vec raw = *reinterpret_cast<const Vec*>(d + i);
+    R* v = reinterpret_cast<R*>(&raw);
     if (sub) {
-      const int q = (int)(i / nu), p = (int)(i - (int64_t)q * nu);
+      const int q = (int)(i >> lognu), p = (int)(i & (nu - 1));
       const int bq = q - pq + nv / 2, bp = p - pp + nu / 2;
-      if ((unsigned)bq < (unsigned)nv && (unsigned)bp < (unsigned)nu) {
-        v = v - amp * beam[(size_t)bq * nu + bp];
-        d[i] = v;
+      if ((unsigned)bq < (unsigned)nv) {
+        const R* brow = beam + (size_t)bq * nu;
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+          if ((unsigned)(bp + j) < (unsigned)nu) {
+            v[j] = v[j] - amp * brow[bp + j];
+            any = true;
+          }
+        }
+        if (any) *reinterpret_cast<Vec*>(d + i) = raw;
       }
     }
-    const Cand c{fabs((double)v), (double)v, i};
-    if (better(c, best)) best = c;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const R m = fabs(v[j]);
+      if (m > bmag) {
+        bmag = m;
+        bval = v[j];
+        bidx = i + j;
+      }
+    }
   }
   if (!search) return;
-  best = block_best(best, s_c);
+  const Cand best = block_best(Cand{(double)bmag, (double)bval, bidx}, s_c);
   if (threadIdx.x == 0) {
     slots[blockIdx.x].mag = best.mag;
     slots[blockIdx.x].val = best.val;
@@ -211,12 +240,23 @@ void launch_clean_minor(void* d, const void* beam, void* model, int nu,
                         int nv, int niter, double gain, double threshold,
                         CleanState* state, CleanSlot* slots, int nslots,
                         int32_t* picks, int32_t* n_done, hipStream_t st) {
+  int lognu = 0;
+  while ((1 << lognu) < nu) ++lognu;
+  // 16-byte loads of the residual where it is 16-byte aligned (rows of a
+  // power-of-two width keep every group of V pixels aligned then).
+  constexpr int V = 16 / (int)sizeof(R);
+  const bool vec = (reinterpret_cast<uintptr_t>(d) % 16) == 0 && nu % V == 0;
   hipLaunchKernelGGL(k_clean_reset, dim3(1), dim3(1), 0, st, state, n_done);
   for (int t = 0; t <= niter; ++t) {
     const int search = t < niter ? 1 : 0;
-    hipLaunchKernelGGL(k_clean_step<R>, dim3(nslots), dim3(kCleanThreads), 0,
-                       st, (R*)d, (const R*)beam, nu, nv, state, slots,
-                       search);
+    if (vec)
+      hipLaunchKernelGGL((k_clean_step<R, V>), dim3(nslots),
+                         dim3(kCleanThreads), 0, st, (R*)d, (const R*)beam,
+                         nu, nv, lognu, state, slots, search);
+    else
+      hipLaunchKernelGGL((k_clean_step<R, 1>), dim3(nslots),
+                         dim3(kCleanThreads), 0, st, (R*)d, (const R*)beam,
+                         nu, nv, lognu, state, slots, search);
     if (search)
       hipLaunchKernelGGL(k_clean_pick<R>, dim3(1), dim3(kCleanThreads), 0,
                          st, slots, nslots, state, (R*)model, picks, gain,

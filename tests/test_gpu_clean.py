@@ -154,6 +154,42 @@ def test_clean_minor_matches_oracle(precision):
         assert _rell2(_h(res), r2, np.linalg.norm(d0)) <= 1e-5
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_clean_minor_unaligned_residual_matches_aligned(precision):
+    """A residual that is not 16-byte aligned takes the one-pixel-per-load
+    form of the minor step: the same picks and the same arithmetic per
+    pixel as the aligned, vector-load form, so equal results."""
+    wl, p = _sky_case(precision, seed=3, n=128, m=2000)
+    b, beta = o.dirty_beam(p, wl.uvw, wl.weight)
+    d0 = o.residual_image(p, wl.uvw, wl.vis, wl.weight,
+                          np.zeros((wl.nv, wl.nu)), beta)
+    plan = ws.WStackPlan.from_workload(wl)
+    dt = plan.rdtype
+    dev = torch.device("cuda", 0)
+    from paper_2301_06061_amd import _abi
+    from paper_2301_06061_amd.api import _ptr
+    out = []
+    for offset in (0, 1):
+        store = torch.zeros(d0.size + 4, dtype=dt, device=dev)
+        res = store[offset:offset + d0.size].view(wl.nv, wl.nu)
+        res.copy_(torch.from_numpy(d0).to(dev).to(dt))
+        assert (res.data_ptr() % 16 == 0) == (offset == 0)
+        beam = torch.from_numpy(b).to(dev).to(dt)
+        model = torch.zeros_like(beam)
+        picks = torch.full((40,), -1, dtype=torch.int32, device=dev)
+        n_done = torch.zeros(1, dtype=torch.int32, device=dev)
+        plan._bind()
+        _abi.call("ws_clean_minor", plan._h, _ptr(res), _ptr(beam),
+                  _ptr(model), 40, 0.25, 0.0, _ptr(picks), _ptr(n_done))
+        torch.cuda.synchronize()
+        out.append((picks.cpu().numpy(), res.cpu().numpy(),
+                    model.cpu().numpy(), int(n_done.item())))
+    (p0, r0, m0, n0), (p1, r1, m1, n1) = out
+    assert n0 == n1 == 40
+    assert np.array_equal(p0, p1)
+    assert np.array_equal(r0, r1) and np.array_equal(m0, m1)
+
+
 def test_clean_minor_threshold_and_zero_iterations():
     wl, p = _sky_case("fp64", seed=2, n=64, m=1500)
     b, beta = o.dirty_beam(p, wl.uvw, wl.weight)
