@@ -307,6 +307,34 @@ def test_grid_image_reuses_a_dirty_stack(precision):
         plan.grid_image(uvw, vis, wt)
 
 
+@pytest.mark.parametrize("precision,shape", [
+    ("fp64", (8192, 512, 2)), ("fp32", (8192, 512, 2)),
+    ("fp64", (512, 8192, 2)), ("fp32", (512, 8192, 2)),
+    ("fp32", (8192, 8192, 2))])
+def test_grid_image_beyond_4096_reuses_a_dirty_stack(precision, shape):
+    """The one-call path beyond 4096 (rows wider than 4096 through the
+    plain row transform and w-correction, columns longer than 4096 through
+    the four-step transform) zeroes the tiles without records before it
+    transforms.  Three calls on one plan (the second with far fewer
+    visibilities, so most of its idle tiles still hold the first call's
+    sums), each image against the oracle."""
+    nu, nv, nw = shape
+    fp = 1 if precision == "fp64" else 0
+    wl1 = synth.random_case(61, n=nu, nv=nv, nw=nw, support=7, m=20000,
+                            law="core", precision=fp)
+    wl2 = synth.random_case(62, n=nu, nv=nv, nw=nw, support=7, m=500,
+                            law="gauss", precision=fp)
+    wl2.w_min, wl2.w_max = wl1.w_min, wl1.w_max
+    wl2.uvw[:, 2] = np.clip(wl2.uvw[:, 2], wl1.w_min, wl1.w_max)
+    plan = plan_for(wl1, tile=64)
+    for wl in (wl1, wl2, wl1):
+        uvw, vis, wt = dev(wl)
+        img = plan.grid_image(uvw, vis, wt)
+        ref = o.image(o.Params.of(wl), wl.uvw, wl.vis, wl.weight)
+        assert_close(host(img), ref, precision == "fp64",
+                     "reuse beyond 4096")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("chunk", [64, 333, 0])
 def test_hot_bin_split_and_merge(precision, chunk):
