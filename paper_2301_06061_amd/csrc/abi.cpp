@@ -3,6 +3,7 @@
 // phase correction and plane reduction) and of degridding.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -67,12 +68,17 @@ struct Layout {
   // binning: WS_BINNING_PARTITION or WS_BINNING_HASHED (resolved)
   int binning;
   uint32_t part_buckets, part_span;  // partition: buckets and keys each
+  // Busy-tile store of the one-call path (FP32, 4096-row columns, tile
+  // edge 64, fused rows): tiles with records are gridded into slots of
+  // their own and the column transform reads them contiguously.
+  bool tstore;
+  int64_t tstore_slots;
   // workspace offsets
   size_t o_tw_u, o_tw_v, o_corr, o_counts, o_sums, o_keyrank, o_rec, o_chunks,
       o_slot, o_counters, o_split, o_extra, o_busy, o_idle, o_copies, o_desc,
       o_strips, o_partials, o_scratch, o_rowscratch, o_clean, o_p_hist1, o_p_hist1x,
       o_p_btot, o_p_bounds, o_p_seg, o_p_rec1, o_p_keys, o_p_chunk0, o_p_rank2,
-      o_p_hist2, o_p_hist2x, total;
+      o_p_hist2, o_p_hist2x, o_tstore, o_tslot, total;
 };
 
 ws_status check_params(const ws_params* p) {
@@ -276,6 +282,17 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
   L->o_rowscratch = take(fft_row_scratch_bytes(p->nu, L->elem));
   // Minor-cycle state and its per-block argmax slots.
   L->o_clean = take(sizeof(CleanState) + kCleanMaxSlots * sizeof(CleanSlot));
+  // Busy-tile store: T x T slots for half the tiles at most (tiles with
+  // records beyond that stay in the stack; each visibility is read by at
+  // most four tiles), and the slot of every tile.
+  L->tstore = L->elem == 8 && p->nv == 4096 && L->T == 64 && p->nu >= 512 &&
+              p->nu <= kFusedRows;
+  L->tstore_slots =
+      L->tstore ? std::max<int64_t>(
+                      1, std::min<int64_t>(L->ntiles / 2, 4 * max_vis))
+                : 0;
+  L->o_tstore = take((size_t)L->tstore_slots * L->T * L->T * L->elem);
+  L->o_tslot = take(L->tstore ? (size_t)L->ntiles * 4 : (size_t)0);
   L->total = o;
   return WS_OK;
 }
@@ -417,7 +434,7 @@ template <typename R>
 ws_status bin_records(ws_plan* pl, int64_t m, const VisSource& src,
                       int degrid, int64_t* n_dropped, uint32_t* max_items,
                       uint32_t* strips = nullptr, bool clear_strips = false,
-                      void* vis_out = nullptr) {
+                      void* vis_out = nullptr, uint32_t* tslot = nullptr) {
   const Layout& L = pl->L;
   const Geo& g = pl->g;
   hipStream_t st = pl->stream;
@@ -491,7 +508,7 @@ ws_status bin_records(ws_plan* pl, int64_t m, const VisSource& src,
     launch_tile_work(g, counts, degrid, chunk, chunks, slot, counters, split,
                      L.max_slots, pl->w<uint2>(L.o_extra), L.max_extra,
                      pl->w<uint32_t>(L.o_busy), pl->w<uint32_t>(L.o_idle),
-                     strips, st);
+                     strips, tslot, st);
   }));
   // Items: one per tile plus the further chunks of split tiles.
   const int64_t reads = degrid ? m : 4 * m;
@@ -511,9 +528,11 @@ ws_status bin_records(ws_plan* pl, int64_t m, const VisSource& src,
 }
 
 bool lazy_ok(const ws_plan* pl);
+bool tstore_ok(const ws_plan* pl);
 
+// With `ts`, finished tiles go to the busy-tile store.
 template <typename R>
-GridJob<R> make_job(ws_plan* pl, int accumulate) {
+GridJob<R> make_job(ws_plan* pl, int accumulate, bool ts = false) {
   const Layout& L = pl->L;
   GridJob<R> j;
   j.g = pl->g;
@@ -532,31 +551,40 @@ GridJob<R> make_job(ws_plan* pl, int accumulate) {
   j.partials = pl->w<cplx<R>>(L.o_partials);
   j.accumulate = accumulate;
   j.zero_idle = lazy_ok(pl) ? 0 : 1;
+  j.tstore = ts ? pl->w<cplx<R>>(L.o_tstore) : nullptr;
+  j.tslot = ts ? pl->w<uint32_t>(L.o_tslot) : nullptr;
+  j.tcap = ts ? (uint32_t)L.tstore_slots : 0u;
   return j;
 }
 
 template <typename R>
-ws_status merge_impl(ws_plan* pl, int acc) {
+ws_status merge_impl(ws_plan* pl, int acc, bool ts = false) {
   const Layout& L = pl->L;
   return launch(pl, "grid_merge", [&] {
     launch_grid_merge<R>(pl->g, pl->w<uint32_t>(L.o_counters),
                          pl->w<uint32_t>(L.o_split),
                          pl->w<uint32_t>(L.o_chunks),
                          pl->w<uint32_t>(L.o_slot), pl->work + L.o_partials,
-                         pl->planes, acc, L.max_slots / 2 + 1, pl->stream);
+                         pl->planes, acc, L.max_slots / 2 + 1,
+                         ts ? pl->work + L.o_tstore : nullptr,
+                         ts ? pl->w<uint32_t>(L.o_tslot) : nullptr,
+                         (uint32_t)L.tstore_slots, pl->stream);
   });
 }
 
 // With `lazy` (a first call whose stack only the fused imaging path will
-// read), tiles without records are not zeroed.
+// read), tiles without records are not zeroed; with `ts` as well, tiles
+// with records go to the busy-tile store instead of the stack.
 template <typename R>
 ws_status grid_impl(ws_plan* pl, int64_t m, const VisSource& src,
-                    int64_t* n_dropped, bool lazy = false) {
+                    int64_t* n_dropped, bool lazy = false, bool ts = false) {
   uint32_t max_items = 0;
   const int acc = pl->state == kGridded ? 1 : 0;
+  ts = ts && lazy && !acc;
   WS_TRY(bin_records<R>(pl, m, src, 0, n_dropped, &max_items,
-                        pl->w<uint32_t>(pl->L.o_strips), !acc));
-  const GridJob<R> j = make_job<R>(pl, acc);
+                        pl->w<uint32_t>(pl->L.o_strips), !acc, nullptr,
+                        ts ? pl->w<uint32_t>(pl->L.o_tslot) : nullptr));
+  const GridJob<R> j = make_job<R>(pl, acc, ts);
   if (!acc && !lazy) {
     // First call since the reset: tiles without records get their zeros.
     WS_TRY(launch(pl, "zero_idle", [&] {
@@ -566,7 +594,7 @@ ws_status grid_impl(ws_plan* pl, int64_t m, const VisSource& src,
   WS_TRY(launch(pl, "grid_tiles", [&] {
     launch_grid_tiles<R>(j, max_items, pl->cus, pl->stream);
   }));
-  WS_TRY(merge_impl<R>(pl, acc));
+  WS_TRY(merge_impl<R>(pl, acc, ts));
   pl->state = kGridded;
   return WS_OK;
 }
@@ -580,7 +608,7 @@ ws_status grid_impl(ws_plan* pl, int64_t m, const VisSource& src,
 template <typename R>
 ws_status cols_impl(ws_plan* pl, int sign, Geo* gout,
                     const uint32_t* strips = nullptr,
-                    const uint32_t* tiles = nullptr) {
+                    const uint32_t* tiles = nullptr, bool ts = false) {
   const ws_params& p = pl->p;
   bool ok = true;
   Geo g = pl->g;
@@ -588,7 +616,9 @@ ws_status cols_impl(ws_plan* pl, int sign, Geo* gout,
     WS_TRY(launch(pl, "fft_cols", [&] {
       ok = launch_fft_cols<R>(pl->planes, p.nv, p.nu, p.nw,
                               pl->work + pl->L.o_tw_v, sign, strips, g.T,
-                              tiles, pl->stream);
+                              tiles, ts ? pl->work + pl->L.o_tstore : nullptr,
+                              ts ? pl->w<uint32_t>(pl->L.o_tslot) : nullptr,
+                              (uint32_t)pl->L.tstore_slots, pl->stream);
     }));
   } else {
     WS_TRY(launch(pl, "fft_cols4", [&] {
@@ -644,13 +674,16 @@ ws_status fft_impl(ws_plan* pl, int sign) {
 // The stack holds what the gridding calls since the reset wrote, so the
 // column strips they never reached are skipped.
 // With `lazy`, tiles without records were never written (their cells are
-// taken as zero from the per-tile record counts).
+// taken as zero from the per-tile record counts); with `ts` as well, the
+// tiles with records are in the busy-tile store.
 template <typename R>
-ws_status image_impl(ws_plan* pl, void* image, bool lazy = false) {
+ws_status image_impl(ws_plan* pl, void* image, bool lazy = false,
+                     bool ts = false) {
   const ws_params& p = pl->p;
   Geo g;
   WS_TRY(cols_impl<R>(pl, +1, &g, pl->w<uint32_t>(pl->L.o_strips),
-                      lazy ? pl->w<uint32_t>(pl->L.o_chunks) : nullptr));
+                      lazy ? pl->w<uint32_t>(pl->L.o_chunks) : nullptr,
+                      lazy && ts));
   if (p.nu <= kFusedRows) {
     bool ok = true;
     WS_TRY(launch(pl, "row_screen_sum", [&] {
@@ -720,6 +753,10 @@ bool lazy_ok(const ws_plan* pl) {
          pl->p.nu <= kFusedRows;
 }
 
+// A first gridding call that only the fused imaging reads may put its
+// tiles with records in the busy-tile store (where the layout has one).
+bool tstore_ok(const ws_plan* pl) { return lazy_ok(pl) && pl->L.tstore; }
+
 ws_status check_plan(ws_plan* pl) {
   if (pl == nullptr) return fail(WS_INVALID_ARG, "plan is NULL");
   if (hipSetDevice(pl->device) != hipSuccess)
@@ -733,11 +770,14 @@ ws_status grid_image_impl(ws_plan* pl, int64_t m, const VisSource& src,
                           void* image, int64_t* n_dropped) {
   const bool lazy = lazy_ok(pl);
   const bool f64 = pl->p.precision == WS_FP64;
+  // The plan is empty here (the call's contract), so the gridding is a
+  // first call and may use the busy-tile store.
+  const bool ts = tstore_ok(pl) && pl->state == kEmpty;
   ws_status st = f64 ? grid_impl<double>(pl, m, src, n_dropped, lazy)
-                     : grid_impl<float>(pl, m, src, n_dropped, lazy);
+                     : grid_impl<float>(pl, m, src, n_dropped, lazy, ts);
   if (st == WS_OK)
     st = f64 ? image_impl<double>(pl, image, lazy)
-             : image_impl<float>(pl, image, lazy);
+             : image_impl<float>(pl, image, lazy, ts);
   pl->state = kEmpty;
   return st;
 }
@@ -830,7 +870,9 @@ ws_status batch_image_impl(ws_batch* b, const int64_t* m,
                           flat_source(uvw[i], vis[i],
                                       weight ? weight[i] : nullptr),
                           0, nullptr, &mi, pl->w<uint32_t>(pl->L.o_strips),
-                          true));
+                          true, nullptr,
+                          tstore_ok(pl) ? pl->w<uint32_t>(pl->L.o_tslot)
+                                        : nullptr));
     items += mi;
   }
   ws_plan* p0 = b->plans[0];
@@ -857,9 +899,9 @@ ws_status batch_image_impl(ws_batch* b, const int64_t* m,
   }));
   for (int i = 0; i < b->n; ++i) {
     ws_plan* pl = b->plans[i];
-    WS_TRY(merge_impl<R>(pl, 0));
+    WS_TRY(merge_impl<R>(pl, 0, tstore_ok(pl)));
     pl->state = kGridded;
-    ws_status st = image_impl<R>(pl, images[i], lazy_ok(pl));
+    ws_status st = image_impl<R>(pl, images[i], lazy_ok(pl), tstore_ok(pl));
     pl->state = kEmpty;
     WS_TRY(st);
   }
@@ -1456,7 +1498,8 @@ ws_status ws_batch_create(int32_t n, ws_plan* const* plans, void* work,
       const GridJob<double> j = make_job<double>(plans[i], 0);
       std::memcpy(host.data() + i * sizeof(GridJob<double>), &j, sizeof(j));
     } else {
-      const GridJob<float> j = make_job<float>(plans[i], 0);
+      const GridJob<float> j = make_job<float>(plans[i], 0,
+                                               tstore_ok(plans[i]));
       std::memcpy(host.data() + i * sizeof(GridJob<float>), &j, sizeof(j));
     }
   }

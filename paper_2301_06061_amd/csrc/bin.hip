@@ -356,7 +356,7 @@ __global__ __launch_bounds__(256) void k_tile_work(
     uint32_t* __restrict__ split_list, uint32_t max_slots,
     uint2* __restrict__ extra, uint32_t max_extra,
     uint32_t* __restrict__ busy, uint32_t* __restrict__ idle,
-    uint32_t* __restrict__ strips) {
+    uint32_t* __restrict__ strips, uint32_t* __restrict__ tslot) {
   // counters[0]: scratch slots taken, [1]: split tiles, [2]: extra items,
   // [4]: tiles with records (listed in busy), [5]: tiles without (idle),
   // [6..7]: 64-bit sum of the records every tile reads.
@@ -409,8 +409,12 @@ __global__ __launch_bounds__(256) void k_tile_work(
   for (int w = 0; w < wave; ++w) ii += s_idle[w];
   ii += (uint32_t)__popcll(imask & ((1ull << lane) - 1ull));
   if (!live) return;
-  if (work > 0) busy[ib] = (uint32_t)t;
-  else idle[ii] = (uint32_t)t;
+  if (work > 0) {
+    busy[ib] = (uint32_t)t;
+    if (tslot != nullptr) tslot[t] = ib;  // its slot in the busy-tile store
+  } else {
+    idle[ii] = (uint32_t)t;
+  }
   if (work > 0 && strips != nullptr) {
     // Column strip of this tile: plane k, tile column tx.
     const int per_plane = g.tiles_u * g.tiles_v;
@@ -1017,12 +1021,12 @@ void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t* tile_slot, uint32_t* counters,
                       uint32_t* split_list, uint32_t max_slots, uint2* extra,
                       uint32_t max_extra, uint32_t* busy, uint32_t* idle,
-                      uint32_t* strips, hipStream_t st) {
+                      uint32_t* strips, uint32_t* tslot, hipStream_t st) {
   const int nb = (g.ntiles + 255) / 256;
   hipLaunchKernelGGL(k_tile_work, dim3(nb), dim3(256), 0, st, g, offsets,
                      mode_degrid, chunk, tile_chunks, tile_slot, counters,
                      split_list, max_slots, extra, max_extra, busy, idle,
-                     strips);
+                     strips, tslot);
 }
 
 }  // namespace ws

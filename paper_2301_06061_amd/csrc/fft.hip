@@ -529,11 +529,20 @@ __global__ __launch_bounds__(NT) void k_fft_cols(
 // while the twiddled differences wait in registers, then the differences
 // (outputs 2e + 1).  The wider block doubles the row segment each access
 // moves (64 bytes instead of 32 for 4096-point FP32 columns).
-template <typename R, int LOGH, int BC, int NT>
+//
+// TS: the input tiles are read from the busy-tile store (tstore, slot of
+// tile t at tslot[t], layout tile_store_at) instead of the stack: the BC
+// columns of a block are one 64-byte sub-block of each tile, so every
+// tile row a wavefront reads is 512 contiguous bytes.  Tiles with a slot
+// of tcap or more did not fit the store and are read from the stack.
+// Needs 64-row tiles and strips, BC = 64 bytes of columns and 64 rows per
+// wavefront pass (TPC = 64); the output still goes to the stack.
+template <typename R, int LOGH, int BC, int NT, bool TS>
 __global__ __launch_bounds__(NT) void k_fft_cols_split(
     cplx<R>* data, int ncols, int nplanes, const cplx<R>* __restrict__ tw, R s,
     const uint32_t* __restrict__ strips, int log_strip,
-    const uint32_t* __restrict__ tiles) {
+    const uint32_t* __restrict__ tiles, const cplx<R>* __restrict__ tstore,
+    const uint32_t* __restrict__ tslot, uint32_t tcap) {
   constexpr int NH = 1 << LOGH;  // half the column length
   constexpr int N = 2 * NH;
   __shared__ cplx<R> lds[lds_line<NH>(BC)];
@@ -562,6 +571,15 @@ __global__ __launch_bounds__(NT) void k_fft_cols_split(
                              : kTwLo * min(tm, N / kTwLo - 1);
   const cplx<R> tval = tw[tidx];
   TileRows tr(tiles, plane, N, ncols, col0, log_strip, base);
+  // TS: lane l holds the store slot of tile row l of this strip (any
+  // value where the tile has no records: such rows are never read).
+  int myslot = 0;
+  if constexpr (TS) {
+    const int rows = N >> log_strip, tcols = ncols >> log_strip;
+    const int lane = (int)(threadIdx.x & 63);
+    myslot = (int)tslot[((size_t)plane * rows + min(lane, rows - 1)) * tcols +
+                        (col0 >> log_strip)];
+  }
   if (threadIdx.x < 4 * kTwLo) {
     if (tq == 0) s_lo[tm] = tval;
     else if (tq == 1) f_lo[tm] = tval;
@@ -584,12 +602,51 @@ __global__ __launch_bounds__(NT) void k_fft_cols_split(
   constexpr int NE = F0::IT * F0::RAD;
   const int c0 = (int)threadIdx.x % BC, jt = (int)threadIdx.x / BC;
   cplx<R> qa[NE], qb[NE];
+  // TS addressing: row e = jt + it TPC + r NB lies in tile row
+  // (it TPC + r NB) / 64 (a constant once unrolled; jt < 64) at row jt of
+  // the tile, and the block's columns are sub-block (col0 % 64) / BC.  A
+  // load address is a wavefront-uniform base (the tile's slot, the row
+  // in the stack for a tile past the store's last slot, or the spare line
+  // for a tile without records) plus one of two per-lane byte offsets, so
+  // choosing between the three costs one vector select.
+  const char* ts_base = nullptr;
+  uint32_t v_ts = 0, v_st = 0;
+  if constexpr (TS) {
+    static_assert(F0::TPC == 64 && F0::NB % 64 == 0 && NH % 64 == 0 &&
+                      BC * sizeof(cplx<R>) == 64,
+                  "busy-tile store: 64-row tiles, 64-byte sub-blocks");
+    ts_base = reinterpret_cast<const char*>(tstore) +
+              (size_t)((col0 & 63) / BC) * (64 * BC) * sizeof(cplx<R>);
+    v_ts = (uint32_t)((jt * BC + c0) * sizeof(cplx<R>));
+    v_st = (uint32_t)(((size_t)jt * ncols + c0) * sizeof(cplx<R>));
+  }
+  // Row jt of tile row `trow` (a constant) whose store slot is s; every
+  // choice below is wavefront-uniform.
+  auto ts_load = [&](int trow, uint32_t s) {
+    const bool h = ((tr.mask >> trow) & 1ull) != 0ull;
+    const bool in = s < tcap;
+    const char* sb =
+        !h ? reinterpret_cast<const char*>(tw)
+           : in ? ts_base + (size_t)s * (64 * 64 * sizeof(cplx<R>))
+                : reinterpret_cast<const char*>(base) +
+                      (size_t)trow * 64 * ncols * sizeof(cplx<R>);
+    const cplx<R> v =
+        *reinterpret_cast<const cplx<R>*>(sb + (size_t)(h && !in ? v_st : v_ts));
+    return cplx<R>{h ? v.re : (R)0, h ? v.im : (R)0};
+  };
   auto issue = [&](int n) {
     const int j = jt + (n / F0::RAD) * F0::TPC;
     if (F0::NB % F0::TPC == 0 || j < F0::NB) {
       const int e = j + (n % F0::RAD) * F0::NB;
-      qa[n] = tr.load(e, base + (size_t)e * ncols + c0, tw);
-      qb[n] = tr.load(e + NH, base + (size_t)(e + NH) * ncols + c0, tw);
+      if constexpr (TS) {
+        const int ta = ((n / F0::RAD) * F0::TPC + (n % F0::RAD) * F0::NB) / 64;
+        qa[n] = ts_load(ta, __builtin_amdgcn_readlane(myslot, ta));
+        qb[n] = ts_load(ta + NH / 64,
+                        __builtin_amdgcn_readlane(myslot, ta + NH / 64));
+      } else {
+        qa[n] = tr.load(e, base + (size_t)e * ncols + c0, tw);
+        qb[n] = tr.load(e + NH, base + (size_t)(e + NH) * ncols + c0, tw);
+      }
     }
   };
 #pragma unroll
@@ -1052,6 +1109,7 @@ int ilog2(int n) {
 template <typename R, int LOGN>
 bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
             const uint32_t* strips, int strip_w, const uint32_t* tiles,
+            const cplx<R>* tstore, const uint32_t* tslot, uint32_t tcap,
             hipStream_t st) {
   if constexpr (LOGN > 12) {
     return false;
@@ -1088,12 +1146,27 @@ bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
         if (tiles != nullptr) return false;  // the table cannot be honoured
         strips = nullptr;
       }
-      hipLaunchKernelGGL((k_fft_cols_split<R, LOGN - 1, BC2, NT2>),
+      if constexpr (BC2 * ELEM == 64 && NT2 / BC2 == 64 && LOGN >= 7) {
+        if (tstore != nullptr) {
+          if (tiles == nullptr || strips == nullptr || strip_w != 64)
+            return false;
+          hipLaunchKernelGGL((k_fft_cols_split<R, LOGN - 1, BC2, NT2, true>),
+                             dim3(((nb2 + 7) / 8) * 8), dim3(NT2), 0, st,
+                             data, ncols, nplanes, tw, s, strips, log_strip,
+                             tiles, tstore, tslot, tcap);
+          return true;
+        }
+      }
+      if (tstore != nullptr) return false;
+      hipLaunchKernelGGL((k_fft_cols_split<R, LOGN - 1, BC2, NT2, false>),
                          dim3(((nb2 + 7) / 8) * 8), dim3(NT2), 0, st, data,
-                         ncols, nplanes, tw, s, strips, log_strip, tiles);
+                         ncols, nplanes, tw, s, strips, log_strip, tiles,
+                         (const cplx<R>*)nullptr, (const uint32_t*)nullptr,
+                         0u);
       return true;
     }
   }
+  if (tstore != nullptr) return false;
   if (strip_w % BC != 0) {
     if (tiles != nullptr) return false;
     strips = nullptr;
@@ -1220,12 +1293,15 @@ bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw, int sign,
 template <typename R>
 bool launch_fft_cols(void* data, int nrows, int ncols, int nplanes,
                      const void* tw, int sign, const uint32_t* strips,
-                     int strip_w, const uint32_t* tiles, hipStream_t st) {
+                     int strip_w, const uint32_t* tiles, const void* tstore,
+                     const uint32_t* tslot, uint32_t tcap, hipStream_t st) {
   const int lg = ilog2(nrows);
   bool ok = false;
   WS_LOGN_SWITCH(lg, (ok = cols_t<R, LG>((cplx<R>*)data, ncols, nplanes,
                                          (const cplx<R>*)tw, (R)sign, strips,
-                                         strip_w, tiles, st)));
+                                         strip_w, tiles,
+                                         (const cplx<R>*)tstore, tslot, tcap,
+                                         st)));
   return ok;
 }
 
@@ -1323,6 +1399,7 @@ void launch_twiddles(void* tw, int n, hipStream_t st) {
                                    hipStream_t);                             \
   template bool launch_fft_cols<R>(void*, int, int, int, const void*, int,   \
                                    const uint32_t*, int, const uint32_t*,    \
+                                   const void*, const uint32_t*, uint32_t,   \
                                    hipStream_t);                             \
   template bool launch_row_screen_sum<R>(const void*, void*, const Geo&,     \
                                          const void*, const uint32_t*,       \

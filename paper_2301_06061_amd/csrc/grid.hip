@@ -129,7 +129,12 @@ __device__ __forceinline__ void store16(cplx<double>* p,
 // Store (or add) a T x T tile of LDS accumulators (type A), held as
 // separate real and imaginary rows, into a row-major complex destination of
 // the path precision, 16 bytes per store; the LDS cells read are cleared.
-template <typename R, typename A>
+// BLOCKED: the destination is a slot of the busy-tile store instead
+// (tile_store_at; dst_pitch unused).  Consecutive threads take
+// consecutive cells of a row either way, which keeps the LDS reads free
+// of bank conflicts; in the store, the two rows a wavefront covers are
+// adjacent in every 64-byte column sub-block.
+template <typename R, typename A, bool BLOCKED = false>
 __device__ __forceinline__ void store_tile_clear(A* s_re, A* s_im,
                                                  int pitch, int T,
                                                  double scale, cplx<R>* dst,
@@ -147,7 +152,10 @@ __device__ __forceinline__ void store_tile_clear(A* s_re, A* s_im,
       s_re[a] = (A)0;
       s_im[a] = (A)0;
     }
-    cplx<R>* p = dst + (size_t)lj * dst_pitch + li;
+    static_assert(!BLOCKED || (64 / sizeof(cplx<R>)) % V == 0,
+                  "a store stays inside one column sub-block");
+    cplx<R>* p = BLOCKED ? dst + tile_store_at<R>(T, lj, li)
+                         : dst + (size_t)lj * dst_pitch + li;
     if (accumulate) {
 #pragma unroll
       for (int e = 0; e < V; ++e) v[e] = cadd(p[e], v[e]);
@@ -191,7 +199,7 @@ struct GridItem {
   int valid;
   int tile;
   uint32_t nch;    // items the tile is split into
-  uint32_t chunk;  // which of them
+  uint32_t chunk;  // which of them; a tile of one chunk: its busy index
   uint32_t f0, f1;
   uint32_t off0;
   uint32_t cum[kSegments];
@@ -241,7 +249,9 @@ __device__ __forceinline__ void wave_share(uint32_t f0, uint32_t f1, int w,
 // written by k_item_desc after the tile work pass, so that the gridder
 // starts an item with one load instead of a chain of dependent loads (queue
 // entry -> tile -> its key ranges).  Words: tile, chunks of the tile, chunk,
-// f0, f1, off0, cum[1 .. kSegments-1], step[1 .. kSegments-1].
+// f0, f1, off0, cum[1 .. kSegments-1], step[1 .. kSegments-1].  A tile of
+// one chunk (chunk 0, never an extra item) has its index in the busy list
+// in the chunk word instead: its slot in the busy-tile store.
 static_assert(6 + 2 * (kSegments - 1) == kDescWords, "descriptor layout");
 
 __global__ __launch_bounds__(256) void k_item_desc(
@@ -278,7 +288,7 @@ __global__ __launch_bounds__(256) void k_item_desc(
   const uint32_t f0 = ch * chunk;
   w[0] = tile;
   w[1] = nch;
-  w[2] = ch;
+  w[2] = nch == 1 ? n - nextra : ch;
   w[3] = f0;
   w[4] = nch == 1 ? cum : min(cum, f0 + chunk);
   uint4* d = reinterpret_cast<uint4*>(desc + (size_t)n * kDescWords);
@@ -480,7 +490,18 @@ __device__ __forceinline__ void store_item(const GridJob<R>& j,
   int k, oy, ox;
   tile_origin(j.g, x.tile, k, oy, ox);
   cplx<R>* dst = j.planes + ((size_t)k * j.g.nv + oy) * j.g.nu + ox;
-  if (x.f1 <= x.f0) {
+  if (j.tstore != nullptr && x.nch == 1 && x.chunk < j.tcap) {
+    // One-call path: the tile goes to its slot of the busy-tile store
+    // (the item's busy-list index is its slot: no load of tslot here).
+    cplx<R>* slot = j.tstore + (size_t)x.chunk * T * T;
+    if (x.f1 <= x.f0) {
+      if (!j.accumulate) zero_tile(T, slot, (size_t)T);
+    } else {
+      store_tile_clear<R, GridAcc<R>, true>(s_re, s_im, j.pitch, T,
+                                            j.g.cnorm, slot, 0,
+                                            j.accumulate != 0);
+    }
+  } else if (x.f1 <= x.f0) {
     if (x.nch == 1 && !j.accumulate) zero_tile(T, dst, (size_t)j.g.nu);
   } else if (x.nch == 1) {
     store_tile_clear(s_re, s_im, j.pitch, T, j.g.cnorm, dst,
@@ -632,7 +653,8 @@ __global__ __launch_bounds__(1024) void k_grid_merge(
     const uint32_t* __restrict__ tile_chunks,
     const uint32_t* __restrict__ tile_slot,
     const cplx<R>* __restrict__ partials, cplx<R>* __restrict__ planes,
-    int accumulate) {
+    int accumulate, cplx<R>* __restrict__ tstore,
+    const uint32_t* __restrict__ tslot, uint32_t tcap) {
   // Several workgroups per split tile (blockIdx.y), each summing the
   // partials of its share of the cells in chunk order, eight loads in
   // flight per thread: the hottest tiles have tens of chunks, and the
@@ -644,7 +666,10 @@ __global__ __launch_bounds__(1024) void k_grid_merge(
   const int T = g.T;
   int k, oy, ox;
   tile_origin(g, t, k, oy, ox);
-  cplx<R>* dst = planes + ((size_t)k * g.nv + oy) * g.nu + ox;
+  const uint32_t ts = tstore != nullptr ? tslot[t] : tcap;
+  const bool in_store = ts < tcap;
+  cplx<R>* dst = in_store ? tstore + (size_t)ts * T * T
+                          : planes + ((size_t)k * g.nv + oy) * g.nu + ox;
   const R cn = (R)g.cnorm;
   const size_t tt = (size_t)T * T;
   for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < T * T;
@@ -662,7 +687,8 @@ __global__ __launch_bounds__(1024) void k_grid_merge(
     for (; c < nch; ++c) acc = cadd(acc, src[c * tt]);
     const int li = i % T, lj = i / T;
     cplx<R> v = {cn * acc.re, cn * acc.im};
-    cplx<R>* p = dst + (size_t)lj * g.nu + li;
+    cplx<R>* p = in_store ? dst + tile_store_at<R>(T, lj, li)
+                          : dst + (size_t)lj * g.nu + li;
     if (accumulate) v = cadd(*p, v);
     *p = v;
   }
@@ -908,12 +934,14 @@ void launch_grid_merge(const Geo& g, const uint32_t* counters,
                        const uint32_t* split_list, const uint32_t* tile_chunks,
                        const uint32_t* tile_slot, const void* partials,
                        void* planes, int accumulate, uint32_t max_split,
+                       void* tstore, const uint32_t* tslot, uint32_t tcap,
                        hipStream_t st) {
   constexpr unsigned kMergeParts = 4;
   hipLaunchKernelGGL(k_grid_merge<R>, dim3(max_split, kMergeParts), dim3(1024),
                      0, st, g,
                      counters, split_list, tile_chunks, tile_slot,
-                     (const cplx<R>*)partials, (cplx<R>*)planes, accumulate);
+                     (const cplx<R>*)partials, (cplx<R>*)planes, accumulate,
+                     (cplx<R>*)tstore, tslot, tcap);
 }
 
 template <typename R>
@@ -950,7 +978,9 @@ size_t degrid_lds_bytes(int T, int K, int elem_bytes) {
   template void launch_grid_merge<R>(const Geo&, const uint32_t*,          \
                                      const uint32_t*, const uint32_t*,     \
                                      const uint32_t*, const void*, void*,  \
-                                     int, uint32_t, hipStream_t);          \
+                                     int, uint32_t, void*,                 \
+                                     const uint32_t*, uint32_t,            \
+                                     hipStream_t);                         \
   template void launch_degrid_tiles<R>(                                    \
       const Geo&, const uint32_t*, uint32_t*, const uint2*,                \
       const uint32_t*, const void*, const void*, uint32_t, void*,          \

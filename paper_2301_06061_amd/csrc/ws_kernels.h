@@ -97,12 +97,13 @@ void launch_bin_scatter(const Geo& g, const VisSource& src, int64_t m,
                         const uint2* keyrank, const uint32_t* offsets,
                         uint32_t nkeys, void* records, int degrid,
                         void* vis_out, hipStream_t st);
+// tslot (optional): busy-list index of every tile with records.
 void launch_tile_work(const Geo& g, const uint32_t* offsets, int mode_degrid,
                       uint32_t chunk, uint32_t* tile_chunks,
                       uint32_t* tile_slot, uint32_t* counters,
                       uint32_t* split_list, uint32_t max_slots, uint2* extra,
                       uint32_t max_extra, uint32_t* busy, uint32_t* idle,
-                      uint32_t* strips, hipStream_t st);
+                      uint32_t* strips, uint32_t* tslot, hipStream_t st);
 
 // gridding and degridding (grid.hip)
 // LDS accumulator of the gridder: FP64 for both paths.  On gfx950 the
@@ -143,7 +144,23 @@ struct GridJob {
   cplx<R>* partials;
   int accumulate;
   int zero_idle;              // batch: this job's idle tiles need zeros
+  // Busy-tile store (one-call path of 4096-row FP32 stacks): finished
+  // tiles go to tstore[tslot[tile]] in column sub-blocks (tile_store_at)
+  // instead of the stack; null = the stack.  Tiles whose busy-list index
+  // (= slot) is tcap or more do not fit and go to the stack.
+  cplx<R>* tstore;
+  const uint32_t* tslot;
+  uint32_t tcap;
 };
+
+// Element (row, col) of a tile of edge T in the busy-tile store: column
+// sub-blocks of 64 bytes (8 FP32 columns) x T rows, one after another, so
+// a column transform of 8 columns reads 512 contiguous bytes per tile row.
+template <typename R>
+__host__ __device__ inline size_t tile_store_at(int T, int row, int col) {
+  constexpr int B = 64 / (int)sizeof(cplx<R>);
+  return (size_t)(col / B) * T * B + (size_t)row * B + (col % B);
+}
 
 // Descriptors of the gridding work items (after launch_tile_work), one
 // per item in queue order; desc holds max_items * kDescWords words.
@@ -166,11 +183,14 @@ void launch_zero_idle(const Geo& g, const uint32_t* counters,
 template <typename R>
 void launch_zero_idle_batch(const GridJob<R>* jobs, int njobs,
                             uint64_t total_tiles, hipStream_t st);
+// With tstore (and tslot), merged tiles with a slot below tcap go to the
+// busy-tile store.
 template <typename R>
 void launch_grid_merge(const Geo& g, const uint32_t* counters,
                        const uint32_t* split_list, const uint32_t* tile_chunks,
                        const uint32_t* tile_slot, const void* partials,
                        void* planes, int accumulate, uint32_t max_split,
+                       void* tstore, const uint32_t* tslot, uint32_t tcap,
                        hipStream_t st);
 template <typename R>
 void launch_degrid_tiles(const Geo& g, const uint32_t* offsets,
@@ -191,11 +211,15 @@ bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw,
 // Column transforms; with `strips` non-null, the blocks of column strips
 // (strip_w columns of one plane) whose mark is zero are skipped; with
 // `tiles` non-null (per-tile record counts, tile edge strip_w), rows of
-// tiles without records are taken as zero and not read.
+// tiles without records are taken as zero and not read.  With `tstore`
+// non-null (FP32, 4096 rows, strip_w 64, strips and tiles given) the
+// tiles with records and a slot tslot[t] below tcap are read from the
+// busy-tile store instead of `data`; false where that is not possible.
 template <typename R>
 bool launch_fft_cols(void* data, int nrows, int ncols, int nplanes,
                      const void* tw, int sign, const uint32_t* strips,
-                     int strip_w, const uint32_t* tiles, hipStream_t st);
+                     int strip_w, const uint32_t* tiles, const void* tstore,
+                     const uint32_t* tslot, uint32_t tcap, hipStream_t st);
 template <typename R>
 bool launch_row_screen_sum(const void* planes, void* img, const Geo& g,
                            const void* tw_u, const uint32_t* strips,

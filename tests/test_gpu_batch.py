@@ -206,12 +206,15 @@ def test_config4_scaled_channels():
 
 def test_batch_graph_replays_lazy_channels():
     """Graph replays of a batch whose plans all leave tiles without records
-    unwritten (tile edge 64, rows of 512 or more): each replay starts from
-    the stacks the previous one left, with new visibility values."""
+    unwritten (tile edge 64, rows of 512 or more; the plan with 4096-row
+    columns grids its tiles with records into the busy-tile store): each
+    replay starts from the stacks the previous one left, with new
+    visibility values."""
     wls = []
     for i, (n, nv, nw, m) in enumerate([(512, 512, 2, 4000),
                                         (1024, 512, 3, 6000),
-                                        (512, 1024, 1, 2000)]):
+                                        (512, 1024, 1, 2000),
+                                        (512, 4096, 2, 3000)]):
         wl = synth.random_case(30 + i, n=n, nv=nv, nw=nw, support=7, m=m,
                                law="core", precision=0)
         if nw == 1:

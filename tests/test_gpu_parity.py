@@ -335,6 +335,90 @@ def test_grid_image_beyond_4096_reuses_a_dirty_stack(precision, shape):
                      "reuse beyond 4096")
 
 
+def _with_hot_spot(wl, seed, count, cell_u, cell_v):
+    """wl with its first `count` visibilities moved to within a few cells
+    of (cell_u, cell_v): that tile gets more records than a chunk."""
+    rng = np.random.default_rng(seed)
+    uvw = wl.uvw.copy()
+    uvw[:count, 0] = (cell_u + rng.normal(0, 2.0, count) - wl.nu / 2) / wl.fov_l
+    uvw[:count, 1] = (cell_v + rng.normal(0, 2.0, count) - wl.nv / 2) / wl.fov_m
+    return synth.Workload(wl.nu, wl.nv, wl.nw, wl.fov_l, wl.fov_m, wl.w_min,
+                          wl.w_max, wl.support, wl.sigma, wl.precision,
+                          np.ascontiguousarray(uvw), wl.vis, wl.weight,
+                          name=wl.name + "+hot")
+
+
+@pytest.mark.parametrize("chunk", [64, 0])
+def test_busy_tile_store_matches_the_stack_path(chunk):
+    """FP32 one-call path on 4096-row columns, tile edge 64: the tiles with
+    records are gridded into a store of their own (split tiles merged into
+    it) and the column transform reads them from there.  Its image matches
+    that of the same data gridded into the stack and imaged by a separate
+    call to 1e-6 (the same sums and transforms; only the partial tiles of
+    split tiles, FP32 roundings of FP64 LDS sums whose order varies from
+    run to run, can differ in the last bit), and the oracle's.  Three calls
+    on one plan with different data: the second has far fewer busy tiles,
+    so most slots and slot numbers of the first are stale."""
+    wl1 = _with_hot_spot(
+        synth.random_case(71, n=512, nv=4096, nw=2, support=7, m=20000,
+                          law="core", precision=0), 72, 6000, 300.5, 1900.5)
+    wl2 = synth.random_case(73, n=512, nv=4096, nw=2, support=7, m=2000,
+                            law="gauss", precision=0)
+    wl2.w_min, wl2.w_max = wl1.w_min, wl1.w_max
+    wl2.uvw[:, 2] = np.clip(wl2.uvw[:, 2], wl1.w_min, wl1.w_max)
+    plan = plan_for(wl1, tile=64, chunk=chunk)
+    stack = plan_for(wl1, tile=64, chunk=chunk)
+    for i, wl in enumerate((wl1, wl2, wl1)):
+        uvw, vis, wt = dev(wl)
+        img = plan.grid_image(uvw, vis, wt)
+        st = plan.tile_stats()
+        assert st["busy"] > 0 and st["idle"] > st["busy"]
+        if i != 1 and chunk == 64:
+            assert st["split"] > 0
+        stack.reset()
+        ref_img = stack.new_image()
+        stack.grid(uvw, vis, wt)
+        stack.image_accumulate(ref_img)
+        got = host(img)
+        err = rel_l2(got, host(ref_img))
+        assert err <= 1e-6, f"call {i}: one-call vs stack path {err:.3e}"
+        assert_close(got, o.image(o.Params.of(wl), wl.uvw, wl.vis, wl.weight),
+                     False, f"busy-tile store, call {i}")
+
+
+def test_busy_tile_store_overflow_goes_to_the_stack():
+    """Visibilities spread over the whole 512 x 4096 grid: every tile has
+    records, more than the busy-tile store holds (half the tiles), so the
+    tiles past its last slot are gridded into the stack and read from
+    there.  Image against the stack path and the oracle, twice in a row."""
+    wl = synth.random_case(75, n=512, nv=4096, nw=2, support=7, m=20000,
+                           law="gauss", precision=0)
+    rng = np.random.default_rng(76)
+    uvw = wl.uvw.copy()
+    uvw[:, 0] = (rng.uniform(8, wl.nu - 8, wl.m) - wl.nu / 2) / wl.fov_l
+    uvw[:, 1] = (rng.uniform(8, wl.nv - 8, wl.m) - wl.nv / 2) / wl.fov_m
+    wl = synth.Workload(wl.nu, wl.nv, wl.nw, wl.fov_l, wl.fov_m, wl.w_min,
+                        wl.w_max, wl.support, wl.sigma, wl.precision,
+                        np.ascontiguousarray(uvw), wl.vis, wl.weight,
+                        name="uniform")
+    plan = plan_for(wl, tile=64)
+    stack = plan_for(wl, tile=64)
+    uvw_d, vis, wt = dev(wl)
+    ref = o.image(o.Params.of(wl), wl.uvw, wl.vis, wl.weight)
+    for i in range(2):
+        img = plan.grid_image(uvw_d, vis, wt)
+        st = plan.tile_stats()
+        assert st["busy"] > (8 * 64 * 2) // 2, st
+        stack.reset()
+        ref_img = stack.new_image()
+        stack.grid(uvw_d, vis, wt)
+        stack.image_accumulate(ref_img)
+        got = host(img)
+        err = rel_l2(got, host(ref_img))
+        assert err <= 1e-6, f"call {i}: one-call vs stack path {err:.3e}"
+        assert_close(got, ref, False, f"store overflow, call {i}")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("chunk", [64, 333, 0])
 def test_hot_bin_split_and_merge(precision, chunk):
