@@ -595,10 +595,12 @@ __global__ __launch_bounds__(NT) void k_fft_cols_split(
   // wavefront keeps 2 AHEAD + 2 loads in flight without holding the whole
   // strip in registers (with one workgroup per CU there is no other
   // workgroup to hide the latency).  FP32 (512 threads, 256 registers)
-  // runs 4 pairs ahead; FP64 at 1024 threads has no registers to spare and
-  // loads each pair where it is used (measured fastest for each; requesting
-  // every pair before any arithmetic measured slower for both).
-  constexpr int AHEAD = sizeof(R) == 4 ? 4 : 0;
+  // runs 4 pairs ahead from the stack and 8 from the busy-tile store;
+  // FP64 at 1024 threads has no registers to spare and loads each pair
+  // where it is used (measured fastest for each; requesting every pair
+  // before any arithmetic measured slower for both; from the store, 2, 4,
+  // 6, 12 and 16 pairs ahead measured slower than 8).
+  constexpr int AHEAD = sizeof(R) == 4 ? (TS ? 8 : 4) : 0;
   constexpr int NE = F0::IT * F0::RAD;
   const int c0 = (int)threadIdx.x % BC, jt = (int)threadIdx.x / BC;
   cplx<R> qa[NE], qb[NE];
