@@ -142,7 +142,10 @@ ws_status ws_validate_params(const ws_params* params);
 
 /* Sizes in bytes of the two caller-owned device buffers a plan needs:
  * the plane stack (nw * nv * nu complex cells) and the workspace for
- * batches of up to max_vis visibilities (1 <= max_vis < 2^31).  Host only;
+ * batches of up to max_vis visibilities (1 <= max_vis < 2^31).  For FP32
+ * plans with nv = 4096, 512 <= nu <= 4096 and tile edge 64, the workspace
+ * includes the one-call path's store of the tiles with records (at most
+ * half the stack's size; tiles beyond it stay in the stack).  Host only;
  * needs no GPU.  Either output pointer may be NULL. */
 ws_status ws_workspace_bytes(const ws_params* params, int64_t max_vis,
                              size_t* planes_bytes, size_t* work_bytes);
