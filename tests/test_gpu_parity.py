@@ -419,6 +419,26 @@ def test_busy_tile_store_overflow_goes_to_the_stack():
         assert_close(got, ref, False, f"store overflow, call {i}")
 
 
+def test_busy_tile_store_empty_call_then_data():
+    """An empty one-call on a plan with the busy-tile store adds nothing to
+    the image (no tile has records, no strip is marked); the next call with
+    data still matches the oracle."""
+    wl = synth.random_case(77, n=512, nv=4096, nw=2, support=7, m=3000,
+                           law="core", precision=0)
+    plan = plan_for(wl, tile=64)
+    uvw, vis, wt = dev(wl)
+    img = plan.new_image()
+    img.fill_(1.0)
+    plan.grid_image(uvw[:0], vis[:0], None if wt is None else wt[:0],
+                    image=img)
+    assert plan.tile_stats()["busy"] == 0
+    got = host(img)
+    assert np.array_equal(got, np.ones_like(got))
+    img = plan.grid_image(uvw, vis, wt)
+    assert_close(host(img), o.image(o.Params.of(wl), wl.uvw, wl.vis, wl.weight),
+                 False, "store after an empty call")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("chunk", [64, 333, 0])
 def test_hot_bin_split_and_merge(precision, chunk):
