@@ -529,6 +529,7 @@ ws_status bin_records(ws_plan* pl, int64_t m, const VisSource& src,
 
 bool lazy_ok(const ws_plan* pl);
 bool tstore_ok(const ws_plan* pl);
+bool marked_ok(const ws_plan* pl);
 
 // With `ts`, finished tiles go to the busy-tile store.
 template <typename R>
@@ -574,10 +575,13 @@ ws_status merge_impl(ws_plan* pl, int acc, bool ts = false) {
 
 // With `lazy` (a first call whose stack only the fused imaging path will
 // read), tiles without records are not zeroed; with `ts` as well, tiles
-// with records go to the busy-tile store instead of the stack.
+// with records go to the busy-tile store instead of the stack.  With
+// `marked` (a first call of the one-call path beyond 4096), only the tiles
+// without records in marked column strips are zeroed.
 template <typename R>
 ws_status grid_impl(ws_plan* pl, int64_t m, const VisSource& src,
-                    int64_t* n_dropped, bool lazy = false, bool ts = false) {
+                    int64_t* n_dropped, bool lazy = false, bool ts = false,
+                    bool marked = false) {
   uint32_t max_items = 0;
   const int acc = pl->state == kGridded ? 1 : 0;
   ts = ts && lazy && !acc;
@@ -588,7 +592,9 @@ ws_status grid_impl(ws_plan* pl, int64_t m, const VisSource& src,
   if (!acc && !lazy) {
     // First call since the reset: tiles without records get their zeros.
     WS_TRY(launch(pl, "zero_idle", [&] {
-      launch_zero_idle<R>(pl->g, j.counters, j.idle, pl->planes, pl->stream);
+      launch_zero_idle<R>(pl->g, j.counters, j.idle, pl->planes,
+                          marked ? pl->w<uint32_t>(pl->L.o_strips) : nullptr,
+                          pl->stream);
     }));
   }
   WS_TRY(launch(pl, "grid_tiles", [&] {
@@ -636,14 +642,16 @@ ws_status cols_impl(ws_plan* pl, int sign, Geo* gout,
   return WS_OK;
 }
 
+// With `strips`, samples of unmarked column strips are taken as zero.
 template <typename R>
-ws_status rows_impl(ws_plan* pl, int sign) {
+ws_status rows_impl(ws_plan* pl, int sign, const uint32_t* strips = nullptr) {
   const ws_params& p = pl->p;
   bool ok = true;
   WS_TRY(launch(pl, "fft_rows", [&] {
     ok = launch_fft_rows<R>(pl->planes, p.nu, (int64_t)p.nw * p.nv,
                             pl->work + pl->L.o_tw_u, sign,
-                            pl->work + pl->L.o_rowscratch, pl->stream);
+                            pl->work + pl->L.o_rowscratch, strips, p.nv,
+                            pl->stream);
   }));
   if (!ok) return fail(WS_UNSUPPORTED_SIZE, "no row FFT for nu=%d", p.nu);
   return WS_OK;
@@ -676,9 +684,11 @@ ws_status fft_impl(ws_plan* pl, int sign) {
 // With `lazy`, tiles without records were never written (their cells are
 // taken as zero from the per-tile record counts); with `ts` as well, the
 // tiles with records are in the busy-tile store.
+// With `marked`, unmarked column strips were never written (the one-call
+// path beyond 4096): the row transform takes them as zero.
 template <typename R>
 ws_status image_impl(ws_plan* pl, void* image, bool lazy = false,
-                     bool ts = false) {
+                     bool ts = false, bool marked = false) {
   const ws_params& p = pl->p;
   Geo g;
   WS_TRY(cols_impl<R>(pl, +1, &g, pl->w<uint32_t>(pl->L.o_strips),
@@ -696,7 +706,8 @@ ws_status image_impl(ws_plan* pl, void* image, bool lazy = false,
                          p.nu);
     return WS_OK;
   }
-  WS_TRY(rows_impl<R>(pl, +1));
+  WS_TRY(rows_impl<R>(pl, +1,
+                      marked ? pl->w<uint32_t>(pl->L.o_strips) : nullptr));
   return launch(pl, "wcorrect", [&] {
     launch_wcorrect<R>(pl->planes, image, g, pl->stream);
   });
@@ -757,6 +768,17 @@ bool lazy_ok(const ws_plan* pl) {
 // tiles with records in the busy-tile store (where the layout has one).
 bool tstore_ok(const ws_plan* pl) { return lazy_ok(pl) && pl->L.tstore; }
 
+// Beyond 4096 the one-call path zeroes only the tiles without records in
+// marked column strips: the column transform skips the unmarked strips,
+// and the row transform (fused below 4096 columns, else by strip marks)
+// takes them as zero.
+bool marked_ok(const ws_plan* pl) {
+  const ws_params& p = pl->p;
+  return !lazy_ok(pl) && pl->g.T == 64 && p.nu >= 1024 &&
+         (p.nu > kFusedRows || p.nv > kOnePassCols) &&
+         (p.nu <= kFusedRows || fft_rows_can_mask(p.nu, pl->L.elem));
+}
+
 ws_status check_plan(ws_plan* pl) {
   if (pl == nullptr) return fail(WS_INVALID_ARG, "plan is NULL");
   if (hipSetDevice(pl->device) != hipSuccess)
@@ -773,11 +795,13 @@ ws_status grid_image_impl(ws_plan* pl, int64_t m, const VisSource& src,
   // The plan is empty here (the call's contract), so the gridding is a
   // first call and may use the busy-tile store.
   const bool ts = tstore_ok(pl) && pl->state == kEmpty;
-  ws_status st = f64 ? grid_impl<double>(pl, m, src, n_dropped, lazy)
-                     : grid_impl<float>(pl, m, src, n_dropped, lazy, ts);
+  const bool marked = marked_ok(pl) && pl->state == kEmpty;
+  ws_status st =
+      f64 ? grid_impl<double>(pl, m, src, n_dropped, lazy, false, marked)
+          : grid_impl<float>(pl, m, src, n_dropped, lazy, ts, marked);
   if (st == WS_OK)
-    st = f64 ? image_impl<double>(pl, image, lazy)
-             : image_impl<float>(pl, image, lazy, ts);
+    st = f64 ? image_impl<double>(pl, image, lazy, false, marked)
+             : image_impl<float>(pl, image, lazy, ts, marked);
   pl->state = kEmpty;
   return st;
 }

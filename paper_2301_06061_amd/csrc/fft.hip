@@ -296,10 +296,46 @@ __device__ __forceinline__ cplx<R> checker(cplx<R> v, int e) {
 
 // ---- plain row and column transforms (in place, any plane count) --------
 
-template <typename R, int LOGN, int NT>
-__global__ __launch_bounds__(NT) void k_fft_rows(cplx<R>* data, int64_t nrows,
-                                                 const cplx<R>* __restrict__ tw,
-                                                 R s) {
+// Sample e of a stack row whose 64-column strips carry marks (mk: the
+// plane's marks, null when every strip holds data): read where the strip
+// is marked, zero elsewhere (the load then goes to the spare line, so it
+// costs no HBM traffic and needs no branch).  e - threadIdx.x must be the
+// same across the workgroup and a multiple of 64, as in the first-stage
+// loads of the row transforms, so that a wavefront's 64 samples lie in one
+// strip and every choice here is wavefront-uniform.
+template <bool MK, typename R>
+__device__ __forceinline__ cplx<R> row_sample(const cplx<R>* line, int e,
+                                              const uint32_t* __restrict__ mk,
+                                              const cplx<R>* spare) {
+  if constexpr (!MK) return line[e];
+  const int c = e - (int)threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const bool on = mk[w + (c >> 6)] != 0u;
+  const char* sb = on ? reinterpret_cast<const char*>(line + c)
+                      : reinterpret_cast<const char*>(spare);
+  const cplx<R> v = *reinterpret_cast<const cplx<R>*>(
+      sb + (size_t)threadIdx.x * sizeof(cplx<R>));
+  return cplx<R>{on ? v.re : (R)0, on ? v.im : (R)0};
+}
+
+// Marks of the plane that stack row `row` belongs to (null: no marks).
+__device__ __forceinline__ const uint32_t* row_marks(const uint32_t* strips,
+                                                     int64_t row,
+                                                     int rows_per_plane,
+                                                     int strips_per_row) {
+  return strips == nullptr
+             ? nullptr
+             : strips + (size_t)(row / rows_per_plane) * strips_per_row;
+}
+
+// MK: with `strips` (marks of the 64-column strips of each plane of
+// rows_per_plane rows), samples of unmarked strips are taken as zero and
+// not read: the one-call path leaves those strips unwritten.
+template <typename R, int LOGN, int NT, bool MK>
+__global__ __launch_bounds__(NT) void k_fft_rows(
+    cplx<R>* data, int64_t nrows, const cplx<R>* __restrict__ tw, R s,
+    const uint32_t* __restrict__ strips, int rows_per_plane,
+    int strips_per_row) {
   constexpr int N = 1 << LOGN;
   __shared__ cplx<R> lds[lds_line<N>(1)];
   __shared__ cplx<R> s_lo[kTwLo], s_hi[(N + kTwLo - 1) / kTwLo];
@@ -308,7 +344,13 @@ __global__ __launch_bounds__(NT) void k_fft_rows(cplx<R>* data, int64_t nrows,
   const Twiddles<R> twl = load_twiddles(s_lo, s_hi, tw, N);
   __syncthreads();
   cplx<R>* line = data + row * N;
-  auto ld = [&](int e, int, int, int) { return checker(line[e], e); };
+  static_assert(!MK || (NT % 64 == 0 && (N / 8) % 64 == 0),
+                "marks need one strip per wavefront");
+  const uint32_t* mk =
+      MK ? row_marks(strips, row, rows_per_plane, strips_per_row) : nullptr;
+  auto ld = [&](int e, int, int, int) {
+    return checker(row_sample<MK>(line, e, mk, tw), e);
+  };
   auto st = [&](int e, int, int, int, cplx<R> v) { line[e] = checker(v, e); };
   fft_line<R, LOGN, 1, NT>(lds, ld, st, twl, s);
 }
@@ -328,9 +370,11 @@ __device__ __forceinline__ cplx<R> twiddle_full(const cplx<R>* tw, int idx,
 // Both halves of the row are read once (coalesced); the difference terms
 // wait in registers while the sum terms are transformed, and the two
 // outputs of each k are written together.
-template <typename R, int LOGH, int NT>
+template <typename R, int LOGH, int NT, bool MK>
 __global__ __launch_bounds__(NT) void k_fft_rows_split(
-    cplx<R>* data, int64_t nrows, const cplx<R>* __restrict__ tw, R s) {
+    cplx<R>* data, int64_t nrows, const cplx<R>* __restrict__ tw, R s,
+    const uint32_t* __restrict__ strips, int rows_per_plane,
+    int strips_per_row) {
   constexpr int NH = 1 << LOGH;  // half length
   constexpr int N = 2 * NH;
   __shared__ cplx<R> lds[lds_line<NH>(1)];
@@ -344,9 +388,13 @@ __global__ __launch_bounds__(NT) void k_fft_rows_split(
   __syncthreads();
   cplx<R> diff[F0::IT][F0::RAD];
   cplx<R> even[FL::IT][FL::RAD];
+  static_assert(!MK || (NT % 64 == 0 && F0::NB % 64 == 0 && NH % 64 == 0),
+                "marks need one strip per wavefront");
+  const uint32_t* mk =
+      MK ? row_marks(strips, row, rows_per_plane, strips_per_row) : nullptr;
   auto ld_sum = [&](int e, int, int it, int r) {
-    const cplx<R> a = checker(line[e], e);
-    const cplx<R> b = checker(line[e + NH], e + NH);
+    const cplx<R> a = checker(row_sample<MK>(line, e, mk, tw), e);
+    const cplx<R> b = checker(row_sample<MK>(line, e + NH, mk, tw), e + NH);
     diff[it][r] = cmul(csub(a, b), twiddle_full(tw, e, s));
     return cadd(a, b);
   };
@@ -1077,20 +1125,40 @@ constexpr bool line_fits() {
 
 template <typename R, int LOGN>
 bool rows_t(cplx<R>* data, int64_t nrows, const cplx<R>* tw, R s,
-            cplx<R>* scratch, hipStream_t st) {
+            cplx<R>* scratch, const uint32_t* strips, int rows_per_plane,
+            int strips_per_row, hipStream_t st) {
   if constexpr (line_fits<R, LOGN>()) {
     constexpr int NT = row_threads(LOGN);
-    hipLaunchKernelGGL((k_fft_rows<R, LOGN, NT>), dim3((unsigned)nrows),
-                       dim3(NT), 0, st, data, nrows, tw, s);
-    return true;
+    if (strips == nullptr) {
+      hipLaunchKernelGGL((k_fft_rows<R, LOGN, NT, false>),
+                         dim3((unsigned)nrows), dim3(NT), 0, st, data, nrows,
+                         tw, s, strips, rows_per_plane, strips_per_row);
+      return true;
+    }
+    if constexpr (NT % 64 == 0 && ((1 << LOGN) / 8) % 64 == 0) {
+      hipLaunchKernelGGL((k_fft_rows<R, LOGN, NT, true>),
+                         dim3((unsigned)nrows), dim3(NT), 0, st, data, nrows,
+                         tw, s, strips, rows_per_plane, strips_per_row);
+      return true;
+    }
+    return false;
   } else if constexpr (line_fits<R, LOGN - 1>()) {
     constexpr int NT = row_threads(LOGN - 1);
-    hipLaunchKernelGGL((k_fft_rows_split<R, LOGN - 1, NT>),
-                       dim3((unsigned)nrows), dim3(NT), 0, st, data, nrows,
-                       tw, s);
-    return true;
+    if (strips == nullptr) {
+      hipLaunchKernelGGL((k_fft_rows_split<R, LOGN - 1, NT, false>),
+                         dim3((unsigned)nrows), dim3(NT), 0, st, data, nrows,
+                         tw, s, strips, rows_per_plane, strips_per_row);
+      return true;
+    }
+    if constexpr (NT % 64 == 0 && ((1 << (LOGN - 1)) / 8) % 64 == 0) {
+      hipLaunchKernelGGL((k_fft_rows_split<R, LOGN - 1, NT, true>),
+                         dim3((unsigned)nrows), dim3(NT), 0, st, data, nrows,
+                         tw, s, strips, rows_per_plane, strips_per_row);
+      return true;
+    }
+    return false;
   } else if constexpr (line_fits<R, LOGN - 2>()) {
-    if (scratch == nullptr) return false;
+    if (scratch == nullptr || strips != nullptr) return false;
     constexpr int NT = row_threads(LOGN - 2);
     const int64_t g = nrows < kSplitRowGroups ? nrows : kSplitRowGroups;
     hipLaunchKernelGGL((k_fft_rows_splitF<R, LOGN - 2, NT, 4>),
@@ -1281,14 +1349,24 @@ size_t fft_row_scratch_bytes(int n, int elem_bytes) {
              ? (size_t)kSplitRowGroups * n * elem_bytes : 0;
 }
 
+// The row kernels for n read by strip marks when one wavefront's 64
+// first-stage samples lie in one strip: the one-pass and two-half forms
+// at n >= 1024, not the 4-way split.
+bool fft_rows_can_mask(int n, int elem_bytes) {
+  return n >= 1024 && fft_supported(n, elem_bytes) &&
+         !fft_row_needs_scratch(n, elem_bytes);
+}
+
 template <typename R>
 bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw, int sign,
-                     void* scratch, hipStream_t st) {
+                     void* scratch, const uint32_t* strips, int rows_per_plane,
+                     hipStream_t st) {
   const int lg = ilog2(n);
   bool ok = false;
   WS_LOGN_SWITCH(lg, (ok = rows_t<R, LG>((cplx<R>*)data, nrows,
                                          (const cplx<R>*)tw, (R)sign,
-                                         (cplx<R>*)scratch, st)));
+                                         (cplx<R>*)scratch, strips,
+                                         rows_per_plane, n / 64, st)));
   return ok;
 }
 
@@ -1397,7 +1475,7 @@ void launch_twiddles(void* tw, int n, hipStream_t st) {
 
 #define WS_INST(R)                                                            \
   template bool launch_fft_rows<R>(void*, int, int64_t, const void*, int,    \
-                                   void*,                                  \
+                                   void*, const uint32_t*, int,            \
                                    hipStream_t);                             \
   template bool launch_fft_cols<R>(void*, int, int, int, const void*, int,   \
                                    const uint32_t*, int, const uint32_t*,    \

@@ -177,9 +177,13 @@ template <typename R>
 void launch_grid_batch(const GridJob<R>* jobs, int njobs, int K, int kern,
                        size_t lds, uint32_t* queue, uint32_t max_items,
                        int cus, hipStream_t st);
+// Zeros of the tiles without records; with `strips`, only of those in
+// marked column strips (the one-call path beyond 4096 never reads the
+// others).
 template <typename R>
 void launch_zero_idle(const Geo& g, const uint32_t* counters,
-                      const uint32_t* idle, void* planes, hipStream_t st);
+                      const uint32_t* idle, void* planes,
+                      const uint32_t* strips, hipStream_t st);
 template <typename R>
 void launch_zero_idle_batch(const GridJob<R>* jobs, int njobs,
                             uint64_t total_tiles, hipStream_t st);
@@ -205,9 +209,15 @@ bool fft_supported(int n, int elem_bytes);
 // Rows too long for two half-length LDS transforms take a 4-way split
 // that writes through a scratch area of this many bytes (0 otherwise).
 size_t fft_row_scratch_bytes(int n, int elem_bytes);
+// Row transforms of nrows rows of n points.  With `strips` (marks of the
+// 64-column strips of each plane of rows_per_plane rows), samples of
+// unmarked strips are taken as zero and not read; false where the row
+// kernel for n cannot (fft_rows_can_mask).
 template <typename R>
 bool launch_fft_rows(void* data, int n, int64_t nrows, const void* tw,
-                     int sign, void* scratch, hipStream_t st);
+                     int sign, void* scratch, const uint32_t* strips,
+                     int rows_per_plane, hipStream_t st);
+bool fft_rows_can_mask(int n, int elem_bytes);
 // Column transforms; with `strips` non-null, the blocks of column strips
 // (strip_w columns of one plane) whose mark is zero are skipped; with
 // `tiles` non-null (per-tile record counts, tile edge strip_w), rows of
