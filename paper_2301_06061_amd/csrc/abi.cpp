@@ -78,7 +78,7 @@ struct Layout {
       o_slot, o_counters, o_split, o_extra, o_busy, o_idle, o_copies, o_desc,
       o_strips, o_partials, o_scratch, o_rowscratch, o_clean, o_p_hist1, o_p_hist1x,
       o_p_btot, o_p_bounds, o_p_seg, o_p_rec1, o_p_keys, o_p_chunk0, o_p_rank2,
-      o_p_hist2, o_p_hist2x, o_tstore, o_tslot, total;
+      o_p_hist2, o_p_hist2x, o_tstore, o_tslot, o_zero, total;
 };
 
 ws_status check_params(const ws_params* p) {
@@ -293,6 +293,9 @@ ws_status make_layout(const ws_params* p, int64_t max_vis, Layout* L) {
                 : 0;
   L->o_tstore = take((size_t)L->tstore_slots * L->T * L->T * L->elem);
   L->o_tslot = take(L->tstore ? (size_t)L->ntiles * 4 : (size_t)0);
+  // 256 bytes of zeros: where the column transform's loads of rows
+  // without records go.
+  L->o_zero = take(256);
   L->total = o;
   return WS_OK;
 }
@@ -573,15 +576,12 @@ ws_status merge_impl(ws_plan* pl, int acc, bool ts = false) {
   });
 }
 
-// With `lazy` (a first call whose stack only the fused imaging path will
-// read), tiles without records are not zeroed; with `ts` as well, tiles
-// with records go to the busy-tile store instead of the stack.  With
-// `marked` (a first call of the one-call path beyond 4096), only the tiles
-// without records in marked column strips are zeroed.
+// With `lazy` (a first call whose stack only the one-call imaging path
+// will read), tiles without records are not zeroed; with `ts` as well,
+// tiles with records go to the busy-tile store instead of the stack.
 template <typename R>
 ws_status grid_impl(ws_plan* pl, int64_t m, const VisSource& src,
-                    int64_t* n_dropped, bool lazy = false, bool ts = false,
-                    bool marked = false) {
+                    int64_t* n_dropped, bool lazy = false, bool ts = false) {
   uint32_t max_items = 0;
   const int acc = pl->state == kGridded ? 1 : 0;
   ts = ts && lazy && !acc;
@@ -592,9 +592,7 @@ ws_status grid_impl(ws_plan* pl, int64_t m, const VisSource& src,
   if (!acc && !lazy) {
     // First call since the reset: tiles without records get their zeros.
     WS_TRY(launch(pl, "zero_idle", [&] {
-      launch_zero_idle<R>(pl->g, j.counters, j.idle, pl->planes,
-                          marked ? pl->w<uint32_t>(pl->L.o_strips) : nullptr,
-                          pl->stream);
+      launch_zero_idle<R>(pl->g, j.counters, j.idle, pl->planes, pl->stream);
     }));
   }
   WS_TRY(launch(pl, "grid_tiles", [&] {
@@ -630,7 +628,7 @@ ws_status cols_impl(ws_plan* pl, int sign, Geo* gout,
     WS_TRY(launch(pl, "fft_cols4", [&] {
       ok = launch_fft_cols4<R>(pl->planes, p.nv, p.nu, p.nw,
                                pl->work + pl->L.o_tw_v, sign, strips, g.T,
-                               pl->stream);
+                               tiles, pl->work + pl->L.o_zero, pl->stream);
     }));
     int lg = 0;
     while ((1 << lg) < p.nv) ++lg;
@@ -684,15 +682,17 @@ ws_status fft_impl(ws_plan* pl, int sign) {
 // With `lazy`, tiles without records were never written (their cells are
 // taken as zero from the per-tile record counts); with `ts` as well, the
 // tiles with records are in the busy-tile store.
-// With `marked`, unmarked column strips were never written (the one-call
-// path beyond 4096): the row transform takes them as zero.
+// With `marked` (the one-call path beyond 4096), tiles without records
+// were never written either: the column transform reads by tile record
+// counts and the row transform takes unmarked strips as zero.
 template <typename R>
 ws_status image_impl(ws_plan* pl, void* image, bool lazy = false,
                      bool ts = false, bool marked = false) {
   const ws_params& p = pl->p;
   Geo g;
   WS_TRY(cols_impl<R>(pl, +1, &g, pl->w<uint32_t>(pl->L.o_strips),
-                      lazy ? pl->w<uint32_t>(pl->L.o_chunks) : nullptr,
+                      lazy || marked ? pl->w<uint32_t>(pl->L.o_chunks)
+                                     : nullptr,
                       lazy && ts));
   if (p.nu <= kFusedRows) {
     bool ok = true;
@@ -768,10 +768,11 @@ bool lazy_ok(const ws_plan* pl) {
 // tiles with records in the busy-tile store (where the layout has one).
 bool tstore_ok(const ws_plan* pl) { return lazy_ok(pl) && pl->L.tstore; }
 
-// Beyond 4096 the one-call path zeroes only the tiles without records in
-// marked column strips: the column transform skips the unmarked strips,
-// and the row transform (fused below 4096 columns, else by strip marks)
-// takes them as zero.
+// Beyond 4096 the one-call path leaves the tiles without records
+// unwritten too: the column transform (one-pass or the first four-step
+// step) reads by tile record counts and skips unmarked strips, and the
+// row transform (fused below 4096 columns, else by strip marks) takes the
+// unmarked strips as zero.
 bool marked_ok(const ws_plan* pl) {
   const ws_params& p = pl->p;
   return !lazy_ok(pl) && pl->g.T == 64 && p.nu >= 1024 &&
@@ -797,8 +798,8 @@ ws_status grid_image_impl(ws_plan* pl, int64_t m, const VisSource& src,
   const bool ts = tstore_ok(pl) && pl->state == kEmpty;
   const bool marked = marked_ok(pl) && pl->state == kEmpty;
   ws_status st =
-      f64 ? grid_impl<double>(pl, m, src, n_dropped, lazy, false, marked)
-          : grid_impl<float>(pl, m, src, n_dropped, lazy, ts, marked);
+      f64 ? grid_impl<double>(pl, m, src, n_dropped, lazy || marked, false)
+          : grid_impl<float>(pl, m, src, n_dropped, lazy || marked, ts);
   if (st == WS_OK)
     st = f64 ? image_impl<double>(pl, image, lazy, false, marked)
              : image_impl<float>(pl, image, lazy, ts, marked);
@@ -980,6 +981,9 @@ ws_status init_plan(ws_plan* pl, const ws_params* params, int64_t max_vis,
       pl->cus = n;
   }
   pl->profile = false;
+  WS_TRY(launch(pl, "zero_line", [&] {
+    launch_zero_u32(pl->w<uint32_t>(L.o_zero), 64, pl->stream);
+  }));
   if (params->correct) {
     double* corr = pl->w<double>(L.o_corr);
     pl->g.corr = corr;

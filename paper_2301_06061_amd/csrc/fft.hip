@@ -731,13 +731,19 @@ __global__ __launch_bounds__(NT) void k_fft_cols_split(
 // 256-byte) row segments; the result has its rows in the transposed order
 // that stack_row() undoes.
 
-template <typename R, int LOG1, int LOG2, int BC, int NT>
+// TM: rows of tiles without records (tile counts `tiles`, tile edge
+// strip_w = 64) are not read: their loads go to `zeros`, a line of zeros
+// (the one-call path leaves those tiles unwritten).  Choosing the address,
+// not the loaded value, keeps the loads free of branches.
+template <typename R, int LOG1, int LOG2, int BC, int NT, bool TM>
 __global__ __launch_bounds__(NT) void k_fft_colA(
     cplx<R>* data, int ncols, int nplanes, const cplx<R>* __restrict__ tw, R s,
-    const uint32_t* __restrict__ strips, int strip_w) {
+    const uint32_t* __restrict__ strips, int strip_w,
+    const uint32_t* __restrict__ tiles, const cplx<R>* __restrict__ zeros) {
   constexpr int N1 = 1 << LOG1, N2 = 1 << LOG2, N = N1 * N2;
   __shared__ cplx<R> lds[lds_line<N1>(BC)];
   __shared__ cplx<R> s_lo[kTwLo], s_hi[(N1 + kTwLo - 1) / kTwLo];
+  __shared__ uint32_t s_tm[TM ? N / 64 : 1];
   const int ncb = ncols / BC;
   const int nb = ncb * N2 * nplanes;
   const int L = xcd_block<R, BC>((int)blockIdx.x, nb);
@@ -750,11 +756,22 @@ __global__ __launch_bounds__(NT) void k_fft_colA(
       strips[plane * (ncols / strip_w) + cb * BC / strip_w] == 0u)
     return;
   cplx<R>* base = data + (size_t)plane * N * ncols + (size_t)cb * BC;
+  if constexpr (TM) {
+    // Record counts of the strip's tiles, one per 64 rows.
+    const int tcols = ncols / 64, strip = cb * BC / 64;
+    for (int i = (int)threadIdx.x; i < N / 64; i += NT)
+      s_tm[i] = tiles[((size_t)plane * (N / 64) + i) * tcols + strip];
+  }
   const Twiddles<R> twl = load_twiddles_sub(s_lo, s_hi, tw, N1, N);
   __syncthreads();
   auto ld = [&](int e, int c, int, int) {
     const int row = e * N2 + n2;
-    return checker(base[(size_t)row * ncols + c], row);
+    if constexpr (TM) {
+      const bool h = s_tm[row >> 6] != 0u;
+      return checker(*(h ? base + (size_t)row * ncols + c : zeros), row);
+    } else {
+      return checker(base[(size_t)row * ncols + c], row);
+    }
   };
   auto st = [&](int e, int c, int, int, cplx<R> v) {
     const int row = e * N2 + n2;
@@ -1248,8 +1265,9 @@ bool cols_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
 }
 
 template <typename R, int LOG1, int LOG2, int BC>
-void cols4_bc(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
-              const uint32_t* strips, int strip_w, hipStream_t st) {
+bool cols4_bc(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
+              const uint32_t* strips, int strip_w, const uint32_t* tiles,
+              const cplx<R>* zeros, hipStream_t st) {
   constexpr int NTA = ((1 << LOG1) * BC) / 8;
   constexpr int NTB = ((1 << LOG2) * BC) / 8;
   static_assert(NTA <= 1024 && NTB <= 1024, "step too long for one block");
@@ -1257,17 +1275,29 @@ void cols4_bc(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
   const int nba = ncb * (1 << LOG2) * nplanes;
   const int nbb = ncb * (1 << LOG1) * nplanes;
   if (strips != nullptr && strip_w % BC != 0) strips = nullptr;
-  hipLaunchKernelGGL((k_fft_colA<R, LOG1, LOG2, BC, NTA>),
-                     dim3(((nba + 7) / 8) * 8), dim3(NTA), 0, st, data, ncols,
-                     nplanes, tw, s, strips, strip_w);
+  if (tiles != nullptr) {
+    // Tile counts need strips of 64 columns holding whole blocks.
+    if (strips == nullptr || strip_w != 64 || 64 % BC != 0 ||
+        zeros == nullptr)
+      return false;
+    hipLaunchKernelGGL((k_fft_colA<R, LOG1, LOG2, BC, NTA, true>),
+                       dim3(((nba + 7) / 8) * 8), dim3(NTA), 0, st, data,
+                       ncols, nplanes, tw, s, strips, strip_w, tiles, zeros);
+  } else {
+    hipLaunchKernelGGL((k_fft_colA<R, LOG1, LOG2, BC, NTA, false>),
+                       dim3(((nba + 7) / 8) * 8), dim3(NTA), 0, st, data,
+                       ncols, nplanes, tw, s, strips, strip_w, tiles, zeros);
+  }
   hipLaunchKernelGGL((k_fft_colB<R, LOG1, LOG2, BC, NTB>),
                      dim3(((nbb + 7) / 8) * 8), dim3(NTB), 0, st, data, ncols,
                      nplanes, tw, s, strips, strip_w);
+  return true;
 }
 
 template <typename R, int LOGN>
 bool cols4_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
-             const uint32_t* strips, int strip_w, hipStream_t st) {
+             const uint32_t* strips, int strip_w, const uint32_t* tiles,
+             const cplx<R>* zeros, hipStream_t st) {
   if constexpr (LOGN < 6) {
     return false;
   } else {
@@ -1279,12 +1309,10 @@ bool cols4_t(cplx<R>* data, int ncols, int nplanes, const cplx<R>* tw, R s,
     constexpr int NMAX = (1 << LOG2) > (1 << LOG1) ? (1 << LOG2) : (1 << LOG1);
     constexpr int BC = (NMAX * BCW) / 8 > 1024 ? (8 * 1024) / NMAX : BCW;
     if (ncols >= BC && ncols % BC == 0)
-      cols4_bc<R, LOG1, LOG2, BC>(data, ncols, nplanes, tw, s, strips,
-                                  strip_w, st);
-    else
-      cols4_bc<R, LOG1, LOG2, 16>(data, ncols, nplanes, tw, s, strips,
-                                  strip_w, st);
-    return true;
+      return cols4_bc<R, LOG1, LOG2, BC>(data, ncols, nplanes, tw, s, strips,
+                                         strip_w, tiles, zeros, st);
+    return cols4_bc<R, LOG1, LOG2, 16>(data, ncols, nplanes, tw, s, strips,
+                                       strip_w, tiles, zeros, st);
   }
 }
 
@@ -1412,12 +1440,14 @@ bool launch_screen_row_bcast(const void* img, int img_real, void* planes,
 template <typename R>
 bool launch_fft_cols4(void* data, int nrows, int ncols, int nplanes,
                       const void* tw, int sign, const uint32_t* strips,
-                      int strip_w, hipStream_t st) {
+                      int strip_w, const uint32_t* tiles, const void* zeros,
+                      hipStream_t st) {
   const int lg = ilog2(nrows);
   bool ok = false;
   WS_LOGN_SWITCH(lg, (ok = cols4_t<R, LG>((cplx<R>*)data, ncols, nplanes,
                                           (const cplx<R>*)tw, (R)sign, strips,
-                                          strip_w, st)));
+                                          strip_w, tiles,
+                                          (const cplx<R>*)zeros, st)));
   return ok;
 }
 
@@ -1490,7 +1520,8 @@ void launch_twiddles(void* tw, int n, hipStream_t st) {
   template void launch_wcorrect<R>(const void*, void*, const Geo&,           \
                                    hipStream_t);                             \
   template bool launch_fft_cols4<R>(void*, int, int, int, const void*, int,  \
-                                    const uint32_t*, int, hipStream_t);      \
+                                    const uint32_t*, int, const uint32_t*,   \
+                                    const void*, hipStream_t);               \
   template void launch_unpermute_rows<R>(const void*, void*, const Geo&,     \
                                          hipStream_t);                       \
   template void launch_screen_bcast<R>(const void*, int, void*, const Geo&,  \

@@ -626,17 +626,8 @@ __device__ __forceinline__ void zero_idle_tile(const Geo& g,
 template <typename R>
 __global__ __launch_bounds__(256) void k_zero_idle(
     Geo g, const uint32_t* __restrict__ counters,
-    const uint32_t* __restrict__ idle, cplx<R>* __restrict__ planes,
-    const uint32_t* __restrict__ strips) {
+    const uint32_t* __restrict__ idle, cplx<R>* __restrict__ planes) {
   if (blockIdx.x >= counters[5]) return;
-  if (strips != nullptr) {
-    // Column strip of the tile: plane k, tile column tx.
-    const int t = (int)idle[blockIdx.x];
-    const int per_plane = g.tiles_u * g.tiles_v;
-    const int k = t / per_plane;
-    const int tx = (t - k * per_plane) % g.tiles_u;
-    if (strips[k * g.tiles_u + tx] == 0u) return;
-  }
   zero_idle_tile(g, idle, blockIdx.x, planes);
 }
 
@@ -924,11 +915,10 @@ void launch_item_desc(const Geo& g, const uint32_t* offsets,
 
 template <typename R>
 void launch_zero_idle(const Geo& g, const uint32_t* counters,
-                      const uint32_t* idle, void* planes,
-                      const uint32_t* strips, hipStream_t st) {
+                      const uint32_t* idle, void* planes, hipStream_t st) {
   if (g.ntiles <= 0) return;
   hipLaunchKernelGGL(k_zero_idle<R>, dim3((unsigned)g.ntiles), dim3(256), 0,
-                     st, g, counters, idle, (cplx<R>*)planes, strips);
+                     st, g, counters, idle, (cplx<R>*)planes);
 }
 
 template <typename R>
@@ -982,8 +972,7 @@ size_t degrid_lds_bytes(int T, int K, int elem_bytes) {
                                      size_t, uint32_t*, uint32_t, int,     \
                                      hipStream_t);                         \
   template void launch_zero_idle<R>(const Geo&, const uint32_t*,           \
-                                    const uint32_t*, void*,                \
-                                    const uint32_t*, hipStream_t);         \
+                                    const uint32_t*, void*, hipStream_t);  \
   template void launch_zero_idle_batch<R>(const GridJob<R>*, int, uint64_t, \
                                           hipStream_t);                    \
   template void launch_grid_merge<R>(const Geo&, const uint32_t*,          \

@@ -177,13 +177,9 @@ template <typename R>
 void launch_grid_batch(const GridJob<R>* jobs, int njobs, int K, int kern,
                        size_t lds, uint32_t* queue, uint32_t max_items,
                        int cus, hipStream_t st);
-// Zeros of the tiles without records; with `strips`, only of those in
-// marked column strips (the one-call path beyond 4096 never reads the
-// others).
 template <typename R>
 void launch_zero_idle(const Geo& g, const uint32_t* counters,
-                      const uint32_t* idle, void* planes,
-                      const uint32_t* strips, hipStream_t st);
+                      const uint32_t* idle, void* planes, hipStream_t st);
 template <typename R>
 void launch_zero_idle_batch(const GridJob<R>* jobs, int njobs,
                             uint64_t total_tiles, hipStream_t st);
@@ -237,10 +233,15 @@ bool launch_row_screen_sum(const void* planes, void* img, const Geo& g,
 template <typename R>
 bool launch_screen_row_bcast(const void* img, int img_real, void* planes,
                              const Geo& g, const void* tw_u, hipStream_t st);
+// Four-step column transform (columns longer than 4096); with `tiles`
+// (per-tile record counts, tile edge strip_w = 64, strips given), rows of
+// tiles without records are taken as zero and not read (their loads go to
+// `zeros`, 16 bytes of zeros in device memory).
 template <typename R>
 bool launch_fft_cols4(void* data, int nrows, int ncols, int nplanes,
                       const void* tw, int sign, const uint32_t* strips,
-                      int strip_w, hipStream_t st);
+                      int strip_w, const uint32_t* tiles, const void* zeros,
+                      hipStream_t st);
 template <typename R>
 void launch_unpermute_rows(const void* src, void* dst, const Geo& g,
                            hipStream_t st);
