@@ -311,16 +311,19 @@ def test_grid_image_reuses_a_dirty_stack(precision):
     ("fp64", (8192, 512, 2)), ("fp32", (8192, 512, 2)),
     ("fp64", (512, 8192, 2)), ("fp32", (512, 8192, 2)),
     ("fp32", (8192, 8192, 2)), ("fp64", (16384, 512, 2)),
-    ("fp32", (32768, 512, 2))])
+    ("fp32", (32768, 512, 2)), ("fp32", (1024, 8192, 2)),
+    ("fp64", (2048, 8192, 2))])
 def test_grid_image_beyond_4096_reuses_a_dirty_stack(precision, shape):
     """The one-call path beyond 4096 (rows wider than 4096 through the
     plain row transform and w-correction, columns longer than 4096 through
-    the four-step transform) zeroes the tiles without records of the
-    column strips that hold records; the row transform reads the other
-    strips as zero (one-pass rows, and the two-half rows of FP64 at 16384
-    and FP32 at 32768).  Three calls on one plan (the second with far
-    fewer visibilities, so most of its idle tiles still hold the first
-    call's sums), each image against the oracle."""
+    the four-step transform) leaves the tiles without records unwritten
+    from 1024 columns on: the column transform reads by tile record counts
+    and the row transform (fused up to 4096 columns, else one-pass rows,
+    or the two-half rows of FP64 at 16384 and FP32 at 32768) reads
+    unmarked strips as zero; at 512 columns the idle tiles are zeroed.
+    Three calls on one plan (the second with far fewer visibilities, so
+    most of its idle tiles still hold the first call's sums), each image
+    against the oracle."""
     nu, nv, nw = shape
     fp = 1 if precision == "fp64" else 0
     wl1 = synth.random_case(61, n=nu, nv=nv, nw=nw, support=7, m=20000,
